@@ -1,0 +1,179 @@
+/*
+ * libcola -- COLA particle-mesh N-body step and 2LPT initial conditions on AMD MI355X (gfx950).
+ *
+ * Method: Izard, Crocce & Fosalba, "ICE-COLA: Towards fast and accurate synthetic galaxy
+ * catalogues optimizing a quasi N-body method" (arXiv:1509.04685).
+ *
+ *   Sec. 1, Eq. 1-2  the displacement splits into the 2LPT trajectory and a residual; only the
+ *                    residual's time derivative is discretised, the 2LPT acceleration is analytic.
+ *   Sec. 2.2         2LPT Gaussian initial conditions; a particle-mesh force on a mesh PM_grid
+ *                    times finer per side than the particle grid; four FFTs per force (one forward
+ *                    of the density, three inverse, one per force component).
+ *   Sec. 4.2, Eq. 3  n time nodes spaced uniformly in f(a), Delta f = (f(1) - f(a_i)) / (n - 1);
+ *                    the optimum is f(a) = a (linear), 40 nodes, z_i = 19, PM_grid = 3 (Sec. 4.5).
+ *   Sec. 2.5         matter power spectrum: CIC onto a grid, FFT, band average of |delta_k|^2,
+ *                    CIC window divided out.
+ *
+ * Conventions (every entry point):
+ *   - Units: lengths in h^-1 Mpc, wavenumbers in h/Mpc, time through the scale factor a, H0 = 1;
+ *     momenta p = a^2 dx/dt in units of H0 h^-1 Mpc.
+ *   - Arrays are C order [x][y][z], z fastest.  Particle arrays are structure-of-arrays in
+ *     Lagrangian index order, idx = (i * N_p + j) * N_p + l.
+ *   - A batch holds n_real realizations of one problem; every particle array then holds
+ *     n_real * N_p^3 floats, realization r at offset r * N_p^3.
+ *   - Every pointer in cola_particles, the P(k) outputs and the workspace is DEVICE memory
+ *     owned by the caller; the library never allocates, frees or keeps it.  Problem and
+ *     cosmology structs and seed arrays are HOST memory, read during the call only.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL = default stream).
+ *     Arguments are validated on the host before any launch, so error returns never leave
+ *     work queued.  Returns COLA_OK (0) or a negative cola_status; cola_status_string gives
+ *     the message.  After COLA_ERR_HIP the stream's contents are undefined.
+ *   - The workspace is carved by the library; cola_workspace_bytes gives its size.  Between
+ *     calls it caches the force mesh of the current node (see cola_particles.force_node).
+ *   - Calls that overlap on one workspace race; use one workspace per stream.
+ */
+#ifndef COLA_H
+#define COLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COLA_OK = 0,
+    COLA_ERR_INVALID_ARG = -1,        /* NULL pointer, out-of-range parameter             */
+    COLA_ERR_UNSUPPORTED_SIZE = -2,   /* a mesh size that is odd or has a prime factor > 3 */
+    COLA_ERR_WORKSPACE_TOO_SMALL = -3,
+    COLA_ERR_HIP = -4,                /* a HIP runtime call failed                         */
+    COLA_ERR_STATE = -5,              /* particle state does not fit the call (node range)  */
+    COLA_ERR_NONFINITE = -6           /* a non-finite value was found where checked         */
+} cola_status;
+
+/* Flat LCDM, Omega_L = 1 - Omega_m, no radiation (Sec. 2.1: Omega_m 0.25, Omega_b 0.044,
+ * h 0.7, n_s 0.95, sigma_8 0.8).  The linear spectrum is the BBKS fit with the Sugiyama
+ * shape parameter, normalised to sigma_8 in 8 h^-1 Mpc top-hat spheres at a = 1 (the paper
+ * used CAMB, Sec. 2.1). */
+typedef struct {
+    double omega_m, omega_b, h, n_s, sigma_8;
+} cola_cosmology;
+
+/* One simulation as Table 1 parameterises it. */
+typedef struct {
+    double  box;        /* L, side of the periodic box [h^-1 Mpc]                             */
+    int32_t n_part;     /* N_p particles per side (N_p^3 particles), >= 2                     */
+    int32_t pm_factor;  /* PM_grid: the force mesh has N_g = pm_factor * N_p cells per side   */
+    double  z_init;     /* a_0 = 1 / (1 + z_init)                                             */
+    double  a_final;    /* last node, normally 1                                              */
+    int32_t n_steps;    /* number of time nodes n of Eq. 3, both ends included (n >= 2);
+                           one force evaluation per node, n - 1 drifts                        */
+    int32_t sampling;   /* time sampling f(a) of Eq. 3: 0 = linear in a (only value accepted) */
+    int32_t n_real;     /* realizations in the batch, >= 1                                    */
+} cola_problem;
+
+/* Particle state of a batch.  Each pointer: n_real * N_p^3 floats on the device.
+ *   x     displacement from the Lagrangian position q (not the absolute position), where
+ *         q = idx_d * L / N_p + H / 2 per axis, H = L / N_g: the lattice sits at force-mesh
+ *         cell centres (on a node the CIC weights have a kink).
+ *   p     residual momentum p_res = p - a^2 (dD1/dt Psi1 + dD2/dt Psi2) (Eq. 1-2 frame).
+ *   psi1  first-order Lagrangian displacement at D1 = 1; psi2 second order (D2 < 0 convention).
+ * node        index of the time node the state sits at (0 after cola_ic_2lpt).
+ * force_node  node whose force mesh the workspace `force_ws` holds, or -1.  Set by the
+ *             library; set it to -1 yourself after changing x or switching workspaces.
+ * force_ws    workspace that holds that force mesh. */
+typedef struct {
+    float* x[3];
+    float* p[3];
+    float* psi1[3];
+    float* psi2[3];
+    int32_t node;
+    int32_t force_node;
+    const void* force_ws;
+} cola_particles;
+
+/* Bytes of device workspace needed by every call on `prob` with a P(k) mesh of n_pk per side
+ * (n_pk = 0: no P(k) buffers).  Returns 0 for invalid arguments. */
+size_t cola_workspace_bytes(const cola_problem* prob, int32_t n_pk);
+
+/* 2LPT Gaussian initial conditions (Sec. 2.2; Crocce, Pueblas & Scoccimarro 2006).
+ * White noise per Lagrangian cell from Philox4x64-10 keyed by the realization's seed
+ * (Sec. 2.3: one seed, one field) with the cell index as counter; delta_k = FFT[w] *
+ * sqrt(P(k) N_p^3 / L^3), k = 0 removed; Psi1 = IFFT[i k delta / k^2]; Psi2 =
+ * IFFT[-i k S_k / k^2] with S = sum_{i>j}(phi_ii phi_jj - phi_ij^2), phi_ij = IFFT[k_i k_j delta/k^2];
+ * a factor odd in k_d is zeroed on the Nyquist plane of axis d.  On return x = D1(a_0) Psi1 +
+ * D2(a_0) Psi2, p = 0, node = 0, force_node = -1.
+ * seeds: host array of n_real seeds.  ws: cola_workspace_bytes(prob, 0) bytes at least. */
+int cola_ic_2lpt(const cola_problem* prob, const cola_cosmology* cosmo, const uint64_t* seeds,
+                 cola_particles* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Particle-mesh acceleration at the current positions (Sec. 2.2): CIC onto the N_g^3 mesh,
+ * delta = rho / rho_bar - 1, forward FFT, g_k = i k delta_k / k^2 (k = 0 and each component's
+ * own Nyquist plane set to 0), three inverse FFTs, CIC interpolation.  acc[d]: device arrays of
+ * n_real * N_p^3 floats receiving g_d (the physical acceleration is (3/2) Omega_m g / a).
+ * Leaves the force mesh in `ws` but does not change `in`. */
+int cola_pm_force(const cola_problem* prob, const cola_particles* in, float* acc[3],
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* COLA steps from node j_begin (= io->node) to node j_end (Eq. 1-2, Eq. 3 nodes, kick-drift-kick
+ * in the 2LPT frame):
+ *   kick  p += (3/2) Omega_m K [g - D1 Psi1 - (D2 - D1^2) Psi2],  K = int da / (a^2 E)
+ *   drift x += p Dr + dD1 Psi1 + dD2 Psi2,                         Dr = int da / (a^3 E)
+ * Half-nodes are arithmetic mid-points in a.  On return p is synchronised at node j_end,
+ * io->node = j_end and the force of node j_end sits in ws (io->force_node = j_end), so the next
+ * call does not evaluate it again: a run costs exactly n force evaluations. */
+int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin,
+              int32_t j_end, cola_particles* io, void* ws, size_t ws_bytes, void* stream);
+
+/* Matter power spectrum at a_out (Sec. 2.5).  Needs a_j <= a_out < a_{j+1} for j = io->node
+ * (or a_out = a_j); between nodes the positions are drifted on a copy with the half-step
+ * momentum (the main run is unchanged).  CIC onto n_pk^3 cells, FFT, |delta_k|^2 / W^2 with
+ * W = prod_d sinc^2(pi m_d / n_pk); bin b >= 1 holds b^2 <= |m|^2 < (b+1)^2 (integer test,
+ * k = 0 excluded); P_b = (L^3 / n_pk^6) sum w |delta|^2 / W^2 / sum w, w the full-k-space
+ * multiplicity of each half-spectrum mode; sums in float64.  No shot-noise or aliasing
+ * correction.  Outputs (device, n_real * n_bins each, bin 0 empty): k_mean [h/Mpc], pk
+ * [(h^-1 Mpc)^3], n_modes.  n_pk: even, factors 2 and 3 only.  ws: cola_workspace_bytes(prob,
+ * n_pk) bytes at least.  May evaluate and cache the node's force if it is not cached. */
+int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo,
+                        cola_particles* in, double a_out, int32_t n_pk, int32_t n_bins,
+                        double* k_mean, double* pk, double* n_modes,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* ---- component entry points (the stages above, exposed for parity checks) ------------- */
+
+/* CIC density contrast of arbitrary positions: pos[d] device arrays of n floats (absolute
+ * positions in [0, box) or any real, wrapped periodically); delta: device n_mesh^3 floats.
+ * rho_bar = n / n_mesh^3. */
+int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box, float* delta,
+                     void* ws, size_t ws_bytes, void* stream);
+size_t cola_cic_workspace_bytes(int64_t n, int32_t n_mesh);
+
+/* 3D real-to-complex FFT, unnormalised forward (sign -1): in n^3 floats, out n*n*(n/2+1)
+ * complex (float2, re/im interleaved), numpy rfftn layout.  3D complex-to-real inverse
+ * (unnormalised, sign +1): the reverse.  n even with factors 2 and 3 only. */
+size_t cola_fft_workspace_bytes(int32_t n);
+int cola_fft_r2c(int32_t n, const float* in, float* out, void* ws, size_t ws_bytes, void* stream);
+int cola_fft_c2r(int32_t n, const float* in, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- host-only helpers (no device work; usable without a GPU) --------------------------- */
+
+/* The float64 schedule the step uses: for each node j, 6 doubles
+ *   a_j, D1(a_j), D2(a_j), K(a_j, a_{j+1/2}), K(a_{j+1/2}, a_{j+1}), Dr(a_j, a_{j+1})
+ * (the last three are 0 on the last node).  out: host array of 6 * n_steps doubles. */
+int cola_schedule_table(const cola_problem* prob, const cola_cosmology* cosmo, double* out);
+
+/* Linear power spectrum at a = 1 [(h^-1 Mpc)^3] at wavenumber k [h/Mpc]; -1 on bad input. */
+double cola_linear_power(const cola_cosmology* cosmo, double k);
+
+/* Message for a cola_status value (static storage). */
+const char* cola_status_string(int status);
+
+/* Library version string (static storage). */
+const char* cola_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COLA_H */

@@ -1,0 +1,92 @@
+"""ctypes binding of libcola (include/cola.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module only converts torch tensors to device
+pointers, passes torch's current HIP stream, and raises on a non-zero status.  If libcola.so is
+missing the import fails loudly -- there is no fallback path.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcola.so")
+
+COLA_OK = 0
+STATUS_NAMES = {0: "COLA_OK", -1: "COLA_ERR_INVALID_ARG", -2: "COLA_ERR_UNSUPPORTED_SIZE",
+                -3: "COLA_ERR_WORKSPACE_TOO_SMALL", -4: "COLA_ERR_HIP", -5: "COLA_ERR_STATE",
+                -6: "COLA_ERR_NONFINITE"}
+
+# every exported symbol of include/cola.h
+EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
+           "cola_power_spectrum", "cola_cic_density", "cola_cic_workspace_bytes",
+           "cola_fft_workspace_bytes", "cola_fft_r2c", "cola_fft_c2r", "cola_schedule_table",
+           "cola_linear_power", "cola_status_string", "cola_version")
+
+
+class ColaError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.cola_status_string(status).decode() if _lib is not None else "?"
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({msg})")
+
+
+class Cosmology(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("omega_b", ctypes.c_double), ("h", ctypes.c_double),
+                ("n_s", ctypes.c_double), ("sigma_8", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("n_part", ctypes.c_int32), ("pm_factor", ctypes.c_int32),
+                ("z_init", ctypes.c_double), ("a_final", ctypes.c_double),
+                ("n_steps", ctypes.c_int32), ("sampling", ctypes.c_int32),
+                ("n_real", ctypes.c_int32)]
+
+
+_F3 = ctypes.c_void_p * 3
+
+
+class Particles(ctypes.Structure):
+    _fields_ = [("x", _F3), ("p", _F3), ("psi1", _F3), ("psi2", _F3),
+                ("node", ctypes.c_int32), ("force_node", ctypes.c_int32),
+                ("force_ws", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcola.so not built at {LIB_PATH}; run python -m paper_1509_04685_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P, C, PP = ctypes.POINTER(Problem), ctypes.POINTER(Cosmology), ctypes.POINTER(Particles)
+    sig = {
+        "cola_workspace_bytes": (sz, [P, i32]),
+        "cola_ic_2lpt": (ctypes.c_int, [P, C, ctypes.POINTER(ctypes.c_uint64), PP, vp, sz, vp]),
+        "cola_pm_force": (ctypes.c_int, [P, PP, ctypes.POINTER(vp), vp, sz, vp]),
+        "cola_step": (ctypes.c_int, [P, C, i32, i32, PP, vp, sz, vp]),
+        "cola_power_spectrum": (ctypes.c_int, [P, C, PP, dbl, i32, i32, vp, vp, vp, vp, sz, vp]),
+        "cola_cic_density": (ctypes.c_int, [ctypes.POINTER(vp), i64, i32, dbl, vp, vp, sz, vp]),
+        "cola_cic_workspace_bytes": (sz, [i64, i32]),
+        "cola_fft_workspace_bytes": (sz, [i32]),
+        "cola_fft_r2c": (ctypes.c_int, [i32, vp, vp, vp, sz, vp]),
+        "cola_fft_c2r": (ctypes.c_int, [i32, vp, vp, vp, sz, vp]),
+        "cola_schedule_table": (ctypes.c_int, [P, C, ctypes.POINTER(dbl)]),
+        "cola_linear_power": (dbl, [C, dbl]),
+        "cola_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "cola_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def check(status, where):
+    if status != COLA_OK:
+        raise ColaError(status, where)

@@ -1,0 +1,442 @@
+// C-ABI entry points of libcola: validation, workspace carving and the order of the passes.
+// Every check runs on the host before the first launch, so error returns leave nothing queued.
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cola_internal.h"
+
+using namespace cola;
+
+namespace {
+
+constexpr int kMaxMesh = 2048;
+
+#define COLA_TRY(expr)                                  \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return COLA_ERR_HIP;      \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+    Mesh3 g;   // force mesh, N_g
+    Mesh3 gp;  // Lagrangian lattice, N_p
+    Mesh3 gk;  // P(k) mesh (n = 0 when absent)
+    long cstride = 0;  // float2 per realization in S, A, B
+    long kstride = 0;  // float2 per realization in K
+    size_t off_s = 0, off_a = 0, off_b = 0, off_k = 0, off_twg = 0, off_twp = 0, off_twk = 0;
+    size_t total = 0;
+};
+
+Layout layout_of(const cola_problem& p, int n_pk) {
+    Layout L;
+    L.g = make_mesh(p.n_part * p.pm_factor);
+    L.gp = make_mesh(p.n_part);
+    L.cstride = std::max(L.g.total_c(), L.gp.total_c());
+    size_t cb = align256((size_t)L.cstride * sizeof(float2) * p.n_real);
+    size_t off = 0;
+    L.off_s = off; off += cb;
+    L.off_a = off; off += cb;
+    L.off_b = off; off += cb;
+    if (n_pk > 0) {
+        L.gk = make_mesh(n_pk);
+        L.kstride = L.gk.total_c();
+        L.off_k = off;
+        off += align256((size_t)L.kstride * sizeof(float2) * p.n_real);
+    }
+    L.off_twg = off; off += align256((size_t)L.g.n * sizeof(float2));
+    L.off_twp = off; off += align256((size_t)L.gp.n * sizeof(float2));
+    L.off_twk = off; off += align256((size_t)(n_pk > 0 ? n_pk : 1) * sizeof(float2));
+    L.total = off;
+    return L;
+}
+
+int check_problem(const cola_problem* p) {
+    if (!p) return COLA_ERR_INVALID_ARG;
+    if (!(p->box > 0.0) || !std::isfinite(p->box)) return COLA_ERR_INVALID_ARG;
+    if (p->n_part < 2 || p->pm_factor < 1 || p->n_real < 1) return COLA_ERR_INVALID_ARG;
+    if (p->n_steps < 2 || p->sampling != 0) return COLA_ERR_INVALID_ARG;
+    if (!(p->z_init > -1.0) || !std::isfinite(p->z_init)) return COLA_ERR_INVALID_ARG;
+    double a0 = 1.0 / (1.0 + p->z_init);
+    if (!(p->a_final > a0) || !std::isfinite(p->a_final)) return COLA_ERR_INVALID_ARG;
+    long ng = (long)p->n_part * p->pm_factor;
+    if (ng > kMaxMesh || !fft_size_ok((int)ng) || !fft_size_ok(p->n_part)) return COLA_ERR_UNSUPPORTED_SIZE;
+    return COLA_OK;
+}
+
+int check_cosmo(const cola_cosmology* c) {
+    if (!c) return COLA_ERR_INVALID_ARG;
+    if (!(c->omega_m > 0.0 && c->omega_m <= 1.0) || !(c->h > 0.0) || !(c->sigma_8 > 0.0) ||
+        !(c->omega_b >= 0.0 && c->omega_b < c->omega_m) || !std::isfinite(c->n_s))
+        return COLA_ERR_INVALID_ARG;
+    return COLA_OK;
+}
+
+int check_particles(const cola_particles* P) {
+    if (!P) return COLA_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!P->x[d] || !P->p[d] || !P->psi1[d] || !P->psi2[d]) return COLA_ERR_INVALID_ARG;
+    return COLA_OK;
+}
+
+ParticlePtrs ptrs_of(const cola_particles* P) {
+    ParticlePtrs q;
+    for (int d = 0; d < 3; ++d) {
+        q.x[d] = P->x[d];
+        q.p[d] = P->p[d];
+        q.psi1[d] = P->psi1[d];
+        q.psi2[d] = P->psi2[d];
+    }
+    return q;
+}
+
+struct Ws {
+    float2 *S, *A, *B, *K, *twg, *twp, *twk;
+};
+
+Ws carve(void* ws, const Layout& L) {
+    char* b = static_cast<char*>(ws);
+    Ws w;
+    w.S = reinterpret_cast<float2*>(b + L.off_s);
+    w.A = reinterpret_cast<float2*>(b + L.off_a);
+    w.B = reinterpret_cast<float2*>(b + L.off_b);
+    w.K = L.kstride ? reinterpret_cast<float2*>(b + L.off_k) : nullptr;
+    w.twg = reinterpret_cast<float2*>(b + L.off_twg);
+    w.twp = reinterpret_cast<float2*>(b + L.off_twp);
+    w.twk = reinterpret_cast<float2*>(b + L.off_twk);
+    return w;
+}
+
+LatticeGeom force_geom(const cola_problem& p, const Layout& L) {
+    LatticeGeom g;
+    g.n_part = p.n_part;
+    g.n_mesh = L.g.n;
+    g.inv_h = (float)(L.g.n / p.box);
+    g.qoff = 0.5f;
+    g.row = 2L * L.g.nzp;
+    g.mesh_bstride = 2L * L.cstride;
+    return g;
+}
+
+// Density, forward transform and force meshes for the current positions.  Force meshes end up
+// as real rows in B (x), A (y), S (z).
+hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, const ParticlePtrs& P,
+                         hipStream_t st) {
+    const long npr = (long)p.n_part * p.n_part * p.n_part;
+    hipError_t e = launch_fill(reinterpret_cast<float*>(w.S), 2L * L.cstride * p.n_real, 0.0f, st);
+    if (e != hipSuccess) return e;
+    LatticeGeom fg = force_geom(p, L);
+    e = cic_deposit_lagrangian(P, npr, p.n_real, fg, reinterpret_cast<float*>(w.S), st);
+    if (e != hipSuccess) return e;
+    double cells = (double)L.g.n * L.g.n * L.g.n;
+    e = fft_zy_forward(reinterpret_cast<const float*>(w.S), 2L * L.g.nzp, 2L * L.cstride, w.S, L.cstride, L.g,
+                       w.twg, p.n_real, (float)(cells / (double)npr), -1.0f, st);
+    if (e != hipSuccess) return e;
+    return pm_force_from_spectrum(w.S, w.A, w.B, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real, st);
+}
+
+struct ForceMeshes {
+    const float *fx, *fy, *fz;
+};
+ForceMeshes force_meshes(const Ws& w) {
+    return {reinterpret_cast<const float*>(w.B), reinterpret_cast<const float*>(w.A),
+            reinterpret_cast<const float*>(w.S)};
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cola_version(void) { return "libcola 0.1 (gfx950)"; }
+
+const char* cola_status_string(int status) {
+    switch (status) {
+        case COLA_OK: return "ok";
+        case COLA_ERR_INVALID_ARG: return "invalid argument (NULL pointer or out-of-range parameter)";
+        case COLA_ERR_UNSUPPORTED_SIZE:
+            return "unsupported mesh size (must be even, <= 2048, with prime factors 2 and 3 only)";
+        case COLA_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case COLA_ERR_HIP: return "HIP runtime error";
+        case COLA_ERR_STATE: return "particle state does not fit the call (node range)";
+        case COLA_ERR_NONFINITE: return "non-finite value";
+        default: return "unknown status";
+    }
+}
+
+size_t cola_workspace_bytes(const cola_problem* prob, int32_t n_pk) {
+    if (check_problem(prob) != COLA_OK) return 0;
+    if (n_pk < 0 || (n_pk > 0 && (!fft_size_ok(n_pk) || n_pk > kMaxMesh))) return 0;
+    return layout_of(*prob, n_pk).total;
+}
+
+int cola_schedule_table(const cola_problem* prob, const cola_cosmology* cosmo, double* out) {
+    int s = check_problem(prob);
+    if (s != COLA_OK) return s;
+    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
+    if (!out) return COLA_ERR_INVALID_ARG;
+    Schedule sc = make_schedule(*prob, *cosmo);
+    int n = prob->n_steps;
+    for (int j = 0; j < n; ++j) {
+        double* r = out + 6 * j;
+        r[0] = sc.a[j];
+        r[1] = sc.d1[j];
+        r[2] = sc.d2[j];
+        r[3] = j + 1 < n ? sc.k_out[j] : 0.0;
+        r[4] = j + 1 < n ? sc.k_in[j] : 0.0;
+        r[5] = j + 1 < n ? sc.drift[j] : 0.0;
+    }
+    return COLA_OK;
+}
+
+double cola_linear_power(const cola_cosmology* cosmo, double k) {
+    if (check_cosmo(cosmo) != COLA_OK || !(k >= 0.0)) return -1.0;
+    if (k == 0.0) return 0.0;
+    double t = bbks_transfer(k, bbks_gamma(*cosmo));
+    return linear_amplitude(*cosmo) * std::pow(k, cosmo->n_s) * t * t;
+}
+
+int cola_ic_2lpt(const cola_problem* prob, const cola_cosmology* cosmo, const uint64_t* seeds,
+                 cola_particles* out, void* ws, size_t ws_bytes, void* stream) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
+    if ((s = check_particles(out)) != COLA_OK) return s;
+    if (!seeds || !ws) return COLA_ERR_INVALID_ARG;
+    Layout L = layout_of(*prob, 0);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    const cola_problem& p = *prob;
+    const int np = p.n_part;
+    const long npr = (long)np * np * np;
+    const Mesh3& gp = L.gp;
+    const float kf = (float)(2.0 * M_PI / p.box);
+    const float inv_n3 = (float)(1.0 / (double)npr);
+    ParticlePtrs P = ptrs_of(out);
+
+    COLA_TRY(launch_twiddles(w.twp, gp.n, st));
+    // white noise -> delta_k in S
+    COLA_TRY(ic_noise(out->p[0], np, seeds, p.n_real, npr, st));
+    COLA_TRY(fft3d_r2c(out->p[0], np, npr, w.S, L.cstride, gp, w.twp, p.n_real, 1.0f, 0.0f, st));
+    double amp = linear_amplitude(*cosmo), gamma = bbks_gamma(*cosmo);
+    COLA_TRY(ic_scale_spectrum(w.S, L.cstride, gp, p.n_real, kf, amp, gamma, cosmo->n_s,
+                               (double)npr / (p.box * p.box * p.box), st));
+    // second-order source S(q) in p[0]; phi_ii in x[0..2], phi_ij scratch in p[1]
+    for (int a = 0; a < 3; ++a)
+        COLA_TRY(fft3d_c2r_mult(w.S, L.cstride, w.A, L.cstride, out->x[a], np, npr, gp, w.twp, p.n_real, MUL_KK,
+                                a, a, kf, inv_n3, st));
+    const long ntot = npr * p.n_real;
+    COLA_TRY(lpt2_source(out->p[0], out->x[0], out->x[1], out->x[2], ntot, 0, st));
+    const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (auto& pr : pairs) {
+        COLA_TRY(fft3d_c2r_mult(w.S, L.cstride, w.A, L.cstride, out->p[1], np, npr, gp, w.twp, p.n_real, MUL_KK,
+                                pr[0], pr[1], kf, inv_n3, st));
+        COLA_TRY(lpt2_source(out->p[0], out->p[1], nullptr, nullptr, ntot, 1, st));
+    }
+    COLA_TRY(fft3d_r2c(out->p[0], np, npr, w.B, L.cstride, gp, w.twp, p.n_real, 1.0f, 0.0f, st));
+    for (int d = 0; d < 3; ++d) {
+        COLA_TRY(fft3d_c2r_mult(w.B, L.cstride, w.A, L.cstride, out->psi2[d], np, npr, gp, w.twp, p.n_real,
+                                MUL_IK, d, d, kf, -inv_n3, st));
+        COLA_TRY(fft3d_c2r_mult(w.S, L.cstride, w.A, L.cstride, out->psi1[d], np, npr, gp, w.twp, p.n_real,
+                                MUL_IK, d, d, kf, inv_n3, st));
+    }
+    Growth g0 = growth(1.0 / (1.0 + p.z_init), cosmo->omega_m);
+    COLA_TRY(ic_set_state(P, ntot, (float)g0.d1, (float)g0.d2, st));
+    out->node = 0;
+    out->force_node = -1;
+    out->force_ws = nullptr;
+    return COLA_OK;
+}
+
+int cola_pm_force(const cola_problem* prob, const cola_particles* in, float* acc[3], void* ws,
+                  size_t ws_bytes, void* stream) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if ((s = check_particles(in)) != COLA_OK) return s;
+    if (!acc || !acc[0] || !acc[1] || !acc[2] || !ws) return COLA_ERR_INVALID_ARG;
+    Layout L = layout_of(*prob, 0);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    ParticlePtrs P = ptrs_of(in);
+    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
+    COLA_TRY(compute_force(*prob, L, w, P, st));
+    ForceMeshes f = force_meshes(w);
+    const long npr = (long)prob->n_part * prob->n_part * prob->n_part;
+    COLA_TRY(gather_force(P, npr, prob->n_real, force_geom(*prob, L), f.fx, f.fy, f.fz, acc, st));
+    return COLA_OK;
+}
+
+int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
+              cola_particles* io, void* ws, size_t ws_bytes, void* stream) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
+    if ((s = check_particles(io)) != COLA_OK) return s;
+    if (!ws) return COLA_ERR_INVALID_ARG;
+    if (j_begin != io->node || j_begin < 0 || j_end < j_begin || j_end >= prob->n_steps) return COLA_ERR_STATE;
+    Layout L = layout_of(*prob, 0);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    if (j_end == j_begin) return COLA_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    const cola_problem& p = *prob;
+    ParticlePtrs P = ptrs_of(io);
+    Schedule sc = make_schedule(p, *cosmo);
+    const double c32 = 1.5 * sc.omega_m;
+    const long npr = (long)p.n_part * p.n_part * p.n_part;
+    LatticeGeom fg = force_geom(p, L);
+    ForceMeshes f = force_meshes(w);
+
+    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
+    if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st));
+    double pending = 0.0;  // kick still owed to the current node (merged with the next kick)
+    for (int j = j_begin; j < j_end; ++j) {
+        KickDrift kd;
+        kd.kick = (float)(c32 * (pending + sc.k_out[j]));
+        kd.d1 = (float)sc.d1[j];
+        kd.d2m = (float)(sc.d2[j] - sc.d1[j] * sc.d1[j]);
+        kd.drift = (float)sc.drift[j];
+        kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
+        kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
+        COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
+        COLA_TRY(compute_force(p, L, w, P, st));
+        pending = sc.k_in[j];
+    }
+    KickDrift kd{};
+    kd.kick = (float)(c32 * pending);
+    kd.d1 = (float)sc.d1[j_end];
+    kd.d2m = (float)(sc.d2[j_end] - sc.d1[j_end] * sc.d1[j_end]);
+    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
+    io->node = j_end;
+    io->force_node = j_end;
+    io->force_ws = ws;
+    return COLA_OK;
+}
+
+int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,
+                        double a_out, int32_t n_pk, int32_t n_bins, double* k_mean, double* pk,
+                        double* n_modes, void* ws, size_t ws_bytes, void* stream) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
+    if ((s = check_particles(in)) != COLA_OK) return s;
+    if (!k_mean || !pk || !n_modes || !ws) return COLA_ERR_INVALID_ARG;
+    if (n_bins < 1 || n_bins > 4096) return COLA_ERR_INVALID_ARG;
+    if (!fft_size_ok(n_pk) || n_pk > kMaxMesh) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (in->node < 0 || in->node >= prob->n_steps) return COLA_ERR_STATE;
+    const cola_problem& p = *prob;
+    Layout L = layout_of(p, n_pk);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    Schedule sc = make_schedule(p, *cosmo);
+    const int j = in->node;
+    const double aj = sc.a[j];
+    const bool on_node = std::fabs(a_out - aj) <= 1e-12 * aj;
+    if (!on_node && !(j + 1 < p.n_steps && a_out > aj && a_out < sc.a[j + 1])) return COLA_ERR_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    ParticlePtrs P = ptrs_of(in);
+    const long npr = (long)p.n_part * p.n_part * p.n_part;
+    LatticeGeom fg = force_geom(p, L);
+    ForceMeshes f = force_meshes(w);
+    KickDrift kd{};
+    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
+    COLA_TRY(launch_twiddles(w.twk, n_pk, st));
+    if (!on_node) {
+        if (!(in->force_node == j && in->force_ws == ws)) {
+            COLA_TRY(compute_force(p, L, w, P, st));
+            in->force_node = j;
+            in->force_ws = ws;
+        }
+        Growth go = growth(a_out, sc.omega_m);
+        kd.kick = (float)(1.5 * sc.omega_m * sc.k_out[j]);
+        kd.d1 = (float)sc.d1[j];
+        kd.d2m = (float)(sc.d2[j] - sc.d1[j] * sc.d1[j]);
+        kd.drift = (float)drift_integral(aj, a_out, sc.omega_m);
+        kd.dd1 = (float)(go.d1 - sc.d1[j]);
+        kd.dd2 = (float)(go.d2 - sc.d2[j]);
+    }
+    const Mesh3& gk = L.gk;
+    COLA_TRY(launch_fill(reinterpret_cast<float*>(w.K), 2L * L.kstride * p.n_real, 0.0f, st));
+    LatticeGeom dg;
+    dg.n_part = p.n_part;
+    dg.n_mesh = n_pk;
+    dg.inv_h = (float)(n_pk / p.box);
+    dg.qoff = (float)(0.5 * (double)n_pk / (double)L.g.n);
+    dg.row = 2L * gk.nzp;
+    dg.mesh_bstride = 2L * L.kstride;
+    COLA_TRY(cic_deposit_drifted(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, dg, reinterpret_cast<float*>(w.K), st));
+    double cells = (double)n_pk * n_pk * n_pk;
+    COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K, L.kstride, gk, w.twk,
+                       p.n_real, (float)(cells / (double)npr), -1.0f, st));
+    const long nb = (long)n_bins * p.n_real;
+    COLA_TRY(launch_fill_d(k_mean, nb, 0.0, st));
+    COLA_TRY(launch_fill_d(pk, nb, 0.0, st));
+    COLA_TRY(launch_fill_d(n_modes, nb, 0.0, st));
+    COLA_TRY(pk_bin(w.K, L.kstride, gk, p.n_real, n_bins, k_mean, pk, n_modes, 2.0 * M_PI / p.box, st));
+    double pnorm = p.box * p.box * p.box / (cells * cells);
+    COLA_TRY(pk_finish(k_mean, pk, n_modes, nb, pnorm, st));
+    return COLA_OK;
+}
+
+// ---------------------------------------------------------------- component entry points
+
+size_t cola_cic_workspace_bytes(int64_t n, int32_t n_mesh) {
+    (void)n;
+    (void)n_mesh;
+    return 0;
+}
+
+int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box, float* delta, void* ws,
+                     size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!pos || !pos[0] || !pos[1] || !pos[2] || !delta || n < 1 || n_mesh < 2 || n_mesh > kMaxMesh ||
+        !(box > 0.0))
+        return COLA_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    long cells = (long)n_mesh * n_mesh * n_mesh;
+    COLA_TRY(launch_fill(delta, cells, 0.0f, st));
+    COLA_TRY(cic_deposit_absolute(pos, n, n_mesh, (float)(n_mesh / box), n_mesh, delta, st));
+    COLA_TRY(density_finish(delta, n_mesh, n_mesh, (float)((double)cells / (double)n), -1.0f, st));
+    return COLA_OK;
+}
+
+size_t cola_fft_workspace_bytes(int32_t n) {
+    if (!fft_size_ok(n) || n > kMaxMesh) return 0;
+    Mesh3 g = make_mesh(n);
+    return align256(g.bytes()) + align256((size_t)n * sizeof(float2));
+}
+
+int cola_fft_r2c(int32_t n, const float* in, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fft_size_ok(n) || n > kMaxMesh) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (!in || !out || !ws) return COLA_ERR_INVALID_ARG;
+    if (ws_bytes < cola_fft_workspace_bytes(n)) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Mesh3 g = make_mesh(n);
+    float2* spec = static_cast<float2*>(ws);
+    float2* tw = reinterpret_cast<float2*>(static_cast<char*>(ws) + align256(g.bytes()));
+    COLA_TRY(launch_twiddles(tw, n, st));
+    COLA_TRY(fft3d_r2c(in, n, 0, spec, 0, g, tw, 1, 1.0f, 0.0f, st));
+    COLA_TRY(copy_pad_to_unpad(spec, reinterpret_cast<float2*>(out), g, st));
+    return COLA_OK;
+}
+
+int cola_fft_c2r(int32_t n, const float* in, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fft_size_ok(n) || n > kMaxMesh) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (!in || !out || !ws) return COLA_ERR_INVALID_ARG;
+    if (ws_bytes < cola_fft_workspace_bytes(n)) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Mesh3 g = make_mesh(n);
+    float2* spec = static_cast<float2*>(ws);
+    float2* tw = reinterpret_cast<float2*>(static_cast<char*>(ws) + align256(g.bytes()));
+    COLA_TRY(launch_twiddles(tw, n, st));
+    COLA_TRY(copy_unpad_to_pad(reinterpret_cast<const float2*>(in), spec, g, st));
+    COLA_TRY(fft3d_c2r_mult(spec, 0, spec, 0, out, n, 0, g, tw, 1, MUL_SCALE, 0, 0, 1.0f, 1.0f, st));
+    return COLA_OK;
+}
+
+}  // extern "C"

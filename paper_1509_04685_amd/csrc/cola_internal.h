@@ -1,0 +1,146 @@
+// Internal declarations of libcola: host-side cosmology, mesh geometry, FFT plans and kernel
+// launchers.  Not part of the public C ABI (include/cola.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/cola.h"
+#include "fft_core.h"
+
+namespace cola {
+
+// ------------------------------------------------------------------ cosmology (float64, host)
+struct Growth {
+    double d1, d2, dd1_da, dd2_da;
+};
+double hubble_e(double a, double om);
+Growth growth(double a, double om);
+double kick_integral(double a0, double a1, double om);
+double drift_integral(double a0, double a1, double om);
+std::vector<double> time_nodes(const cola_problem& p);
+double bbks_gamma(const cola_cosmology& c);
+double bbks_transfer(double k, double gamma);
+double linear_amplitude(const cola_cosmology& c);
+
+struct Schedule {
+    double omega_m;
+    std::vector<double> a, d1, d2;          // per node
+    std::vector<double> k_out, k_in, drift;  // per interval j -> j+1
+};
+Schedule make_schedule(const cola_problem& p, const cola_cosmology& c);
+
+// ------------------------------------------------------------------ mesh geometry
+// A cubic mesh of n cells per side held as a half spectrum [n][n][nzp] of float2, nzp >= n/2+1
+// rounded up to 16 so that rows start on 128-byte boundaries.  The same memory holds the real
+// field in place as [n][n][2 nzp] floats (first n used per row).
+struct Mesh3 {
+    int n = 0;
+    int m = 0;    // n / 2
+    int nzp = 0;  // padded complex row length
+    long row_c() const { return nzp; }
+    long total_c() const { return (long)n * n * nzp; }
+    size_t bytes() const { return (size_t)total_c() * sizeof(float2); }
+};
+Mesh3 make_mesh(int n);
+bool fft_size_ok(int n);  // even, >= 4, factors 2 and 3 only
+FftPlan make_plan(int n, bool reverse = false);
+
+// ------------------------------------------------------------------ launchers (fft.hip)
+hipError_t launch_twiddles(float2* tw, int len, hipStream_t st);
+
+// Forward 3D r2c: real rows at `in` (in_row floats apart, batch stride in_bstride floats) with
+// y = pa * x + pb applied on load -> padded half spectrum `out` (batch stride out_bstride float2),
+// in place allowed (in == (float*)out with in_row = 2 nzp).  z, then y, then x.
+hipError_t fft3d_r2c(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
+                     const Mesh3& g, const float2* tw, int n_real, float pa, float pb, hipStream_t st);
+
+// PM force from the y-transformed spectrum in S (z and y forward passes done):
+//   fused x (forward, Green 1/(k^2 n^3), inverse) -> A = G S, B = i k_x G S;
+//   y inverse: A -> A (times i k_y), S (plain);  B -> B;  z c2r in place: B -> F_x,
+//   A -> F_y, S -> F_z (times i k_z).  Real force rows of 2 nzp floats.
+hipError_t pm_force_from_spectrum(float2* S, float2* A, float2* B, long bstride, const Mesh3& g,
+                                  const float2* tw, float kf, int n_real, hipStream_t st);
+// z r2c + y forward only (first half of the PM force transform)
+hipError_t fft_zy_forward(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
+                          const Mesh3& g, const float2* tw, int n_real, float pa, float pb,
+                          hipStream_t st);
+
+// Multiplier types for the inverse transforms of the initial conditions.
+enum MulType { MUL_SCALE = 0, MUL_IK = 1, MUL_KK = 2 };
+// Inverse 3D c2r of mult(k) * spec: spec is a full forward spectrum (padded), work a padded
+// scratch spectrum of the same size, out real rows of out_row floats.
+hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, long work_bstride,
+                          float* out, long out_row, long out_bstride, const Mesh3& g, const float2* tw,
+                          int n_real, int mtype, int axis_a, int axis_b, float kf, float scale,
+                          hipStream_t st);
+
+// padded <-> numpy rfftn layout copies
+hipError_t copy_unpad_to_pad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st);
+hipError_t copy_pad_to_unpad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st);
+
+// ------------------------------------------------------------------ launchers (pm_kernels.hip)
+struct ParticlePtrs {
+    float* x[3];
+    float* p[3];
+    const float* psi1[3];
+    const float* psi2[3];
+};
+
+// Geometry of a CIC mesh relative to the Lagrangian lattice.
+struct LatticeGeom {
+    int n_part;     // N_p
+    int n_mesh;     // cells per side of this mesh
+    float inv_h;    // n_mesh / L
+    float qoff;     // lattice offset in this mesh's cells (0.5 * n_mesh / N_g)
+    long row;       // floats per mesh row
+    long mesh_bstride;  // floats between realizations
+};
+
+struct KickDrift {
+    float kick;     // (3/2) Omega_m K for this kick (0: no kick)
+    float d1;       // D1 at the node of the force
+    float d2m;      // D2 - D1^2 at that node
+    float drift;    // Dr of the drift (0 with no drift)
+    float dd1, dd2; // growth increments of the drift
+};
+
+hipError_t launch_fill(float* p, long n, float v, hipStream_t st);
+hipError_t launch_fill_d(double* p, long n, double v, hipStream_t st);
+hipError_t cic_deposit_lagrangian(const ParticlePtrs& P, long n_per_real, int n_real,
+                                  const LatticeGeom& dep, float* mesh, hipStream_t st);
+// Deposit of positions drifted on the fly: x' = x + (p + kick * bracket(g)) * drift + dd1 psi1 + dd2 psi2,
+// g gathered from the force mesh (fgeom) -- for outputs between nodes.
+hipError_t cic_deposit_drifted(const ParticlePtrs& P, long n_per_real, int n_real,
+                               const LatticeGeom& fgeom, const float* fx, const float* fy,
+                               const float* fz, const KickDrift& kd, const LatticeGeom& dep,
+                               float* mesh, hipStream_t st);
+hipError_t cic_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, long row,
+                                float* mesh, hipStream_t st);
+hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float offset, hipStream_t st);
+hipError_t gather_kick_drift(const ParticlePtrs& P, long n_per_real, int n_real,
+                             const LatticeGeom& fgeom, const float* fx, const float* fy,
+                             const float* fz, const KickDrift& kd, hipStream_t st);
+hipError_t gather_force(const ParticlePtrs& P, long n_per_real, int n_real, const LatticeGeom& fgeom,
+                        const float* fx, const float* fy, const float* fz, float* const acc[3],
+                        hipStream_t st);
+
+// ------------------------------------------------------------------ launchers (ic_kernels.hip)
+hipError_t ic_noise(float* w, int n_part, const uint64_t* seeds_host, int n_real, long bstride,
+                    hipStream_t st);
+hipError_t ic_scale_spectrum(float2* spec, long bstride, const Mesh3& g, int n_real, float kf,
+                             double amp, double gamma, double n_s, double norm, hipStream_t st);
+// S = phi_xx phi_yy + phi_xx phi_zz + phi_yy phi_zz  (first call, mode 0) or S -= phi^2 (mode 1)
+hipError_t lpt2_source(float* s, const float* a, const float* b, const float* c, long n, int mode,
+                       hipStream_t st);
+hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, hipStream_t st);
+
+// ------------------------------------------------------------------ launchers (pk_kernels.hip)
+hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, int n_bins,
+                  double* ksum, double* psum, double* cnt, double kf, hipStream_t st);
+hipError_t pk_finish(double* kmean, double* pk, double* cnt, long n, double pnorm, hipStream_t st);
+
+}  // namespace cola

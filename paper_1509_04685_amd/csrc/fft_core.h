@@ -1,0 +1,204 @@
+// Register/LDS Stockham FFT engine for gfx950 (64-wide wavefronts).
+//
+// A line of n complex values (n = 2^a 3^b) is transformed by T = n / R threads, each owning
+// R values in registers.  Radix-r stages (r in {2,3,4,8}, r | R) follow the Stockham
+// autosort recursion: with ns the product of the radices already applied, butterfly j
+// (0 <= j < n/r) reads elements j + i n/r (i < r), multiplies element i by W_{ns r}^{i (j mod ns)},
+// applies an r-point DFT and writes element i to (j / ns) ns r + (j mod ns) + i ns.  Thread t
+// owns butterflies j = t + s T, s < R/r.  Between stages the values go through LDS (write,
+// barrier, read, barrier).  The first stage's inputs and the last stage's outputs use the same
+// pattern -- element (t + s T) + i n / r -- so a caller loads and stores straight from and to
+// global memory, and a forward and an inverse transform can be chained in registers when the
+// inverse plan starts with the forward plan's last radix.
+//
+// Twiddles come from a table tw[m] = exp(-2 pi i m / (n * tw_stride)) built in float64 on the
+// device; the inverse uses conjugates.  Transforms are unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cola {
+
+constexpr int kMaxStages = 12;
+
+struct FftPlan {
+    int n;        // complex line length
+    int R;        // values per thread
+    int T;        // threads per line, n / R
+    int nst;      // number of stages
+    int radix[kMaxStages];
+};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by the forward twiddle w = e^{-i theta} (or its conjugate for the inverse)
+template <bool INV>
+__device__ __forceinline__ float2 twiddle(float2 a, float2 w) {
+    return INV ? make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y)
+               : make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+    const float c = -0.5f;
+    const float s = 0.86602540378443864676f;  // sin(2 pi / 3)
+    float2 t = cadd(a1, a2);
+    float2 u = csub(a1, a2);
+    float2 m = make_float2(a0.x + c * t.x, a0.y + c * t.y);
+    // forward: X1 = m - i s u, X2 = m + i s u
+    float2 isu = INV ? make_float2(-s * u.y, s * u.x) : make_float2(s * u.y, -s * u.x);  // (-+ i) s u
+    a0 = cadd(a0, t);
+    a1 = cadd(m, isu);
+    a2 = csub(m, isu);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+    float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    float2 t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* a) {
+    const float h = 0.70710678118654752440f;
+    float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+    float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+    dft4<INV>(e0, e1, e2, e3);
+    dft4<INV>(o0, o1, o2, o3);
+    // W8^1 = (1 - i)/sqrt2, W8^2 = -i, W8^3 = (-1 - i)/sqrt2 (forward); conjugates inverse
+    float2 w1 = INV ? make_float2(h * (o1.x - o1.y), h * (o1.x + o1.y))
+                    : make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));
+    float2 w2 = mul_mi<INV>(o2);
+    float2 w3 = INV ? make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y))
+                    : make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+    a[0] = cadd(e0, o0);
+    a[4] = csub(e0, o0);
+    a[1] = cadd(e1, w1);
+    a[5] = csub(e1, w1);
+    a[2] = cadd(e2, w2);
+    a[6] = csub(e2, w2);
+    a[3] = cadd(e3, w3);
+    a[7] = csub(e3, w3);
+}
+
+// One radix-r stage on the registers of one thread: twiddle then butterfly.
+template <int r, int R, bool INV>
+__device__ __forceinline__ void stage_compute(float2 (&v)[R], int t, int T, int n, int ns,
+                                              const float2* tw, int tw_stride) {
+#pragma unroll
+    for (int s = 0; s < R / r; ++s) {
+        float2* a = &v[s * r];
+        if (ns > 1) {
+            int j = t + s * T;
+            int k = j % ns;
+            int step = (n / (ns * r)) * k * tw_stride;
+#pragma unroll
+            for (int i = 1; i < r; ++i) a[i] = twiddle<INV>(a[i], tw[i * step]);
+        }
+        if constexpr (r == 2) dft2<INV>(a[0], a[1]);
+        if constexpr (r == 3) dft3<INV>(a[0], a[1], a[2]);
+        if constexpr (r == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
+        if constexpr (r == 8) dft8<INV>(a);
+    }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void stage_dispatch(int r, float2 (&v)[R], int t, int T, int n, int ns,
+                                               const float2* tw, int tw_stride) {
+    if constexpr (R % 8 == 0) { if (r == 8) { stage_compute<8, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { stage_compute<4, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { stage_compute<3, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { stage_compute<2, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
+}
+
+// Scatter a stage's outputs to LDS: value v[s r + i] goes to element (j/ns) ns r + j%ns + i ns.
+template <int r, int R>
+__device__ __forceinline__ void stage_store(const float2 (&v)[R], float2* lds, int les, int t, int T,
+                                            int ns) {
+#pragma unroll
+    for (int s = 0; s < R / r; ++s) {
+        int j = t + s * T;
+        int base = (j / ns) * ns * r + (j % ns);
+#pragma unroll
+        for (int i = 0; i < r; ++i) lds[(base + i * ns) * les] = v[s * r + i];
+    }
+}
+
+// Gather a stage's inputs from LDS: v[s r + i] = element (t + s T) + i n / r.
+template <int r, int R>
+__device__ __forceinline__ void stage_load(float2 (&v)[R], const float2* lds, int les, int t, int T,
+                                           int n) {
+#pragma unroll
+    for (int s = 0; s < R / r; ++s) {
+        int j = t + s * T;
+#pragma unroll
+        for (int i = 0; i < r; ++i) v[s * r + i] = lds[(j + i * (n / r)) * les];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void store_dispatch(int r, const float2 (&v)[R], float2* lds, int les,
+                                               int t, int T, int ns) {
+    if constexpr (R % 8 == 0) { if (r == 8) { stage_store<8, R>(v, lds, les, t, T, ns); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { stage_store<4, R>(v, lds, les, t, T, ns); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { stage_store<3, R>(v, lds, les, t, T, ns); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { stage_store<2, R>(v, lds, les, t, T, ns); return; } }
+}
+
+template <int R>
+__device__ __forceinline__ void load_dispatch(int r, float2 (&v)[R], const float2* lds, int les,
+                                              int t, int T, int n) {
+    if constexpr (R % 8 == 0) { if (r == 8) { stage_load<8, R>(v, lds, les, t, T, n); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { stage_load<4, R>(v, lds, les, t, T, n); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { stage_load<3, R>(v, lds, les, t, T, n); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { stage_load<2, R>(v, lds, les, t, T, n); return; } }
+}
+
+// Element index held in v[s r + i] by the load/store pattern of a radix-r first/last stage.
+__device__ __forceinline__ int pattern_index(int s, int i, int r, int t, int T, int n) {
+    return t + s * T + i * (n / r);
+}
+
+// Full line transform.  On entry v holds the inputs in the pattern of plan radix[0]; on exit v
+// holds the outputs in the pattern of plan radix[nst-1].  `active` threads take part in the
+// LDS exchange; every thread of the block must call this (barriers inside).  `lds` points at
+// element 0 of this thread's line; consecutive elements are `les` float2 apart.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_line(float2 (&v)[R], const FftPlan& pl, float2* lds, int les,
+                                         int t, const float2* tw, int tw_stride, bool active) {
+    int ns = 1;
+    for (int st = 0; st < pl.nst; ++st) {
+        int r = pl.radix[st];
+        if (active) stage_dispatch<R, INV>(r, v, t, pl.T, pl.n, ns, tw, tw_stride);
+        if (st + 1 < pl.nst) {
+            if (active) store_dispatch<R>(r, v, lds, les, t, pl.T, ns);
+            __syncthreads();
+            if (active) load_dispatch<R>(pl.radix[st + 1], v, lds, les, t, pl.T, pl.n);
+            __syncthreads();
+        }
+        ns *= r;
+    }
+}
+
+}  // namespace cola

@@ -1,0 +1,100 @@
+// Matter power-spectrum binning (Sec. 2.5): |delta_k|^2 with the CIC window divided out,
+// averaged over integer |m| shells; float64 sums.
+//
+// Bin b >= 1 holds the modes with b^2 <= |m|^2 < (b+1)^2, decided on integers so that every
+// implementation bins a mode identically; k = 0 is excluded.  Each half-spectrum mode counts
+// twice (itself and its mirror) except on the kz = 0 and kz = n/2 planes.
+
+#include "cola_internal.h"
+
+namespace cola {
+
+constexpr int kMaxBinsLds = 1024;
+
+__device__ __forceinline__ int isqrt_floor(long v) {
+    int b = (int)sqrtf((float)v);
+    while ((long)b * b > v) --b;
+    while ((long)(b + 1) * (b + 1) <= v) ++b;
+    return b;
+}
+
+__device__ __forceinline__ float sinc_pi(float x) {  // sin(pi x) / (pi x)
+    return x == 0.0f ? 1.0f : sinpif(x) / (3.14159265358979323846f * x);
+}
+
+__global__ void k_pk_bin(const float2* spec, long bstride, int n, int nzp, int n_bins, double* ksum,
+                         double* psum, double* cnt, double kf) {
+    __shared__ double sk[kMaxBinsLds], sp[kMaxBinsLds], sc[kMaxBinsLds];
+    const bool use_lds = n_bins <= kMaxBinsLds;
+    if (use_lds)
+        for (int b = threadIdx.x; b < n_bins; b += blockDim.x) sk[b] = sp[b] = sc[b] = 0.0;
+    __syncthreads();
+    const int r = blockIdx.y;
+    spec += (long)r * bstride;
+    ksum += (long)r * n_bins;
+    psum += (long)r * n_bins;
+    cnt += (long)r * n_bins;
+    const int m = n / 2;
+    const long total = (long)n * n * (m + 1);
+    const float inv_n = 1.0f / (float)n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        int kz = (int)(i % (m + 1));
+        long rr = i / (m + 1);
+        int ky = (int)(rr % n), kx = (int)(rr / n);
+        int mx = kx < m ? kx : kx - n, my = ky < m ? ky : ky - n;
+        long m2 = (long)mx * mx + (long)my * my + (long)kz * kz;
+        if (m2 == 0) continue;
+        int b = isqrt_floor(m2);
+        if (b >= n_bins) continue;
+        float2 d = spec[rr * nzp + kz];
+        float w1 = sinc_pi(mx * inv_n) * sinc_pi(my * inv_n) * sinc_pi(kz * inv_n);
+        float w2 = w1 * w1;
+        float pw = (d.x * d.x + d.y * d.y) / (w2 * w2);
+        double wt = (kz == 0 || kz == m) ? 1.0 : 2.0;
+        double kk = kf * sqrt((double)m2);
+        if (use_lds) {
+            atomicAdd(&sk[b], wt * kk);
+            atomicAdd(&sp[b], wt * (double)pw);
+            atomicAdd(&sc[b], wt);
+        } else {
+            atomicAdd(&ksum[b], wt * kk);
+            atomicAdd(&psum[b], wt * (double)pw);
+            atomicAdd(&cnt[b], wt);
+        }
+    }
+    __syncthreads();
+    if (use_lds)
+        for (int b = threadIdx.x; b < n_bins; b += blockDim.x) {
+            if (sc[b] != 0.0) {
+                atomicAdd(&ksum[b], sk[b]);
+                atomicAdd(&psum[b], sp[b]);
+                atomicAdd(&cnt[b], sc[b]);
+            }
+        }
+}
+
+hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, int n_bins, double* ksum,
+                  double* psum, double* cnt, double kf, hipStream_t st) {
+    long total = (long)g.n * g.n * (g.m + 1);
+    long blocks = (total + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_pk_bin, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.nzp,
+                       n_bins, ksum, psum, cnt, kf);
+    return hipGetLastError();
+}
+
+// k_mean = ksum / cnt, pk = psum / cnt * pnorm (pnorm = L^3 / n^6), zero for empty bins.
+__global__ void k_pk_finish(double* kmean, double* pk, const double* cnt, long n, double pnorm) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double c = cnt[i];
+    kmean[i] = c > 0.0 ? kmean[i] / c : 0.0;
+    pk[i] = c > 0.0 ? pk[i] / c * pnorm : 0.0;
+}
+
+hipError_t pk_finish(double* kmean, double* pk, double* cnt, long n, double pnorm, hipStream_t st) {
+    hipLaunchKernelGGL(k_pk_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, kmean, pk, cnt, n, pnorm);
+    return hipGetLastError();
+}
+
+}  // namespace cola

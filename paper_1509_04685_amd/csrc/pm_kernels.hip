@@ -1,0 +1,276 @@
+// Particle kernels of the COLA particle-mesh step (Sec. 2.2; Eq. 1-2):
+//   CIC mass assignment onto the force mesh, CIC interpolation of the three force meshes back to
+//   the particles fused with the COLA kick and drift in the frame of the 2LPT trajectories.
+//
+// Particles are structure-of-arrays in Lagrangian order; the position is never stored as an
+// absolute float.  Along each axis the cell coordinate is split into an exact integer part from
+// the lattice index and a small float part from the displacement:
+//   u = (i * n_mesh) / N_p  +  [ ((i * n_mesh) mod N_p) / N_p + qoff + x * n_mesh / L ],
+// so the CIC fraction keeps the precision of the displacement (about 1e-6 cell) even on 1536^3
+// meshes where an absolute float coordinate would only resolve 1e-4 cell.
+
+#include "cola_internal.h"
+
+namespace cola {
+
+struct Cell {
+    int m;    // lower node, wrapped into [0, n)
+    float f;  // fraction towards m + 1
+};
+
+__device__ __forceinline__ Cell cell_of(int i, float x, int n_part, int n_mesh, float inv_h, float qoff) {
+    long a = (long)i * n_mesh;
+    int q = (int)(a / n_part);
+    int rem = (int)(a - (long)q * n_part);
+    float w = (float)rem / (float)n_part + qoff + x * inv_h;
+    float fl = floorf(w);
+    Cell c;
+    c.f = w - fl;
+    int m = (q + (int)fl) % n_mesh;
+    m = m < 0 ? m + n_mesh : m;
+    c.m = min(max(m, 0), n_mesh - 1);  // a non-finite position still maps inside the mesh
+    return c;
+}
+
+__device__ __forceinline__ int wrap1(int m, int n) { return m + 1 == n ? 0 : m + 1; }
+
+__device__ __forceinline__ void lagr_index(long p, int n_part, int& i, int& j, int& l) {
+    long np2 = (long)n_part * n_part;
+    i = (int)(p / np2);
+    long r = p - (long)i * np2;
+    j = (int)(r / n_part);
+    l = (int)(r - (long)j * n_part);
+}
+
+// CIC gather of three meshes at one particle.
+__device__ __forceinline__ void gather3(const float* fx, const float* fy, const float* fz, long row, int n,
+                                        const Cell& cx, const Cell& cy, const Cell& cz, float g[3]) {
+    const int x0 = cx.m, x1 = wrap1(cx.m, n), y0 = cy.m, y1 = wrap1(cy.m, n), z0 = cz.m, z1 = wrap1(cz.m, n);
+    const float wx[2] = {1.0f - cx.f, cx.f}, wy[2] = {1.0f - cy.f, cy.f}, wz[2] = {1.0f - cz.f, cz.f};
+    const int xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    g[0] = g[1] = g[2] = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            long r = ((long)xs[a] * n + ys[b]) * row;
+            float wab = wx[a] * wy[b];
+            float w0 = wab * wz[0], w1 = wab * wz[1];
+            g[0] += w0 * fx[r + z0] + w1 * fx[r + z1];
+            g[1] += w0 * fy[r + z0] + w1 * fy[r + z1];
+            g[2] += w0 * fz[r + z0] + w1 * fz[r + z1];
+        }
+}
+
+__device__ __forceinline__ void deposit8(float* mesh, long row, int n, const Cell& cx, const Cell& cy,
+                                         const Cell& cz) {
+    const int xs[2] = {cx.m, wrap1(cx.m, n)}, ys[2] = {cy.m, wrap1(cy.m, n)}, zs[2] = {cz.m, wrap1(cz.m, n)};
+    const float wx[2] = {1.0f - cx.f, cx.f}, wy[2] = {1.0f - cy.f, cy.f}, wz[2] = {1.0f - cz.f, cz.f};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            long r = ((long)xs[a] * n + ys[b]) * row;
+            float wab = wx[a] * wy[b];
+            atomicAdd(&mesh[r + zs[0]], wab * wz[0]);
+            atomicAdd(&mesh[r + zs[1]], wab * wz[1]);
+        }
+}
+
+// ------------------------------------------------------------------ fills
+
+__global__ void k_fill(float* p, long n, float v) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_d(double* p, long n, double v) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static unsigned grid_for(long n, int block) {
+    long b = (n + block - 1) / block;
+    if (b > 65535L * 16) b = 65535L * 16;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_fill(float* p, long n, float v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_d(double* p, long n, double v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ CIC deposit
+
+__global__ void k_deposit_lagr(ParticlePtrs P, long npr, int n_real, LatticeGeom dg, float* mesh) {
+    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= npr * n_real) return;
+    long r = gid / npr, p = gid - r * npr;
+    int i, j, l;
+    lagr_index(p, dg.n_part, i, j, l);
+    Cell cx = cell_of(i, P.x[0][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
+    Cell cy = cell_of(j, P.x[1][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
+    Cell cz = cell_of(l, P.x[2][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
+    deposit8(mesh + r * dg.mesh_bstride, dg.row, dg.n_mesh, cx, cy, cz);
+}
+
+hipError_t cic_deposit_lagrangian(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg,
+                                  float* mesh, hipStream_t st) {
+    long n = npr * n_real;
+    hipLaunchKernelGGL(k_deposit_lagr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
+                       dg, mesh);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ float bracket(float g, float d1, float d2m, float s1, float s2) {
+    return g - d1 * s1 - d2m * s2;
+}
+
+__global__ void k_deposit_drifted(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* fx,
+                                  const float* fy, const float* fz, KickDrift kd, LatticeGeom dg,
+                                  float* mesh) {
+    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= npr * n_real) return;
+    long r = gid / npr, p = gid - r * npr;
+    int idx[3];
+    lagr_index(p, fg.n_part, idx[0], idx[1], idx[2]);
+    float x[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];
+    if (kd.drift != 0.0f || kd.dd1 != 0.0f) {
+        Cell c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
+        float g[3];
+        long mo = r * fg.mesh_bstride;
+        gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
+            float ph = P.p[d][gid] + kd.kick * bracket(g[d], kd.d1, kd.d2m, s1, s2);
+            x[d] = x[d] + ph * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
+        }
+    }
+    Cell c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], x[d], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
+    deposit8(mesh + r * dg.mesh_bstride, dg.row, dg.n_mesh, c[0], c[1], c[2]);
+}
+
+hipError_t cic_deposit_drifted(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg,
+                               const float* fx, const float* fy, const float* fz, const KickDrift& kd,
+                               const LatticeGeom& dg, float* mesh, hipStream_t st) {
+    long n = npr * n_real;
+    hipLaunchKernelGGL(k_deposit_drifted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
+                       fg, fx, fy, fz, kd, dg, mesh);
+    return hipGetLastError();
+}
+
+__global__ void k_deposit_abs(const float* px, const float* py, const float* pz, long n, int n_mesh,
+                              float inv_h, long row, float* mesh) {
+    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n) return;
+    Cell c[3];
+    const float* ps[3] = {px, py, pz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float u = ps[d][gid] * inv_h;
+        float fl = floorf(u);
+        c[d].f = u - fl;
+        int m = (int)fl % n_mesh;
+        m = m < 0 ? m + n_mesh : m;
+        c[d].m = min(max(m, 0), n_mesh - 1);
+    }
+    deposit8(mesh, row, n_mesh, c[0], c[1], c[2]);
+}
+
+hipError_t cic_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, long row,
+                                float* mesh, hipStream_t st) {
+    hipLaunchKernelGGL(k_deposit_abs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos[0], pos[1],
+                       pos[2], n, n_mesh, inv_h, row, mesh);
+    return hipGetLastError();
+}
+
+__global__ void k_density_finish(float* mesh, long row, int n, float scale, float offset) {
+    long total = (long)n * n * n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        long r = i / n;
+        int z = (int)(i - r * n);
+        float* c = mesh + r * row + z;
+        *c = fmaf(*c, scale, offset);
+    }
+}
+
+hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float offset, hipStream_t st) {
+    long total = (long)n_mesh * n_mesh * n_mesh;
+    hipLaunchKernelGGL(k_density_finish, dim3(grid_for(total, 256)), dim3(256), 0, st, mesh, row, n_mesh,
+                       scale, offset);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gather + kick + drift
+
+// p += kick [g - D1 psi1 - (D2 - D1^2) psi2];  x += p Dr + dD1 psi1 + dD2 psi2.
+__global__ void k_gather_kick_drift(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* fx,
+                                    const float* fy, const float* fz, KickDrift kd) {
+    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= npr * n_real) return;
+    long r = gid / npr, p = gid - r * npr;
+    int idx[3];
+    lagr_index(p, fg.n_part, idx[0], idx[1], idx[2]);
+    float x[3];
+    Cell c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        x[d] = P.x[d][gid];
+        c[d] = cell_of(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
+    }
+    float g[3];
+    long mo = r * fg.mesh_bstride;
+    gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
+        float pp = P.p[d][gid] + kd.kick * bracket(g[d], kd.d1, kd.d2m, s1, s2);
+        P.p[d][gid] = pp;
+        if (kd.drift != 0.0f || kd.dd1 != 0.0f) P.x[d][gid] = x[d] + pp * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
+    }
+}
+
+hipError_t gather_kick_drift(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg,
+                             const float* fx, const float* fy, const float* fz, const KickDrift& kd,
+                             hipStream_t st) {
+    long n = npr * n_real;
+    hipLaunchKernelGGL(k_gather_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr,
+                       n_real, fg, fx, fy, fz, kd);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_force(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* fx,
+                               const float* fy, const float* fz, float* ax, float* ay, float* az) {
+    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= npr * n_real) return;
+    long r = gid / npr, p = gid - r * npr;
+    int idx[3];
+    lagr_index(p, fg.n_part, idx[0], idx[1], idx[2]);
+    Cell c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], P.x[d][gid], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
+    float g[3];
+    long mo = r * fg.mesh_bstride;
+    gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
+    ax[gid] = g[0];
+    ay[gid] = g[1];
+    az[gid] = g[2];
+}
+
+hipError_t gather_force(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
+                        const float* fy, const float* fz, float* const acc[3], hipStream_t st) {
+    long n = npr * n_real;
+    hipLaunchKernelGGL(k_gather_force, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
+                       fg, fx, fy, fz, acc[0], acc[1], acc[2]);
+    return hipGetLastError();
+}
+
+}  // namespace cola

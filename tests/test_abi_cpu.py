@@ -1,0 +1,121 @@
+"""The C-ABI library on the host: it loads, exports every symbol the header declares, rejects
+bad arguments before any launch, and its float64 host schedule matches the oracle.
+
+No test here launches device work."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cola.h")
+
+cola = pytest.importorskip("paper_1509_04685_amd")
+from paper_1509_04685_amd import _lib  # noqa: E402
+from oracle import cola as ocola, cosmology as ocosmo  # noqa: E402
+
+LIB = _lib.lib()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cola_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(LIB, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_version_and_status_strings():
+    assert b"gfx950" in LIB.cola_version()
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert LIB.cola_status_string(s)
+
+
+def prob(**kw):
+    d = dict(box=256.0, n_part=32, pm_factor=3, z_init=19.0, n_steps=10, n_real=1)
+    d.update(kw)
+    return cola.make_problem(**d)
+
+
+COSMO = cola.make_cosmology()
+
+
+@pytest.mark.parametrize("bad", [dict(n_part=35), dict(pm_factor=5), dict(n_part=1),
+                                 dict(n_part=770, pm_factor=1), dict(n_steps=1), dict(box=-1.0),
+                                 dict(z_init=-1.5), dict(n_real=0), dict(pm_factor=0)])
+def test_workspace_bytes_rejects_bad_problems(bad):
+    assert cola.workspace_bytes(prob(**bad)) == 0
+
+
+def test_workspace_bytes_scales():
+    a = cola.workspace_bytes(prob())
+    b = cola.workspace_bytes(prob(n_real=4))
+    c = cola.workspace_bytes(prob(), n_pk=96)
+    assert a > 0 and b > 3 * a and c > a
+    assert cola.workspace_bytes(prob(), n_pk=97) == 0
+
+
+def test_entry_points_validate_before_launch():
+    p = prob()
+    st = cola.Particles()
+    seeds = (ctypes.c_uint64 * 1)(1)
+    # NULL particle pointers
+    assert LIB.cola_ic_2lpt(ctypes.byref(p), ctypes.byref(COSMO), seeds, ctypes.byref(st), None, 0, None) == -1
+    fake = ctypes.c_void_p(0x1000)
+    for d in range(3):
+        st.x[d] = st.p[d] = st.psi1[d] = st.psi2[d] = 0x1000
+    # workspace missing, then too small
+    assert LIB.cola_ic_2lpt(ctypes.byref(p), ctypes.byref(COSMO), seeds, ctypes.byref(st), None, 0, None) == -1
+    assert LIB.cola_ic_2lpt(ctypes.byref(p), ctypes.byref(COSMO), seeds, ctypes.byref(st), fake, 16, None) == -3
+    # unsupported size: 770 = 2 5 7 11
+    p2 = prob(n_part=770, pm_factor=1)
+    assert LIB.cola_ic_2lpt(ctypes.byref(p2), ctypes.byref(COSMO), seeds, ctypes.byref(st), fake, 1 << 40, None) == -2
+    # a_init >= a_final
+    p3 = prob(z_init=0.0)
+    assert LIB.cola_step(ctypes.byref(p3), ctypes.byref(COSMO), 0, 1, ctypes.byref(st), fake, 1 << 40, None) == -1
+    # node range
+    st.node = 2
+    assert LIB.cola_step(ctypes.byref(p), ctypes.byref(COSMO), 0, 3, ctypes.byref(st), fake, 1 << 40, None) == -5
+    assert LIB.cola_step(ctypes.byref(p), ctypes.byref(COSMO), 2, 10, ctypes.byref(st), fake, 1 << 40, None) == -5
+    # bad cosmology
+    bad = cola.make_cosmology(omega_m=0.0)
+    st.node = 0
+    assert LIB.cola_step(ctypes.byref(p), ctypes.byref(bad), 0, 1, ctypes.byref(st), fake, 1 << 40, None) == -1
+    # P(k): a_out outside the current interval, bad n_pk
+    out = ctypes.c_void_p(0x2000)
+    assert LIB.cola_power_spectrum(ctypes.byref(p), ctypes.byref(COSMO), ctypes.byref(st), 0.9, 96, 48,
+                                   out, out, out, fake, 1 << 40, None) == -5
+    assert LIB.cola_power_spectrum(ctypes.byref(p), ctypes.byref(COSMO), ctypes.byref(st), 0.05, 100, 48,
+                                   out, out, out, fake, 1 << 40, None) == -2
+    assert LIB.cola_fft_r2c(14, fake, fake, fake, 1 << 30, None) == -2
+    assert LIB.cola_fft_r2c(16, fake, fake, fake, 8, None) == -3
+
+
+def test_host_schedule_matches_oracle():
+    for n_steps, z_i in ((10, 19.0), (40, 19.0), (40, 39.0)):
+        p = prob(n_steps=n_steps, z_init=z_i)
+        tab = cola.schedule_table(p, COSMO)
+        op = ocola.Problem(256.0, 32, 3, z_i, n_steps)
+        sch = ocola.Schedule(op, ocosmo.Cosmology())
+        assert np.allclose(tab[:, 0], sch.a, rtol=1e-14)
+        assert np.allclose(tab[:, 1], sch.d1, rtol=1e-10)
+        assert np.allclose(tab[:, 2], sch.d2, rtol=1e-10)
+        assert np.allclose(tab[:-1, 3], sch.k_out, rtol=1e-11)
+        assert np.allclose(tab[:-1, 4], sch.k_in, rtol=1e-11)
+        assert np.allclose(tab[:-1, 5], sch.drift, rtol=1e-11)
+
+
+def test_host_linear_power_matches_oracle():
+    c = ocosmo.Cosmology()
+    amp = ocosmo.linear_amplitude(c)
+    for k in (1e-3, 0.01, 0.1, 0.5, 1.0, 3.0):
+        assert cola.linear_power(COSMO, k) == pytest.approx(float(ocosmo.linear_power(k, c, amp)), rel=1e-8)
