@@ -1,0 +1,252 @@
+#!/usr/bin/env python
+"""Throughput of the COLA particle-mesh method on one MI355X.
+
+Workload (the paper's optimum of Sec. 4.5 scaled to one GPU): 256^3 particles, a 768^3 force
+mesh (PM_grid = 3), box 768 h^-1 Mpc, 40 time nodes linear in a from z = 19 to 0, 2LPT Gaussian
+initial conditions with a BBKS spectrum in the MICE-GC cosmology, P(k) on the 768^3 mesh at
+z = 1, 0.5 and 0.  One benchmark step is one whole realization: initial conditions, the 40-node
+COLA run (40 force evaluations) and the three spectra.  Inputs are synthetic and seeded.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Prints one JSON line.  value = particles x 40 nodes x K / wall time of the K timed steps
+(particle-steps/s), timed between two device synchronisations with everything resident in HBM.
+The roofline block reports the kernel with the largest share of the timed region: its
+algorithmic bytes per launch over its mean launch duration, both from HIP events recorded on
+the launch stream during the timed region.  cpu_baseline times the float64 oracle (test
+infrastructure) on one COLA step of the same workload on the host cores.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1509_04685_amd import workloads as W  # noqa: E402
+
+METRIC = "particle-steps/s at 256³ part/768³ mesh; learned vs plain at 1% P(k)"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plain_256_768")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profiler", action="store_true",
+                    help="time without per-kernel events (roofline omitted)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kind, n_g, n_part, n_pk):
+    """Bytes one launch of a kernel kind must move at minimum (one read of its inputs, one
+    write of its outputs), float32 fields, half spectra counted without padding."""
+    G = n_g ** 3
+    C = n_g * n_g * (n_g // 2 + 1)
+    N = n_part ** 3
+    Gk = n_pk ** 3
+    Ck = n_pk * n_pk * (n_pk // 2 + 1)
+    table = {
+        "cic_deposit": 12 * N + 4 * G,          # displacements in, density mesh out
+        "fft_z_r2c": 4 * G + 8 * C,
+        "fft_y_forward": 16 * C,
+        "fft_x_green": 8 * C + 16 * C,          # one spectrum in, two x-transformed outputs
+        "fft_y_split": 8 * C + 16 * C,          # one in, two out
+        "fft_y_inverse": 16 * C,
+        "fft_z_c2r": 8 * C + 4 * G,
+        "gather_kick_drift": 12 * G + 72 * N,   # 3 force meshes; x,p,psi1,psi2 in; x,p out
+        "gather_kick": 12 * G + 60 * N,
+        "pk_deposit": 12 * G + 84 * N + 4 * Gk,
+    }
+    if n_pk == n_g:
+        table["fft_x_forward"] = 16 * C
+    else:
+        table["fft_x_forward"] = 16 * Ck
+    return table.get(kind)
+
+
+def node_index(table, a_out):
+    a = table[:, 0]
+    j = int((a <= a_out * (1 + 1e-12)).sum()) - 1
+    return max(0, min(j, len(a) - 1))
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1509_04685_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kind, launches_per_step):
+    """HBM bytes per launch from the committed counter summary, if it was taken on this source."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, seed):
+    """One COLA step of the workload by the float64 oracle on the host (test infrastructure)."""
+    from scipy import fft as sfft
+    from oracle import cola as ocola, cosmology as ocosmo
+    try:
+        workers = len(os.sched_getaffinity(0))
+    except AttributeError:
+        workers = os.cpu_count() or 1
+    with sfft.set_workers(workers):
+        op = ocola.Problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], cfg["z_init"], cfg["n_steps"])
+        c = ocosmo.Cosmology(**W.COSMOLOGY)
+        sched = ocola.Schedule(op, c)
+        st = ocola.initial_state(op, c, seed)
+        ocola.evaluate_force(st, op)
+        t0 = time.perf_counter()
+        ocola.step(st, op, sched, 1)
+        dt = time.perf_counter() - t0
+    n = cfg["n_part"] ** 3
+    return {
+        "value": n / dt,
+        "unit": "particle-steps/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": (f"one COLA step (kick, drift, PM force on the {op.n_mesh}^3 mesh, kick) of the "
+                   f"{cfg['n_part']}^3 workload from its 2LPT state, float64 numpy/scipy; "
+                   f"{dt:.1f} s; FFTs on {workers} threads, CIC and gather single-threaded"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(an ensemble shards one realization per GPU with no communication).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1509_04685_amd as cola
+
+    cfg = W.CONFIGS[args.workload]
+    box, n_part, pm = cfg["box"], cfg["n_part"], cfg["pm_factor"]
+    n_g = n_part * pm
+    n_steps = cfg["n_steps"]
+    a_outs = cfg.get("a_out", (1.0,))
+    n_pk = n_g
+    n_bins = n_pk // 2
+    seed = cfg["seeds"][0]
+
+    torch.cuda.set_device(0)
+    prob = cola.make_problem(box, n_part, pm, cfg["z_init"], n_steps)
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    table = cola.schedule_table(prob, cosmo)
+    st = cola.ParticleState(prob)
+    ws = cola.Workspace(prob, n_pk=n_pk)
+    outs = [tuple(torch.empty((1, n_bins), dtype=torch.float64, device="cuda") for _ in range(3))
+            for _ in a_outs]
+    plan = [(a, node_index(table, a)) for a in sorted(a_outs)]
+
+    def realization():
+        cola.ic_2lpt(prob, cosmo, [seed], st, ws)
+        for i, (a, j) in enumerate(plan):
+            cola.step(prob, cosmo, st, j, ws)
+            cola.power_spectrum(prob, cosmo, st, a, n_pk, n_bins, ws, out=outs[i])
+        cola.step(prob, cosmo, st, n_steps - 1, ws)
+
+    print(f"[bench] {args.workload}: {n_part}^3 particles, {n_g}^3 mesh, {n_steps} nodes; "
+          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        realization()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if not args.no_profiler:
+        cola.profiler_enable(True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        realization()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    kernels = cola.profiler_read() if not args.no_profiler else {}
+    cola.profiler_enable(False)
+    pk_final = outs[-1][1].cpu().numpy()[0]
+    if not np.all(np.isfinite(pk_final)):
+        raise RuntimeError("non-finite power spectrum")
+
+    ms_per_step = ms_total / args.steps
+    particles = n_part ** 3
+    value = particles * n_steps * args.steps / (ms_total / 1e3)
+    print(f"[bench] {ms_per_step:.1f} ms per realization ({wall:.2f} s wall for {args.steps}); "
+          f"{value:.3e} particle-steps/s", file=sys.stderr, flush=True)
+
+    roofline = None
+    if kernels:
+        ranked = sorted(kernels.items(), key=lambda kv: -kv[1][0])
+        for name, (ms, cnt) in ranked:
+            b = algorithmic_bytes(name, n_g, n_part, n_pk)
+            gbs = (b / (ms / cnt / 1e3) / 1e9) if b else float("nan")
+            print(f"[bench]   {name:20s} {ms / args.steps:9.2f} ms/step  {cnt // args.steps:5d} launches/step"
+                  f"  {ms / cnt:8.3f} ms/launch  {gbs:8.1f} GB/s", file=sys.stderr, flush=True)
+        dom = next((kv for kv in ranked if algorithmic_bytes(kv[0], n_g, n_part, n_pk)), None)
+        if dom:
+            name, (ms, cnt) = dom
+            b = algorithmic_bytes(name, n_g, n_part, n_pk)
+            achieved = b / (ms / cnt / 1e3) / 1e9
+            traffic = read_traffic(name, cnt / args.steps)
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": traffic, "kernel": name, "bytes_per_launch": b,
+                        "ms_per_launch": round(ms / cnt, 4),
+                        "share_of_step": round(ms / ms_total, 4)}
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n_part}^3 particles, {n_g}^3 mesh (PM_grid {pm}), "
+                               f"box {box:g} h^-1 Mpc, {n_steps} nodes linear in a from z={cfg['z_init']:g}, "
+                               f"2LPT ICs, P(k) at a={','.join(f'{a:.3f}' for a in sorted(a_outs))}",
+                   "particles": particles, "mesh": n_g, "nodes": n_steps, "seed": seed,
+                   "step_unit": "one realization (ICs + all nodes + P(k) outputs)"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline: float64 oracle, one step", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(cfg, seed)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

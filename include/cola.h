@@ -166,8 +166,27 @@ int cola_schedule_table(const cola_problem* prob, const cola_cosmology* cosmo, d
 /* Linear power spectrum at a = 1 [(h^-1 Mpc)^3] at wavenumber k [h/Mpc]; -1 on bad input. */
 double cola_linear_power(const cola_cosmology* cosmo, double k);
 
+/* ---- diagnostics ----------------------------------------------------------------------- */
+
+/* Per-kernel timing.  While enabled, each library kernel launch is bracketed by a pair of HIP
+ * events recorded on its stream; cola_profiler_read waits for the recorded events and returns,
+ * per kernel kind, the summed milliseconds and the launch count (arrays of n_kinds, host
+ * memory), then forgets them.  cola_profiler_enable resets the record; not thread-safe across
+ * concurrent streams' readings. */
+int cola_profiler_enable(int on);
+int cola_profiler_num_kinds(void);
+const char* cola_profiler_kind_name(int kind);
+int cola_profiler_read(int32_t n_kinds, double* total_ms, int64_t* launches);
+
+/* Plain device-to-device copy of `bytes` bytes with the library's streaming kernel (16-byte
+ * vectors): the yardstick against which hardware byte counters are scaled. */
+int cola_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Message for a cola_status value (static storage). */
 const char* cola_status_string(int status);
+
+/* Detail of the last COLA_ERR_HIP on this thread: the failing call and the HIP error text. */
+const char* cola_last_error(void);
 
 /* Library version string (static storage). */
 const char* cola_version(void);

@@ -188,5 +188,29 @@ def schedule_table(prob, cosmo):
     return out
 
 
+def profiler_enable(on=True):
+    _lib.check(_lib.lib().cola_profiler_enable(1 if on else 0), "cola_profiler_enable")
+
+
+def profiler_read():
+    """{kernel kind: (total ms, launches)} for the launches since the last read/enable."""
+    n = int(_lib.lib().cola_profiler_num_kinds())
+    ms = np.zeros(n, dtype=np.float64)
+    cnt = np.zeros(n, dtype=np.int64)
+    _lib.check(_lib.lib().cola_profiler_read(n, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+               "cola_profiler_read")
+    return {_lib.lib().cola_profiler_kind_name(i).decode(): (float(ms[i]), int(cnt[i]))
+            for i in range(n) if cnt[i] > 0}
+
+
+def copy(src, dst):
+    """Device copy with the library's streaming kernel (counter yardstick)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    _lib.check(_lib.lib().cola_copy(_ptr(src), _ptr(dst), nbytes, _stream()), "cola_copy")
+
+
 def linear_power(cosmo, k):
     return float(_lib.lib().cola_linear_power(ctypes.byref(cosmo), float(k)))

@@ -20,13 +20,17 @@ STATUS_NAMES = {0: "COLA_OK", -1: "COLA_ERR_INVALID_ARG", -2: "COLA_ERR_UNSUPPOR
 EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_power_spectrum", "cola_cic_density", "cola_cic_workspace_bytes",
            "cola_fft_workspace_bytes", "cola_fft_r2c", "cola_fft_c2r", "cola_schedule_table",
-           "cola_linear_power", "cola_status_string", "cola_version")
+           "cola_linear_power", "cola_status_string", "cola_version", "cola_profiler_enable",
+           "cola_profiler_num_kinds", "cola_profiler_kind_name", "cola_profiler_read", "cola_copy",
+           "cola_last_error")
 
 
 class ColaError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
         msg = _lib.cola_status_string(status).decode() if _lib is not None else "?"
+        if status == -4 and _lib is not None:
+            msg += "; " + _lib.cola_last_error().decode()
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({msg})")
 
 
@@ -52,6 +56,10 @@ class Particles(ctypes.Structure):
 
 
 def _load():
+    # torch bundles its own HIP runtime under the same soname (libamdhip64.so.7).  Whichever is
+    # loaded first serves the whole process, and the streams and device pointers this binding
+    # passes in come from torch's instance, so torch must be loaded before libcola.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libcola.so not built at {LIB_PATH}; run python -m paper_1509_04685_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
@@ -72,6 +80,12 @@ def _load():
         "cola_linear_power": (dbl, [C, dbl]),
         "cola_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "cola_version": (ctypes.c_char_p, []),
+        "cola_profiler_enable": (ctypes.c_int, [ctypes.c_int]),
+        "cola_profiler_num_kinds": (ctypes.c_int, []),
+        "cola_profiler_kind_name": (ctypes.c_char_p, [ctypes.c_int]),
+        "cola_profiler_read": (ctypes.c_int, [i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]),
+        "cola_copy": (ctypes.c_int, [vp, vp, sz, vp]),
+        "cola_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

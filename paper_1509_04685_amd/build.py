@@ -1,6 +1,8 @@
 """Build libcola.so (HIP for gfx950) in place, next to this file.
 
-    python -m paper_1509_04685_amd.build [--jobs N]
+    python paper_1509_04685_amd/build.py [--jobs N]
+
+(run it as a file: importing the package loads the library this script builds)
 
 Every source under csrc/ is compiled with hipcc for gfx950 and linked into one shared library
 that exports the C ABI of include/cola.h.  Packed fp32 instructions are disabled for device code

@@ -2,6 +2,7 @@
 // Every check runs on the host before the first launch, so error returns leave nothing queued.
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -13,10 +14,17 @@ namespace {
 
 constexpr int kMaxMesh = 2048;
 
-#define COLA_TRY(expr)                                  \
-    do {                                                \
-        hipError_t _e = (expr);                         \
-        if (_e != hipSuccess) return COLA_ERR_HIP;      \
+thread_local char g_last_error[512] = "";
+
+int hip_fail(hipError_t e, const char* what) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return COLA_ERR_HIP;
+}
+
+#define COLA_TRY(expr)                                       \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);    \
     } while (0)
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -152,6 +160,8 @@ extern "C" {
 
 const char* cola_version(void) { return "libcola 0.1 (gfx950)"; }
 
+const char* cola_last_error(void) { return g_last_error; }
+
 const char* cola_status_string(int status) {
     switch (status) {
         case COLA_OK: return "ok";
@@ -217,6 +227,7 @@ int cola_ic_2lpt(const cola_problem* prob, const cola_cosmology* cosmo, const ui
     const float inv_n3 = (float)(1.0 / (double)npr);
     ParticlePtrs P = ptrs_of(out);
 
+    (void)hipGetLastError();  // drop a stale error left by other code on this thread
     COLA_TRY(launch_twiddles(w.twp, gp.n, st));
     // white noise -> delta_k in S
     COLA_TRY(ic_noise(out->p[0], np, seeds, p.n_real, npr, st));
@@ -262,6 +273,7 @@ int cola_pm_force(const cola_problem* prob, const cola_particles* in, float* acc
     hipStream_t st = static_cast<hipStream_t>(stream);
     Ws w = carve(ws, L);
     ParticlePtrs P = ptrs_of(in);
+    (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     COLA_TRY(compute_force(*prob, L, w, P, st));
     ForceMeshes f = force_meshes(w);
@@ -291,6 +303,7 @@ int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     LatticeGeom fg = force_geom(p, L);
     ForceMeshes f = force_meshes(w);
 
+    (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st));
     double pending = 0.0;  // kick still owed to the current node (merged with the next kick)
@@ -343,6 +356,7 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     LatticeGeom fg = force_geom(p, L);
     ForceMeshes f = force_meshes(w);
     KickDrift kd{};
+    (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     COLA_TRY(launch_twiddles(w.twk, n_pk, st));
     if (!on_node) {
@@ -399,9 +413,17 @@ int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box,
         return COLA_ERR_INVALID_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
     long cells = (long)n_mesh * n_mesh * n_mesh;
+    (void)hipGetLastError();
     COLA_TRY(launch_fill(delta, cells, 0.0f, st));
     COLA_TRY(cic_deposit_absolute(pos, n, n_mesh, (float)(n_mesh / box), n_mesh, delta, st));
     COLA_TRY(density_finish(delta, n_mesh, n_mesh, (float)((double)cells / (double)n), -1.0f, st));
+    return COLA_OK;
+}
+
+int cola_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst) return COLA_ERR_INVALID_ARG;
+    (void)hipGetLastError();
+    COLA_TRY(launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
     return COLA_OK;
 }
 
@@ -419,6 +441,7 @@ int cola_fft_r2c(int32_t n, const float* in, float* out, void* ws, size_t ws_byt
     Mesh3 g = make_mesh(n);
     float2* spec = static_cast<float2*>(ws);
     float2* tw = reinterpret_cast<float2*>(static_cast<char*>(ws) + align256(g.bytes()));
+    (void)hipGetLastError();
     COLA_TRY(launch_twiddles(tw, n, st));
     COLA_TRY(fft3d_r2c(in, n, 0, spec, 0, g, tw, 1, 1.0f, 0.0f, st));
     COLA_TRY(copy_pad_to_unpad(spec, reinterpret_cast<float2*>(out), g, st));
@@ -433,6 +456,7 @@ int cola_fft_c2r(int32_t n, const float* in, float* out, void* ws, size_t ws_byt
     Mesh3 g = make_mesh(n);
     float2* spec = static_cast<float2*>(ws);
     float2* tw = reinterpret_cast<float2*>(static_cast<char*>(ws) + align256(g.bytes()));
+    (void)hipGetLastError();
     COLA_TRY(launch_twiddles(tw, n, st));
     COLA_TRY(copy_unpad_to_pad(reinterpret_cast<const float2*>(in), spec, g, st));
     COLA_TRY(fft3d_c2r_mult(spec, 0, spec, 0, out, n, 0, g, tw, 1, MUL_SCALE, 0, 0, 1.0f, 1.0f, st));

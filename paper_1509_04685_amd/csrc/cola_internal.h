@@ -13,6 +13,26 @@
 
 namespace cola {
 
+// ------------------------------------------------------------------ profiler (profiler.cpp)
+enum ProfKind {
+    PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
+    PROF_Y_INV, PROF_Z_C2R, PROF_GKD, PROF_GATHER, PROF_IC, PROF_X_INV_MULT, PROF_PK, PROF_COPY,
+    PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_NUM_KINDS
+};
+// Brackets one kernel launch with an event pair when the profiler is enabled.
+class ProfScope {
+  public:
+    ProfScope(int kind, hipStream_t st);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+  private:
+    int kind_;
+    hipStream_t st_;
+    hipEvent_t start_ = nullptr;
+};
+
 // ------------------------------------------------------------------ cosmology (float64, host)
 struct Growth {
     double d1, d2, dd1_da, dd2_da;
@@ -109,6 +129,7 @@ struct KickDrift {
 };
 
 hipError_t launch_fill(float* p, long n, float v, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_fill_d(double* p, long n, double v, hipStream_t st);
 hipError_t cic_deposit_lagrangian(const ParticlePtrs& P, long n_per_real, int n_real,
                                   const LatticeGeom& dep, float* mesh, hipStream_t st);

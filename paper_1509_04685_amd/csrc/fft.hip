@@ -64,10 +64,10 @@ static int pick_tk(int n, int T) {
 }
 
 template <class K>
-static void allow_lds(K kernel, size_t bytes) {
-    if (bytes > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+static hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // ------------------------------------------------------------------ twiddles
@@ -81,6 +81,7 @@ __global__ void k_twiddles(float2* tw, int len) {
 }
 
 hipError_t launch_twiddles(float2* tw, int len, hipStream_t st) {
+    ProfScope ps(PROF_OTHER, st);
     hipLaunchKernelGGL(k_twiddles, dim3((len + 255) / 256), dim3(256), 0, st, tw, len);
     return hipGetLastError();
 }
@@ -422,11 +423,14 @@ static hipError_t run_cols(float2* data, long bstride, const Mesh3& g, bool y_ax
     ColGeom cg = y_axis ? cols_y(g, tk) : cols_x(g, tk);
     size_t lds = (size_t)tk * g.n * sizeof(float2);
     dim3 grid((unsigned)col_blocks(cg, g, y_axis), n_real), block(tk * pl.T);
+    hipError_t err = hipSuccess;
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_cols<decltype(rr)::value, INV>;
-        allow_lds(kern, lds);
+        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
+        ProfScope ps(INV ? (y_axis ? PROF_Y_INV : PROF_OTHER) : (y_axis ? PROF_Y_FWD : PROF_X_FWD), st);
         hipLaunchKernelGGL(kern, grid, block, lds, st, data, bstride, cg, pl, tw);
     });
+    if (err != hipSuccess) return err;
     if (de != hipSuccess) return de;
     return hipGetLastError();
 }
@@ -439,12 +443,15 @@ static hipError_t run_z_r2c(const float* in, long in_row, long in_bstride, float
     long nrows = (long)g.n * g.n;
     size_t lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
     dim3 grid((unsigned)((nrows + lpb - 1) / lpb), n_real), block(lpb * pl.T);
+    hipError_t err = hipSuccess;
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_z_r2c<decltype(rr)::value>;
-        allow_lds(kern, lds);
+        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
+        ProfScope ps(PROF_Z_R2C, st);
         hipLaunchKernelGGL(kern, grid, block, lds, st, in, in_row, in_bstride, out, (long)g.nzp,
                            out_bstride, nrows, pl, tw, pa, pb);
     });
+    if (err != hipSuccess) return err;
     if (de != hipSuccess) return de;
     return hipGetLastError();
 }
@@ -458,12 +465,15 @@ static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long 
     long nrows = (long)g.n * g.n;
     size_t lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
     dim3 grid((unsigned)((nrows + lpb - 1) / lpb), n_real), block(lpb * pl.T);
+    hipError_t err = hipSuccess;
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_z_c2r<decltype(rr)::value, MUL>;
-        allow_lds(kern, lds);
+        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
+        ProfScope ps(PROF_Z_C2R, st);
         hipLaunchKernelGGL(kern, grid, block, lds, st, in, (long)g.nzp, in_bstride, out, out_row,
                            out_bstride, nrows, pl, tw, kf, scale);
     });
+    if (err != hipSuccess) return err;
     if (de != hipSuccess) return de;
     return hipGetLastError();
 }
@@ -492,11 +502,14 @@ hipError_t pm_force_from_spectrum(float2* S, float2* A, float2* B, long bstride,
         ColGeom cg = cols_x(g, tk);
         dim3 grid((unsigned)col_blocks(cg, g, false), n_real), block(tk * pf.T);
         float gscale = 1.0f / ((float)g.n * (float)g.n * (float)g.n);
-        hipError_t de = dispatch_r(pf.R, [&](auto rr) {
+        hipError_t err = hipSuccess;
+    hipError_t de = dispatch_r(pf.R, [&](auto rr) {
             auto kern = k_fft_x_green<decltype(rr)::value>;
-            allow_lds(kern, lds);
+            if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
+            ProfScope ps(PROF_X_GREEN, st);
             hipLaunchKernelGGL(kern, grid, block, lds, st, S, A, B, bstride, cg, pf, pi, tw, kf, gscale);
         });
+    if (err != hipSuccess) return err;
     if (de != hipSuccess) return de;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -504,11 +517,14 @@ hipError_t pm_force_from_spectrum(float2* S, float2* A, float2* B, long bstride,
     {
         ColGeom cg = cols_y(g, tk);
         dim3 grid((unsigned)col_blocks(cg, g, true), n_real), block(tk * pf.T);
-        hipError_t de = dispatch_r(pf.R, [&](auto rr) {
+        hipError_t err = hipSuccess;
+    hipError_t de = dispatch_r(pf.R, [&](auto rr) {
             auto kern = k_fft_y_split<decltype(rr)::value>;
-            allow_lds(kern, lds);
+            if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
+            ProfScope ps(PROF_Y_SPLIT, st);
             hipLaunchKernelGGL(kern, grid, block, lds, st, A, S, bstride, cg, pf, tw, kf);
         });
+    if (err != hipSuccess) return err;
     if (de != hipSuccess) return de;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -532,12 +548,15 @@ hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, l
     size_t lds = (size_t)tk * g.n * sizeof(float2);
     ColGeom cg = cols_x(g, tk);
     dim3 grid((unsigned)col_blocks(cg, g, false), n_real), block(tk * pl.T);
+    hipError_t err = hipSuccess;
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_x_mult<decltype(rr)::value>;
-        allow_lds(kern, lds);
+        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
+        ProfScope ps(PROF_X_INV_MULT, st);
         hipLaunchKernelGGL(kern, grid, block, lds, st, spec, spec_bstride, work, work_bstride, cg, pl, tw,
                            mtype, axis_a, axis_b, kf, scale);
     });
+    if (err != hipSuccess) return err;
     if (de != hipSuccess) return de;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -560,6 +579,7 @@ __global__ void k_copy_rows(const float2* src, long src_row, float2* dst, long d
 hipError_t copy_unpad_to_pad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st) {
     long nrows = (long)g.n * g.n;
     long total = nrows * (g.m + 1);
+    ProfScope ps(PROF_COPY, st);
     hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src,
                        (long)(g.m + 1), dst, (long)g.nzp, nrows, g.m + 1);
     return hipGetLastError();
@@ -568,6 +588,7 @@ hipError_t copy_unpad_to_pad(const float2* src, float2* dst, const Mesh3& g, hip
 hipError_t copy_pad_to_unpad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st) {
     long nrows = (long)g.n * g.n;
     long total = nrows * (g.m + 1);
+    ProfScope ps(PROF_COPY, st);
     hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src,
                        (long)g.nzp, dst, (long)(g.m + 1), nrows, g.m + 1);
     return hipGetLastError();

@@ -41,6 +41,7 @@ __global__ void k_noise(float* w, long n, uint64_t seed) {
 hipError_t ic_noise(float* w, int n_part, const uint64_t* seeds, int n_real, long bstride, hipStream_t st) {
     long n = (long)n_part * n_part * n_part;
     for (int r = 0; r < n_real; ++r) {
+        ProfScope ps(PROF_IC, st);
         hipLaunchKernelGGL(k_noise, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w + r * bstride, n,
                            seeds[r]);
         hipError_t e = hipGetLastError();
@@ -88,6 +89,7 @@ hipError_t ic_scale_spectrum(float2* spec, long bstride, const Mesh3& g, int n_r
     long total = g.total_c();
     long blocks = (total + 255) / 256;
     if (blocks > 65535) blocks = 65535;
+    ProfScope ps(PROF_IC, st);
     hipLaunchKernelGGL(k_ic_scale, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.nzp,
                        g.m + 1, kf, amp, gamma, n_s, norm);
     return hipGetLastError();
@@ -110,6 +112,7 @@ hipError_t lpt2_source(float* s, const float* a, const float* b, const float* c,
                        hipStream_t st) {
     long blocks = (n + 255) / 256;
     if (blocks > 65535L * 4) blocks = 65535L * 4;
+    ProfScope ps(PROF_IC, st);
     hipLaunchKernelGGL(k_lpt2, dim3((unsigned)blocks), dim3(256), 0, st, s, a, b, c, n, mode);
     return hipGetLastError();
 }
@@ -126,6 +129,7 @@ __global__ void k_ic_state(ParticlePtrs P, long n, float d1, float d2) {
 }
 
 hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, hipStream_t st) {
+    ProfScope ps(PROF_IC, st);
     hipLaunchKernelGGL(k_ic_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, n, d1, d2);
     return hipGetLastError();
 }

@@ -78,6 +78,7 @@ hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, 
     long total = (long)g.n * g.n * (g.m + 1);
     long blocks = (total + 255) / 256;
     if (blocks > 2048) blocks = 2048;
+    ProfScope ps(PROF_PK, st);
     hipLaunchKernelGGL(k_pk_bin, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.nzp,
                        n_bins, ksum, psum, cnt, kf);
     return hipGetLastError();
@@ -93,6 +94,7 @@ __global__ void k_pk_finish(double* kmean, double* pk, const double* cnt, long n
 }
 
 hipError_t pk_finish(double* kmean, double* pk, double* cnt, long n, double pnorm, hipStream_t st) {
+    ProfScope ps(PROF_PK, st);
     hipLaunchKernelGGL(k_pk_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, kmean, pk, cnt, n, pnorm);
     return hipGetLastError();
 }

@@ -93,11 +93,37 @@ static unsigned grid_for(long n, int block) {
 }
 
 hipError_t launch_fill(float* p, long n, float v, hipStream_t st) {
+    ProfScope ps(PROF_FILL, st);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 hipError_t launch_fill_d(double* p, long n, double v, hipStream_t st) {
+    ProfScope ps(PROF_FILL, st);
     hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// Plain streaming copy (16-byte vectors plus a byte tail): the yardstick for HBM counters.
+__global__ void k_copy(const uint4* src, uint4* dst, long n16) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+__global__ void k_copy_tail(const unsigned char* src, unsigned char* dst, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+    long n16 = (long)(bytes / 16);
+    long tail = (long)(bytes - (size_t)n16 * 16);
+    ProfScope ps(PROF_COPY, st);
+    if (n16 > 0)
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(n16, 256)), dim3(256), 0, st, static_cast<const uint4*>(src),
+                           static_cast<uint4*>(dst), n16);
+    if (tail > 0)
+        hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, st,
+                           static_cast<const unsigned char*>(src) + n16 * 16,
+                           static_cast<unsigned char*>(dst) + n16 * 16, tail);
     return hipGetLastError();
 }
 
@@ -118,6 +144,7 @@ __global__ void k_deposit_lagr(ParticlePtrs P, long npr, int n_real, LatticeGeom
 hipError_t cic_deposit_lagrangian(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg,
                                   float* mesh, hipStream_t st) {
     long n = npr * n_real;
+    ProfScope ps(PROF_DEPOSIT, st);
     hipLaunchKernelGGL(k_deposit_lagr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
                        dg, mesh);
     return hipGetLastError();
@@ -162,6 +189,7 @@ hipError_t cic_deposit_drifted(const ParticlePtrs& P, long npr, int n_real, cons
                                const float* fx, const float* fy, const float* fz, const KickDrift& kd,
                                const LatticeGeom& dg, float* mesh, hipStream_t st) {
     long n = npr * n_real;
+    ProfScope ps(PROF_PK_DEPOSIT, st);
     hipLaunchKernelGGL(k_deposit_drifted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
                        fg, fx, fy, fz, kd, dg, mesh);
     return hipGetLastError();
@@ -187,6 +215,7 @@ __global__ void k_deposit_abs(const float* px, const float* py, const float* pz,
 
 hipError_t cic_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, long row,
                                 float* mesh, hipStream_t st) {
+    ProfScope ps(PROF_DEPOSIT, st);
     hipLaunchKernelGGL(k_deposit_abs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos[0], pos[1],
                        pos[2], n, n_mesh, inv_h, row, mesh);
     return hipGetLastError();
@@ -204,6 +233,7 @@ __global__ void k_density_finish(float* mesh, long row, int n, float scale, floa
 
 hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float offset, hipStream_t st) {
     long total = (long)n_mesh * n_mesh * n_mesh;
+    ProfScope ps(PROF_OTHER, st);
     hipLaunchKernelGGL(k_density_finish, dim3(grid_for(total, 256)), dim3(256), 0, st, mesh, row, n_mesh,
                        scale, offset);
     return hipGetLastError();
@@ -242,6 +272,7 @@ hipError_t gather_kick_drift(const ParticlePtrs& P, long npr, int n_real, const 
                              const float* fx, const float* fy, const float* fz, const KickDrift& kd,
                              hipStream_t st) {
     long n = npr * n_real;
+    ProfScope ps((kd.drift != 0.0f || kd.dd1 != 0.0f) ? PROF_GKD : PROF_KICK, st);
     hipLaunchKernelGGL(k_gather_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr,
                        n_real, fg, fx, fy, fz, kd);
     return hipGetLastError();
@@ -268,6 +299,7 @@ __global__ void k_gather_force(ParticlePtrs P, long npr, int n_real, LatticeGeom
 hipError_t gather_force(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
                         const float* fy, const float* fz, float* const acc[3], hipStream_t st) {
     long n = npr * n_real;
+    ProfScope ps(PROF_GATHER, st);
     hipLaunchKernelGGL(k_gather_force, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
                        fg, fx, fy, fz, acc[0], acc[1], acc[2]);
     return hipGetLastError();

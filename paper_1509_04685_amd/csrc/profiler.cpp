@@ -1,0 +1,119 @@
+// Per-kernel HIP-event timing for libcola launches (a diagnostic, off by default).
+//
+// While enabled, every launcher brackets its kernel with an event pair recorded on the launch
+// stream; cola_profiler_read synchronises the recorded events and reports total milliseconds
+// and launch counts per kernel kind.  Events come from a pool that is reused across reads.
+
+#include <mutex>
+#include <vector>
+
+#include "cola_internal.h"
+
+namespace cola {
+
+namespace {
+
+const char* const kKindNames[PROF_NUM_KINDS] = {
+    "fill", "cic_deposit", "fft_z_r2c", "fft_y_forward", "fft_x_forward", "fft_x_green",
+    "fft_y_split", "fft_y_inverse", "fft_z_c2r", "gather_kick_drift", "gather_force",
+    "ic_kernels", "fft_x_inverse_mult", "pk_bin", "copy", "other", "gather_kick", "pk_deposit"};
+
+struct Record {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<Record> records;
+    int depth = 0;  // nested scopes record only the outermost launch
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+Profiler& prof() {
+    static Profiler p;
+    return p;
+}
+
+}  // namespace
+
+ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st) {
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!p.enabled || p.depth++ > 0) return;
+    start_ = p.get();
+    if (start_) (void)hipEventRecord(start_, st_);
+}
+
+ProfScope::~ProfScope() {
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!p.enabled) return;
+    if (--p.depth > 0 || !start_) return;
+    hipEvent_t stop = p.get();
+    if (!stop) return;
+    (void)hipEventRecord(stop, st_);
+    p.records.push_back({kind_, start_, stop});
+}
+
+}  // namespace cola
+
+using namespace cola;
+
+extern "C" {
+
+int cola_profiler_enable(int on) {
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    for (auto& r : p.records) {
+        p.pool.push_back(r.start);
+        p.pool.push_back(r.stop);
+    }
+    p.records.clear();
+    p.depth = 0;
+    p.enabled = on != 0;
+    return COLA_OK;
+}
+
+int cola_profiler_num_kinds(void) { return PROF_NUM_KINDS; }
+
+const char* cola_profiler_kind_name(int kind) {
+    if (kind < 0 || kind >= PROF_NUM_KINDS) return "";
+    return kKindNames[kind];
+}
+
+int cola_profiler_read(int32_t n_kinds, double* total_ms, int64_t* launches) {
+    if (!total_ms || !launches || n_kinds < 1) return COLA_ERR_INVALID_ARG;
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    for (int k = 0; k < n_kinds; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto& r : p.records) {
+        if (hipEventSynchronize(r.stop) != hipSuccess) return COLA_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return COLA_ERR_HIP;
+        if (r.kind < n_kinds) {
+            total_ms[r.kind] += ms;
+            launches[r.kind] += 1;
+        }
+        p.pool.push_back(r.start);
+        p.pool.push_back(r.stop);
+    }
+    p.records.clear();
+    return COLA_OK;
+}
+
+}  // extern "C"
