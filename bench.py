@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plain_256_768")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
     ap.add_argument("--no-profiler", action="store_true",
                     help="time without per-kernel events (roofline omitted)")
     return ap.parse_args()
@@ -175,6 +176,11 @@ def main():
 
     print(f"[bench] {args.workload}: {n_part}^3 particles, {n_g}^3 mesh, {n_steps} nodes; "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    if not args.no_autotune:
+        t_at = time.perf_counter()
+        report = cola.autotune(prob, ws, n_pk=n_pk, state=st)
+        print(f"[bench] FFT autotune ({time.perf_counter() - t_at:.1f} s):\n" + report.rstrip(),
+              file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         realization()
     torch.cuda.synchronize()

@@ -140,6 +140,15 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo,
                         double* k_mean, double* pk, double* n_modes,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* FFT autotuner.  Times every admissible kernel shape (values per thread, lines or columns per
+ * block) of each FFT pass at the problem's force-mesh, lattice and P(k) sizes, on `stream`, and
+ * keeps the fastest for every later call in this process (until then a fixed heuristic is
+ * used).  Uses ws as scratch: its contents, including a cached force mesh, are destroyed --
+ * call it before cola_ic_2lpt or set force_node = -1 afterwards.  Synchronises the stream.
+ * report (host, may be NULL): one line per pass with the chosen shape and its time. */
+int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_bytes, void* stream,
+                  char* report, size_t report_len);
+
 /* ---- component entry points (the stages above, exposed for parity checks) ------------- */
 
 /* CIC density contrast of arbitrary positions: pos[d] device arrays of n floats (absolute

@@ -188,6 +188,16 @@ def schedule_table(prob, cosmo):
     return out
 
 
+def autotune(prob, ws, n_pk=0, state=None):
+    """Pick the fastest FFT kernel shapes for this problem's sizes (destroys ws contents)."""
+    buf = ctypes.create_string_buffer(4096)
+    _lib.check(_lib.lib().cola_autotune(ctypes.byref(prob), int(n_pk), ws.ptr, ws.nbytes, _stream(), buf,
+                                        len(buf)), "cola_autotune")
+    if state is not None:
+        state.invalidate_force()
+    return buf.value.decode()
+
+
 def profiler_enable(on=True):
     _lib.check(_lib.lib().cola_profiler_enable(1 if on else 0), "cola_profiler_enable")
 

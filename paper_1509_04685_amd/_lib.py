@@ -22,7 +22,7 @@ EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_fft_workspace_bytes", "cola_fft_r2c", "cola_fft_c2r", "cola_schedule_table",
            "cola_linear_power", "cola_status_string", "cola_version", "cola_profiler_enable",
            "cola_profiler_num_kinds", "cola_profiler_kind_name", "cola_profiler_read", "cola_copy",
-           "cola_last_error")
+           "cola_last_error", "cola_autotune")
 
 
 class ColaError(RuntimeError):
@@ -86,6 +86,7 @@ def _load():
         "cola_profiler_read": (ctypes.c_int, [i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]),
         "cola_copy": (ctypes.c_int, [vp, vp, sz, vp]),
         "cola_last_error": (ctypes.c_char_p, []),
+        "cola_autotune": (ctypes.c_int, [P, i32, vp, sz, vp, ctypes.c_char_p, sz]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

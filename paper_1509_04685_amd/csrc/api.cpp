@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "cola_internal.h"
@@ -12,7 +13,7 @@ using namespace cola;
 
 namespace {
 
-constexpr int kMaxMesh = 2048;
+constexpr int kMaxMesh = 1536;  // keeps per-realization mesh offsets below 2^31
 
 thread_local char g_last_error[512] = "";
 
@@ -35,7 +36,9 @@ struct Layout {
     Mesh3 gk;  // P(k) mesh (n = 0 when absent)
     long cstride = 0;  // float2 per realization in S, A, B
     long kstride = 0;  // float2 per realization in K
-    size_t off_s = 0, off_a = 0, off_b = 0, off_k = 0, off_twg = 0, off_twp = 0, off_twk = 0;
+    TileGeom tg;  // force-mesh tiles of the deposit
+    TileGeom tk;  // P(k)-mesh tiles
+    size_t off_s = 0, off_a = 0, off_b = 0, off_k = 0, off_twg = 0, off_twp = 0, off_twk = 0, off_sort = 0;
     size_t total = 0;
 };
 
@@ -55,6 +58,14 @@ Layout layout_of(const cola_problem& p, int n_pk) {
         L.off_k = off;
         off += align256((size_t)L.kstride * sizeof(float2) * p.n_real);
     }
+    const long npr = (long)p.n_part * p.n_part * p.n_part;
+    L.tg = make_tiles(L.g.n);
+    size_t sb = sort_bytes(npr, L.tg, p.n_real);
+    if (n_pk > 0) {
+        L.tk = make_tiles(n_pk);
+        sb = std::max(sb, sort_bytes(npr, L.tk, p.n_real));
+    }
+    L.off_sort = off; off += align256(sb);
     L.off_twg = off; off += align256((size_t)L.g.n * sizeof(float2));
     L.off_twp = off; off += align256((size_t)L.gp.n * sizeof(float2));
     L.off_twk = off; off += align256((size_t)(n_pk > 0 ? n_pk : 1) * sizeof(float2));
@@ -103,6 +114,7 @@ ParticlePtrs ptrs_of(const cola_particles* P) {
 
 struct Ws {
     float2 *S, *A, *B, *K, *twg, *twp, *twk;
+    void* sort;
 };
 
 Ws carve(void* ws, const Layout& L) {
@@ -115,6 +127,7 @@ Ws carve(void* ws, const Layout& L) {
     w.twg = reinterpret_cast<float2*>(b + L.off_twg);
     w.twp = reinterpret_cast<float2*>(b + L.off_twp);
     w.twk = reinterpret_cast<float2*>(b + L.off_twk);
+    w.sort = b + L.off_sort;
     return w;
 }
 
@@ -134,14 +147,15 @@ LatticeGeom force_geom(const cola_problem& p, const Layout& L) {
 hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, const ParticlePtrs& P,
                          hipStream_t st) {
     const long npr = (long)p.n_part * p.n_part * p.n_part;
-    hipError_t e = launch_fill(reinterpret_cast<float*>(w.S), 2L * L.cstride * p.n_real, 0.0f, st);
-    if (e != hipSuccess) return e;
     LatticeGeom fg = force_geom(p, L);
-    e = cic_deposit_lagrangian(P, npr, p.n_real, fg, reinterpret_cast<float*>(w.S), st);
+    const double cells = (double)L.g.n * L.g.n * L.g.n;
+    SortBufs sb = carve_sort(w.sort, npr, L.tg, p.n_real);
+    KickDrift none{};
+    hipError_t e = sorted_deposit(P, npr, p.n_real, fg, false, fg, nullptr, nullptr, nullptr, none, L.tg, sb,
+                                  reinterpret_cast<float*>(w.S), (float)(cells / (double)npr), -1.0f, st);
     if (e != hipSuccess) return e;
-    double cells = (double)L.g.n * L.g.n * L.g.n;
     e = fft_zy_forward(reinterpret_cast<const float*>(w.S), 2L * L.g.nzp, 2L * L.cstride, w.S, L.cstride, L.g,
-                       w.twg, p.n_real, (float)(cells / (double)npr), -1.0f, st);
+                       w.twg, p.n_real, 1.0f, 0.0f, st);
     if (e != hipSuccess) return e;
     return pm_force_from_spectrum(w.S, w.A, w.B, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real, st);
 }
@@ -167,7 +181,7 @@ const char* cola_status_string(int status) {
         case COLA_OK: return "ok";
         case COLA_ERR_INVALID_ARG: return "invalid argument (NULL pointer or out-of-range parameter)";
         case COLA_ERR_UNSUPPORTED_SIZE:
-            return "unsupported mesh size (must be even, <= 2048, with prime factors 2 and 3 only)";
+            return "unsupported mesh size (must be even, <= 1536, with prime factors 2 and 3 only)";
         case COLA_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
         case COLA_ERR_HIP: return "HIP runtime error";
         case COLA_ERR_STATE: return "particle state does not fit the call (node range)";
@@ -374,7 +388,6 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
         kd.dd2 = (float)(go.d2 - sc.d2[j]);
     }
     const Mesh3& gk = L.gk;
-    COLA_TRY(launch_fill(reinterpret_cast<float*>(w.K), 2L * L.kstride * p.n_real, 0.0f, st));
     LatticeGeom dg;
     dg.n_part = p.n_part;
     dg.n_mesh = n_pk;
@@ -382,10 +395,12 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     dg.qoff = (float)(0.5 * (double)n_pk / (double)L.g.n);
     dg.row = 2L * gk.nzp;
     dg.mesh_bstride = 2L * L.kstride;
-    COLA_TRY(cic_deposit_drifted(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, dg, reinterpret_cast<float*>(w.K), st));
     double cells = (double)n_pk * n_pk * n_pk;
+    SortBufs sb = carve_sort(w.sort, npr, L.tk, p.n_real);
+    COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, !on_node, fg, f.fx, f.fy, f.fz, kd, L.tk, sb,
+                            reinterpret_cast<float*>(w.K), (float)(cells / (double)npr), -1.0f, st));
     COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K, L.kstride, gk, w.twk,
-                       p.n_real, (float)(cells / (double)npr), -1.0f, st));
+                       p.n_real, 1.0f, 0.0f, st));
     const long nb = (long)n_bins * p.n_real;
     COLA_TRY(launch_fill_d(k_mean, nb, 0.0, st));
     COLA_TRY(launch_fill_d(pk, nb, 0.0, st));
@@ -417,6 +432,35 @@ int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box,
     COLA_TRY(launch_fill(delta, cells, 0.0f, st));
     COLA_TRY(cic_deposit_absolute(pos, n, n_mesh, (float)(n_mesh / box), n_mesh, delta, st));
     COLA_TRY(density_finish(delta, n_mesh, n_mesh, (float)((double)cells / (double)n), -1.0f, st));
+    return COLA_OK;
+}
+
+int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_bytes, void* stream, char* report,
+                  size_t report_len) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if (!ws) return COLA_ERR_INVALID_ARG;
+    if (n_pk < 0 || (n_pk > 0 && (!fft_size_ok(n_pk) || n_pk > kMaxMesh))) return COLA_ERR_UNSUPPORTED_SIZE;
+    Layout L = layout_of(*prob, n_pk);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    std::string rep;
+    (void)hipGetLastError();
+    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
+    COLA_TRY(autotune_fft(L.g.n, w.S, w.A, w.B, w.twg, st, &rep));
+    if (L.gp.n != L.g.n) {
+        COLA_TRY(launch_twiddles(w.twp, L.gp.n, st));
+        COLA_TRY(autotune_fft(L.gp.n, w.S, w.A, w.B, w.twp, st, &rep));
+    }
+    if (n_pk > 0 && n_pk != L.g.n && n_pk != L.gp.n) {
+        COLA_TRY(launch_twiddles(w.twk, n_pk, st));
+        if (n_pk <= L.g.n) COLA_TRY(autotune_fft(n_pk, w.S, w.A, w.B, w.twk, st, &rep));
+        else COLA_TRY(autotune_fft(n_pk, w.K, w.K, w.K, w.twk, st, &rep));
+    }
+    if (report && report_len > 0) {
+        std::snprintf(report, report_len, "%s", rep.c_str());
+    }
     return COLA_OK;
 }
 

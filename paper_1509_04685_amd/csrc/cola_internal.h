@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "../../include/cola.h"
@@ -17,7 +18,7 @@ namespace cola {
 enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
     PROF_Y_INV, PROF_Z_C2R, PROF_GKD, PROF_GATHER, PROF_IC, PROF_X_INV_MULT, PROF_PK, PROF_COPY,
-    PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_NUM_KINDS
+    PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_NUM_KINDS
 };
 // Brackets one kernel launch with an event pair when the profiler is enabled.
 class ProfScope {
@@ -68,6 +69,11 @@ struct Mesh3 {
 Mesh3 make_mesh(int n);
 bool fft_size_ok(int n);  // even, >= 4, factors 2 and 3 only
 FftPlan make_plan(int n, bool reverse = false);
+FftPlan make_plan_r(int n, int R, bool reverse);
+// Times the admissible shapes of every FFT kernel at mesh size n on scratch spectra S, A, B
+// (overwritten) and keeps the fastest for the process.
+hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw, hipStream_t st,
+                        std::string* report);
 
 // ------------------------------------------------------------------ launchers (fft.hip)
 hipError_t launch_twiddles(float2* tw, int len, hipStream_t st);
@@ -148,6 +154,35 @@ hipError_t gather_kick_drift(const ParticlePtrs& P, long n_per_real, int n_real,
 hipError_t gather_force(const ParticlePtrs& P, long n_per_real, int n_real, const LatticeGeom& fgeom,
                         const float* fx, const float* fy, const float* fz, float* const acc[3],
                         hipStream_t st);
+
+// ------------------------------------------------------------------ tiled deposit (deposit_sorted.hip)
+struct TileGeom {
+    int n = 0;             // mesh cells per side
+    int tx = 1, ty = 1, tz = 1;
+    int ntx = 1, nty = 1, ntz = 1;
+    long ntiles = 0;
+    long nkeys = 0;        // ntiles * 8 categories
+};
+struct SortBufs {
+    uint32_t* keys = nullptr;     // per particle
+    float4* recs = nullptr;       // per particle: (local cell bits, fx, fy, fz)
+    float4* sorted = nullptr;     // records in key order
+    uint32_t* count = nullptr;    // per key (per realization stride kstride)
+    uint32_t* start = nullptr;    // exclusive prefix, nkeys + 1 entries
+    uint32_t* cursor = nullptr;
+    uint32_t* block_sums = nullptr;
+    long kstride = 0;
+    int nblocks = 0;
+};
+TileGeom make_tiles(int n);
+size_t sort_bytes(long n_particles_per_real, const TileGeom& tg, int n_real);
+SortBufs carve_sort(void* base, long npr, const TileGeom& tg, int n_real);
+// CIC deposit of every particle (drifted on the fly when `drift`, with the force gathered from
+// fgeom's meshes) onto a mesh of dg's geometry, written as delta = rho * scale + offset.
+hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg, bool drift,
+                          const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
+                          const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
+                          float scale, float offset, hipStream_t st);
 
 // ------------------------------------------------------------------ launchers (ic_kernels.hip)
 hipError_t ic_noise(float* w, int n_part, const uint64_t* seeds_host, int n_real, long bstride,

@@ -1,0 +1,393 @@
+// Cloud-in-cell mass assignment by tile ownership (Sec. 2.2: CIC onto the force mesh; Sec. 2.5:
+// CIC onto the P(k) mesh), without atomics to HBM and without clearing the mesh first.
+//
+// The mesh is cut into tiles of TX x TY x TZ cells.  Each particle gets a key
+//   key = tile(home cell) * 8 + category,   category = 4 [x on the tile's upper face]
+//                                                      + 2 [y on it] + [z on it],
+// where the home cell is the lower CIC corner.  A particle's eight corners land in its own tile
+// and, only along axes where its category bit is set, in the next tile up.  After a counting sort
+// by key, the block that owns tile M reads its own bin and, from each of the seven tiles M - d
+// (d in {0,1}^3, d != 0), just the categories that contain d -- the particles whose corners reach
+// into M.  It accumulates the corners that fall inside M in LDS and writes every cell of M once,
+// already converted to delta = rho * scale + offset.
+//
+// Passes: bin (key + cell record per particle, wave-aggregated counts), exclusive scan of the
+// counts, scatter of the records into key order, tile accumulation.  Records keep the CIC
+// fractions exactly as computed from the lattice index and displacement.
+
+#include "cola_internal.h"
+
+namespace cola {
+
+TileGeom make_tiles(int n) {
+    TileGeom t;
+    t.n = n;
+    t.tz = 1;
+    for (int c : {64, 32, 16, 8, 4, 2})
+        if (n % c == 0) { t.tz = c; break; }
+    t.tx = 1;
+    for (int c : {8, 4, 2})
+        if (n % c == 0) { t.tx = c; break; }
+    t.ty = t.tx;
+    t.ntx = n / t.tx;
+    t.nty = n / t.ty;
+    t.ntz = n / t.tz;
+    t.ntiles = (long)t.ntx * t.nty * t.ntz;
+    t.nkeys = t.ntiles * 8;
+    return t;
+}
+
+namespace {
+
+struct CellC {
+    int m;
+    float f;
+};
+
+__device__ __forceinline__ CellC cell_c(int i, float x, int n_part, int n_mesh, float inv_h, float qoff) {
+    long a = (long)i * n_mesh;
+    int q = (int)(a / n_part);
+    int rem = (int)(a - (long)q * n_part);
+    float w = (float)rem / (float)n_part + qoff + x * inv_h;
+    float fl = floorf(w);
+    CellC c;
+    c.f = w - fl;
+    int m = (q + (int)fl) % n_mesh;
+    m = m < 0 ? m + n_mesh : m;
+    c.m = min(max(m, 0), n_mesh - 1);
+    return c;
+}
+
+__device__ __forceinline__ void lagr_idx(long p, int n_part, int& i, int& j, int& l) {
+    long np2 = (long)n_part * n_part;
+    i = (int)(p / np2);
+    long r = p - (long)i * np2;
+    j = (int)(r / n_part);
+    l = (int)(r - (long)j * n_part);
+}
+
+__device__ __forceinline__ int wrapn(int m, int n) { return m + 1 == n ? 0 : m + 1; }
+
+// CIC gather of three meshes (force at the particle, for positions drifted between nodes).
+__device__ __forceinline__ void gather3c(const float* fx, const float* fy, const float* fz, long row, int n,
+                                         const CellC* c, float g[3]) {
+    const int xs[2] = {c[0].m, wrapn(c[0].m, n)}, ys[2] = {c[1].m, wrapn(c[1].m, n)},
+              zs[2] = {c[2].m, wrapn(c[2].m, n)};
+    const float wx[2] = {1.0f - c[0].f, c[0].f}, wy[2] = {1.0f - c[1].f, c[1].f}, wz[2] = {1.0f - c[2].f, c[2].f};
+    g[0] = g[1] = g[2] = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            long r = ((long)xs[a] * n + ys[b]) * row;
+            float wab = wx[a] * wy[b];
+            float w0 = wab * wz[0], w1 = wab * wz[1];
+            g[0] += w0 * fx[r + zs[0]] + w1 * fx[r + zs[1]];
+            g[1] += w0 * fy[r + zs[0]] + w1 * fy[r + zs[1]];
+            g[2] += w0 * fz[r + zs[0]] + w1 * fz[r + zs[1]];
+        }
+}
+
+// Wave-aggregated atomic increment: lanes sharing a key get consecutive slots from one atomic.
+// Returns the old counter value plus the lane's rank among the lanes with its key.
+__device__ __forceinline__ uint32_t wave_increment(uint32_t* counter_base, uint32_t key, bool valid) {
+    const int lane = __lane_id();
+    const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    bool pending = valid;
+    uint32_t slot = 0;
+    while (true) {
+        unsigned long long pm = __ballot(pending);
+        if (pm == 0ull) break;
+        int leader = __ffsll((long long)pm) - 1;
+        uint32_t lkey = __shfl(key, leader);
+        bool mine = pending && key == lkey;
+        unsigned long long mm = __ballot(mine);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counter_base[lkey], (uint32_t)__popcll(mm));
+        base = __shfl(base, leader);
+        if (mine) {
+            slot = base + (uint32_t)__popcll(mm & lt);
+            pending = false;
+        }
+    }
+    return slot;
+}
+
+template <bool DRIFT>
+__global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg, LatticeGeom fg, const float* fx,
+                          const float* fy, const float* fz, KickDrift kd, SortBufs sb) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const bool valid = p < npr;
+    const long gid = (long)r * npr + p;
+    uint32_t key = 0;
+    float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+        int idx[3];
+        lagr_idx(p, dg.n_part, idx[0], idx[1], idx[2]);
+        float x[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];
+        if (DRIFT) {
+            CellC c[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c[d] = cell_c(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
+            float g[3];
+            const long mo = (long)r * fg.mesh_bstride;
+            gather3c(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c, g);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
+                float ph = P.p[d][gid] + kd.kick * (g[d] - kd.d1 * s1 - kd.d2m * s2);
+                x[d] = x[d] + ph * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
+            }
+        }
+        CellC c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) c[d] = cell_c(idx[d], x[d], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
+        const int lx = c[0].m % tg.tx, ly = c[1].m % tg.ty, lz = c[2].m % tg.tz;
+        const long tile = ((long)(c[0].m / tg.tx) * tg.nty + c[1].m / tg.ty) * tg.ntz + c[2].m / tg.tz;
+        const int cat = ((lx == tg.tx - 1) ? 4 : 0) | ((ly == tg.ty - 1) ? 2 : 0) | ((lz == tg.tz - 1) ? 1 : 0);
+        key = (uint32_t)(tile * 8 + cat);
+        const int local = (lx * tg.ty + ly) * tg.tz + lz;
+        rec = make_float4(__int_as_float(local), c[0].f, c[1].f, c[2].f);
+        sb.keys[gid] = key;
+        sb.recs[gid] = rec;
+    }
+    (void)wave_increment(sb.count + (long)r * sb.kstride, key, valid);
+}
+
+// Exclusive scan, phase 1: each block scans 1024 counts (4 per thread) and stores its total.
+__global__ void k_scan_blocks(const uint32_t* count, uint32_t* start, uint32_t* block_sums, long nkeys,
+                              long kstride, int nblocks) {
+    __shared__ uint32_t sh[256];
+    const int r = blockIdx.y;
+    count += (long)r * kstride;
+    start += (long)r * kstride;
+    block_sums += (long)r * nblocks;
+    const long base = (long)blockIdx.x * 1024 + threadIdx.x * 4;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < nkeys) ? count[base + i] : 0u;
+        s += v[i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // Hillis-Steele inclusive scan of thread sums
+        uint32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = sh[threadIdx.x] - s;  // exclusive prefix of this thread
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (base + i < nkeys) start[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 255) block_sums[blockIdx.x] = sh[255];
+}
+
+// Phase 2: one block scans the block totals (up to 8192) in place, exclusive.
+__global__ void k_scan_totals(uint32_t* block_sums, int nblocks) {
+    __shared__ uint32_t sh[1024];
+    const int r = blockIdx.y;
+    block_sums += (long)r * nblocks;
+    const int per = (nblocks + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < nblocks) s += block_sums[b0 + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = sh[threadIdx.x] - s;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < nblocks) {
+            uint32_t v = block_sums[b0 + i];
+            block_sums[b0 + i] = run;
+            run += v;
+        }
+}
+
+// Phase 3: add the block offsets; cursor = start; start[nkeys] = total.
+__global__ void k_scan_finish(uint32_t* start, uint32_t* cursor, const uint32_t* block_sums,
+                              long nkeys, long kstride, int nblocks, uint32_t total) {
+    const int r = blockIdx.y;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    start += (long)r * kstride;
+    cursor += (long)r * kstride;
+    block_sums += (long)r * nblocks;
+    if (i < nkeys) {
+        uint32_t v = start[i] + block_sums[i / 1024];
+        start[i] = v;
+        cursor[i] = v;
+    } else if (i == nkeys) {
+        start[i] = total;
+    }
+}
+
+__global__ void k_dep_scatter(long npr, SortBufs sb) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const bool valid = p < npr;
+    const long gid = (long)r * npr + p;
+    uint32_t key = valid ? sb.keys[gid] : 0u;
+    float4 rec = valid ? sb.recs[gid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t slot = wave_increment(sb.cursor + (long)r * sb.kstride, key, valid);
+    if (valid) sb.sorted[(long)r * npr + slot] = rec;
+}
+
+// The 14 (offset d, category range) pairs a tile pulls: from tile M - d, the categories c with
+// (c & d) == d, grouped into contiguous runs [c_lo, c_hi).
+struct Pull {
+    int d, c_lo, c_hi;
+};
+__constant__ Pull kPulls[14] = {{0, 0, 8}, {4, 4, 8}, {2, 2, 4}, {2, 6, 8}, {1, 1, 2}, {1, 3, 4}, {1, 5, 6},
+                                {1, 7, 8}, {6, 6, 8}, {5, 5, 6}, {5, 7, 8}, {3, 3, 4}, {3, 7, 8}, {7, 7, 8}};
+
+// One block per tile: pull the records whose corners reach into the tile, accumulate in LDS,
+// write every cell of the tile once as delta = rho * scale + offset.  The 14 record ranges are
+// fetched in parallel first, then all threads sweep their concatenation.
+__global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long npr, float* mesh, long row,
+                                                  long mesh_bstride, float scale, float offset) {
+    extern __shared__ float acc[];
+    __shared__ uint32_t rb[14], rlen[15];
+    const int r = blockIdx.y;
+    const long tile = blockIdx.x;
+    const int ncell = tg.tx * tg.ty * tg.tz;
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = 0.0f;
+    const int tzi = (int)(tile % tg.ntz);
+    const int tyi = (int)((tile / tg.ntz) % tg.nty);
+    const int txi = (int)(tile / ((long)tg.ntz * tg.nty));
+    const uint32_t* start = sb.start + (long)r * sb.kstride;
+    const float4* recs = sb.sorted + (long)r * npr;
+    if (threadIdx.x < 14) {
+        const Pull pl = kPulls[threadIdx.x];
+        const int dx = (pl.d >> 2) & 1, dy = (pl.d >> 1) & 1, dz = pl.d & 1;
+        const int sx = txi - dx < 0 ? tg.ntx - 1 : txi - dx;
+        const int sy = tyi - dy < 0 ? tg.nty - 1 : tyi - dy;
+        const int sz = tzi - dz < 0 ? tg.ntz - 1 : tzi - dz;
+        const long src = ((long)sx * tg.nty + sy) * tg.ntz + sz;
+        const uint32_t b = start[src * 8 + pl.c_lo], e = start[src * 8 + pl.c_hi];
+        rb[threadIdx.x] = b;
+        rlen[threadIdx.x] = e - b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive prefix of the range lengths, total in rlen[14]
+        uint32_t run = 0;
+        for (int q = 0; q < 14; ++q) {
+            uint32_t l = rlen[q];
+            rlen[q] = run;
+            run += l;
+        }
+        rlen[14] = run;
+    }
+    __syncthreads();
+    const uint32_t total = rlen[14];
+    int q = 0;
+    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) {
+        while (q < 13 && i >= rlen[q + 1]) ++q;  // i only grows, so q only moves forward
+        const int d = kPulls[q].d;
+        const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+        const float4 rec = recs[rb[q] + (i - rlen[q])];
+        const int local = __float_as_int(rec.x);
+        const int lz = local % tg.tz, ly = (local / tg.tz) % tg.ty, lx = local / (tg.tz * tg.ty);
+        const int hx = lx - dx * tg.tx, hy = ly - dy * tg.ty, hz = lz - dz * tg.tz;
+        const float wx[2] = {1.0f - rec.y, rec.y}, wy[2] = {1.0f - rec.z, rec.z}, wz[2] = {1.0f - rec.w, rec.w};
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+            const int ux = hx + cx;
+            if (ux < 0 || ux >= tg.tx) continue;
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+                const int uy = hy + cy;
+                if (uy < 0 || uy >= tg.ty) continue;
+#pragma unroll
+                for (int cz = 0; cz < 2; ++cz) {
+                    const int uz = hz + cz;
+                    if (uz < 0 || uz >= tg.tz) continue;
+                    atomicAdd(&acc[(ux * tg.ty + uy) * tg.tz + uz], wx[cx] * wy[cy] * wz[cz]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    float* out = mesh + (long)r * mesh_bstride;
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+        const int uz = i % tg.tz, uy = (i / tg.tz) % tg.ty, ux = i / (tg.tz * tg.ty);
+        const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
+        out[(gx * tg.n + gy) * row + gz] = fmaf(acc[i], scale, offset);
+    }
+}
+
+}  // namespace
+
+size_t sort_bytes(long n_particles_per_real, const TileGeom& tg, int n_real) {
+    size_t nkp = (size_t)tg.nkeys + 1;
+    size_t nblocks = (size_t)((tg.nkeys + 1023) / 1024);
+    size_t per = (size_t)n_particles_per_real * (4 + 16 + 16) + nkp * 4 * 3 + nblocks * 4 + 256 * 6;
+    return per * (size_t)n_real + 1024;
+}
+
+SortBufs carve_sort(void* base, long npr, const TileGeom& tg, int n_real) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    char* b = static_cast<char*>(base);
+    SortBufs s;
+    s.kstride = tg.nkeys + 1;
+    s.nblocks = (int)((tg.nkeys + 1023) / 1024);
+    size_t off = 0;
+    s.keys = reinterpret_cast<uint32_t*>(b + off); off = al(off + (size_t)npr * n_real * 4);
+    s.recs = reinterpret_cast<float4*>(b + off); off = al(off + (size_t)npr * n_real * 16);
+    s.sorted = reinterpret_cast<float4*>(b + off); off = al(off + (size_t)npr * n_real * 16);
+    s.count = reinterpret_cast<uint32_t*>(b + off); off = al(off + (size_t)s.kstride * n_real * 4);
+    s.start = reinterpret_cast<uint32_t*>(b + off); off = al(off + (size_t)s.kstride * n_real * 4);
+    s.cursor = reinterpret_cast<uint32_t*>(b + off); off = al(off + (size_t)s.kstride * n_real * 4);
+    s.block_sums = reinterpret_cast<uint32_t*>(b + off);
+    return s;
+}
+
+hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg, bool drift,
+                          const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
+                          const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
+                          float scale, float offset, hipStream_t st) {
+    const dim3 pgrid((unsigned)((npr + 255) / 256), n_real);
+    hipError_t e = launch_fill(reinterpret_cast<float*>(sb.count), sb.kstride * n_real, 0.0f, st);
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(drift ? PROF_PK_DEPOSIT : PROF_DEPOSIT, st);
+        if (drift)
+            hipLaunchKernelGGL(k_dep_bin<true>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
+        else
+            hipLaunchKernelGGL(k_dep_bin<false>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(PROF_DEP_SORT, st);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(sb.nblocks, n_real), dim3(256), 0, st, sb.count, sb.start,
+                           sb.block_sums, tg.nkeys, sb.kstride, sb.nblocks);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1, n_real), dim3(1024), 0, st, sb.block_sums, sb.nblocks);
+        hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)((tg.nkeys + 1 + 255) / 256), n_real), dim3(256), 0, st,
+                           sb.start, sb.cursor, sb.block_sums, tg.nkeys, sb.kstride, sb.nblocks,
+                           (uint32_t)npr);
+        hipLaunchKernelGGL(k_dep_scatter, pgrid, dim3(256), 0, st, npr, sb);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(PROF_DEP_TILE, st);
+        size_t lds = (size_t)tg.tx * tg.ty * tg.tz * sizeof(float);
+        hipLaunchKernelGGL(k_dep_tile, dim3((unsigned)tg.ntiles, n_real), dim3(256), lds, st, tg, sb, npr, mesh,
+                           dg.row, dg.mesh_bstride, scale, offset);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cola

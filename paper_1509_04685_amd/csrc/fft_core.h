@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace cola {
 
 constexpr int kMaxStages = 12;
@@ -27,7 +29,25 @@ struct FftPlan {
     int T;        // threads per line, n / R
     int nst;      // number of stages
     int radix[kMaxStages];
+    // per-stage constants, filled on the host by finish_plan():
+    int ns[kMaxStages];        // product of the radices before the stage
+    uint32_t nsm[kMaxStages];  // magic multiplier: j / ns == umulhi(j, nsm) for j < 2^16
+    int nr[kMaxStages];        // n / radix: distance between a butterfly's inputs
+    int tstep[kMaxStages];     // twiddle table step per unit of (j mod ns)
 };
+
+// Fills the per-stage constants of a plan whose radices are set (host side).
+inline void finish_plan(FftPlan& p, int tw_stride) {
+    int ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        int r = p.radix[s];
+        p.ns[s] = ns;
+        p.nsm[s] = ns > 1 ? (uint32_t)(0x100000000ull / (uint64_t)ns + 1ull) : 0u;  // ns = 1 special-cased
+        p.nr[s] = p.n / r;
+        p.tstep[s] = (p.n / (ns * r)) * tw_stride;
+        ns *= r;
+    }
+}
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -102,17 +122,19 @@ __device__ __forceinline__ void dft8(float2* a) {
     a[7] = csub(e3, w3);
 }
 
+__device__ __forceinline__ int div_ns(int j, uint32_t nsm) { return (int)__umulhi((uint32_t)j, nsm); }
+
 // One radix-r stage on the registers of one thread: twiddle then butterfly.
 template <int r, int R, bool INV>
-__device__ __forceinline__ void stage_compute(float2 (&v)[R], int t, int T, int n, int ns,
-                                              const float2* tw, int tw_stride) {
+__device__ __forceinline__ void stage_compute(float2 (&v)[R], int t, int T, int ns, uint32_t nsm, int tstep,
+                                              const float2* tw) {
 #pragma unroll
     for (int s = 0; s < R / r; ++s) {
         float2* a = &v[s * r];
         if (ns > 1) {
             int j = t + s * T;
-            int k = j % ns;
-            int step = (n / (ns * r)) * k * tw_stride;
+            int k = j - div_ns(j, nsm) * ns;
+            int step = tstep * k;
 #pragma unroll
             for (int i = 1; i < r; ++i) a[i] = twiddle<INV>(a[i], tw[i * step]);
         }
@@ -124,22 +146,23 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[R], int t, int T, int 
 }
 
 template <int R, bool INV>
-__device__ __forceinline__ void stage_dispatch(int r, float2 (&v)[R], int t, int T, int n, int ns,
-                                               const float2* tw, int tw_stride) {
-    if constexpr (R % 8 == 0) { if (r == 8) { stage_compute<8, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
-    if constexpr (R % 4 == 0) { if (r == 4) { stage_compute<4, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
-    if constexpr (R % 3 == 0) { if (r == 3) { stage_compute<3, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
-    if constexpr (R % 2 == 0) { if (r == 2) { stage_compute<2, R, INV>(v, t, T, n, ns, tw, tw_stride); return; } }
+__device__ __forceinline__ void stage_dispatch(int r, float2 (&v)[R], int t, int T, int ns, uint32_t nsm, int tstep,
+                                               const float2* tw) {
+    if constexpr (R % 8 == 0) { if (r == 8) { stage_compute<8, R, INV>(v, t, T, ns, nsm, tstep, tw); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { stage_compute<4, R, INV>(v, t, T, ns, nsm, tstep, tw); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { stage_compute<3, R, INV>(v, t, T, ns, nsm, tstep, tw); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { stage_compute<2, R, INV>(v, t, T, ns, nsm, tstep, tw); return; } }
 }
 
 // Scatter a stage's outputs to LDS: value v[s r + i] goes to element (j/ns) ns r + j%ns + i ns.
 template <int r, int R>
-__device__ __forceinline__ void stage_store(const float2 (&v)[R], float2* lds, int les, int t, int T,
-                                            int ns) {
+__device__ __forceinline__ void stage_store(const float2 (&v)[R], float2* lds, int les, int t, int T, int ns,
+                                            uint32_t nsm) {
 #pragma unroll
     for (int s = 0; s < R / r; ++s) {
         int j = t + s * T;
-        int base = (j / ns) * ns * r + (j % ns);
+        int q = (ns == 1) ? j : div_ns(j, nsm);
+        int base = q * ns * (r - 1) + j;  // (j/ns) ns r + j%ns
 #pragma unroll
         for (int i = 0; i < r; ++i) lds[(base + i * ns) * les] = v[s * r + i];
     }
@@ -147,32 +170,48 @@ __device__ __forceinline__ void stage_store(const float2 (&v)[R], float2* lds, i
 
 // Gather a stage's inputs from LDS: v[s r + i] = element (t + s T) + i n / r.
 template <int r, int R>
-__device__ __forceinline__ void stage_load(float2 (&v)[R], const float2* lds, int les, int t, int T,
-                                           int n) {
+__device__ __forceinline__ void stage_load(float2 (&v)[R], const float2* lds, int les, int t, int T, int nr) {
 #pragma unroll
     for (int s = 0; s < R / r; ++s) {
         int j = t + s * T;
 #pragma unroll
-        for (int i = 0; i < r; ++i) v[s * r + i] = lds[(j + i * (n / r)) * les];
+        for (int i = 0; i < r; ++i) v[s * r + i] = lds[(j + i * nr) * les];
     }
 }
 
 template <int R>
-__device__ __forceinline__ void store_dispatch(int r, const float2 (&v)[R], float2* lds, int les,
-                                               int t, int T, int ns) {
-    if constexpr (R % 8 == 0) { if (r == 8) { stage_store<8, R>(v, lds, les, t, T, ns); return; } }
-    if constexpr (R % 4 == 0) { if (r == 4) { stage_store<4, R>(v, lds, les, t, T, ns); return; } }
-    if constexpr (R % 3 == 0) { if (r == 3) { stage_store<3, R>(v, lds, les, t, T, ns); return; } }
-    if constexpr (R % 2 == 0) { if (r == 2) { stage_store<2, R>(v, lds, les, t, T, ns); return; } }
+__device__ __forceinline__ void store_dispatch(int r, const float2 (&v)[R], float2* lds, int les, int t, int T,
+                                               int ns, uint32_t nsm) {
+    if constexpr (R % 8 == 0) { if (r == 8) { stage_store<8, R>(v, lds, les, t, T, ns, nsm); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { stage_store<4, R>(v, lds, les, t, T, ns, nsm); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { stage_store<3, R>(v, lds, les, t, T, ns, nsm); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { stage_store<2, R>(v, lds, les, t, T, ns, nsm); return; } }
 }
 
 template <int R>
-__device__ __forceinline__ void load_dispatch(int r, float2 (&v)[R], const float2* lds, int les,
-                                              int t, int T, int n) {
-    if constexpr (R % 8 == 0) { if (r == 8) { stage_load<8, R>(v, lds, les, t, T, n); return; } }
-    if constexpr (R % 4 == 0) { if (r == 4) { stage_load<4, R>(v, lds, les, t, T, n); return; } }
-    if constexpr (R % 3 == 0) { if (r == 3) { stage_load<3, R>(v, lds, les, t, T, n); return; } }
-    if constexpr (R % 2 == 0) { if (r == 2) { stage_load<2, R>(v, lds, les, t, T, n); return; } }
+__device__ __forceinline__ void load_dispatch(int r, float2 (&v)[R], const float2* lds, int les, int t, int T,
+                                              int nr) {
+    if constexpr (R % 8 == 0) { if (r == 8) { stage_load<8, R>(v, lds, les, t, T, nr); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { stage_load<4, R>(v, lds, les, t, T, nr); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { stage_load<3, R>(v, lds, les, t, T, nr); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { stage_load<2, R>(v, lds, les, t, T, nr); return; } }
+}
+
+// Calls f(q, e) for every register q of a thread and the element e it holds in the load/store
+// pattern of a radix-r first or last stage: q = s r + i holds element (t + s T) + i nr.
+template <int R, class F>
+__device__ __forceinline__ void for_pattern(int r, int t, int T, int nr, F&& f) {
+    auto run = [&](auto rc) {
+        constexpr int rr = decltype(rc)::value;
+#pragma unroll
+        for (int s = 0; s < R / rr; ++s)
+#pragma unroll
+            for (int i = 0; i < rr; ++i) f(s * rr + i, t + s * T + i * nr);
+    };
+    if constexpr (R % 8 == 0) { if (r == 8) { run(std::integral_constant<int, 8>{}); return; } }
+    if constexpr (R % 4 == 0) { if (r == 4) { run(std::integral_constant<int, 4>{}); return; } }
+    if constexpr (R % 3 == 0) { if (r == 3) { run(std::integral_constant<int, 3>{}); return; } }
+    if constexpr (R % 2 == 0) { if (r == 2) { run(std::integral_constant<int, 2>{}); return; } }
 }
 
 // Element index held in v[s r + i] by the load/store pattern of a radix-r first/last stage.
@@ -183,21 +222,20 @@ __device__ __forceinline__ int pattern_index(int s, int i, int r, int t, int T, 
 // Full line transform.  On entry v holds the inputs in the pattern of plan radix[0]; on exit v
 // holds the outputs in the pattern of plan radix[nst-1].  `active` threads take part in the
 // LDS exchange; every thread of the block must call this (barriers inside).  `lds` points at
-// element 0 of this thread's line; consecutive elements are `les` float2 apart.
+// element 0 of this thread's line; consecutive elements are `les` float2 apart.  The plan's
+// twiddle steps already include the table stride.
 template <int R, bool INV>
-__device__ __forceinline__ void fft_line(float2 (&v)[R], const FftPlan& pl, float2* lds, int les,
-                                         int t, const float2* tw, int tw_stride, bool active) {
-    int ns = 1;
+__device__ __forceinline__ void fft_line(float2 (&v)[R], const FftPlan& pl, float2* lds, int les, int t,
+                                         const float2* tw, bool active) {
     for (int st = 0; st < pl.nst; ++st) {
-        int r = pl.radix[st];
-        if (active) stage_dispatch<R, INV>(r, v, t, pl.T, pl.n, ns, tw, tw_stride);
+        const int r = pl.radix[st];
+        if (active) stage_dispatch<R, INV>(r, v, t, pl.T, pl.ns[st], pl.nsm[st], pl.tstep[st], tw);
         if (st + 1 < pl.nst) {
-            if (active) store_dispatch<R>(r, v, lds, les, t, pl.T, ns);
+            if (active) store_dispatch<R>(r, v, lds, les, t, pl.T, pl.ns[st], pl.nsm[st]);
             __syncthreads();
-            if (active) load_dispatch<R>(pl.radix[st + 1], v, lds, les, t, pl.T, pl.n);
+            if (active) load_dispatch<R>(pl.radix[st + 1], v, lds, les, t, pl.T, pl.nr[st + 1]);
             __syncthreads();
         }
-        ns *= r;
     }
 }
 

@@ -259,3 +259,28 @@ def test_resume_matches_uninterrupted(cola):
     cola.step(prob, cosmo, b, 7, wb)
     cola.step(prob, cosmo, a, 7, wa)
     assert rel_rms(b.x.cpu().numpy(), a.x.cpu().numpy()) < 1e-5
+
+
+# ----------------------------------------------------------------------------- autotuned shapes
+
+def test_autotuned_shapes_keep_parity(cola):
+    """The autotuner changes only kernel shapes (values per thread, tile widths); every shape
+    must give the same transform and force."""
+    say("autotune")
+    prob = cola.make_problem(256.0, 32, 3, 19.0, 10)
+    ws = cola.Workspace(prob, n_pk=48)
+    report = cola.autotune(prob, ws, n_pk=48)
+    assert "n=96" in report and "x_green" in report
+    for n in (32, 48, 96):
+        x = W.random_field(n, seed=300 + n)
+        xk = np.fft.rfftn(x)
+        got = cola.fft_r2c(to_dev(x)).cpu().numpy()
+        assert np.sqrt(np.mean(np.abs(got - xk) ** 2) / np.mean(np.abs(xk) ** 2)) < 2e-6 * math.log2(n)
+        back = cola.fft_c2r(torch.as_tensor(xk.astype(np.complex64), device="cuda")).cpu().numpy()
+        assert rel_rms(back, x * n ** 3) < 2e-6 * math.log2(n)
+    disp = W.random_displacements(32, 6.0, seed=77).astype(np.float32)
+    st = gpu_state_from_disp(cola, prob, disp)
+    acc = cola.pm_force(prob, st, ws).cpu().numpy()
+    op = ocola.Problem(256.0, 32, 3, 19.0, 10)
+    ref = opm.pm_accel(ocola.positions(ocola.State(disp.astype(np.float64), None, None, None), op), 96, 256.0)
+    assert rel_rms(acc, ref) < 1e-5
