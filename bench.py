@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plain_256_768")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-seed ensemble measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="for hardware counters: autotune, ICs, one COLA step, one 1 GiB copy; no timing")
     ap.add_argument("--no-profiler", action="store_true",
                     help="time without per-kernel events (roofline omitted)")
     return ap.parse_args()
@@ -138,6 +141,49 @@ def cpu_baseline(cfg, seed):
     }
 
 
+def ensemble_bench(cola, torch, reps):
+    """48-seed ensemble in two shape classes (96^3/288^3 in 300 h^-1 Mpc and 128^3/384^3 in 400),
+    40 nodes each, P(k) at z = 0, replayed as one captured hipGraph."""
+    spec = []
+    total_ps = 0
+    for name in ("ens_96_288", "ens_128_384"):
+        c = W.CONFIGS[name]
+        prob = cola.make_problem(c["box"], c["n_part"], c["pm_factor"], c["z_init"], c["n_steps"],
+                                 n_real=len(c["seeds"]))
+        n_g = c["n_part"] * c["pm_factor"]
+        spec.append(dict(prob=prob, seeds=c["seeds"], a_out=(1.0,), n_pk=n_g, n_bins=n_g // 2))
+        total_ps += len(c["seeds"]) * c["n_part"] ** 3 * c["n_steps"]
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    ens = cola.Ensemble(spec, cosmo)
+    ens.autotune()
+    t0 = time.perf_counter()
+    ens.run(graph=True)  # capture, instantiate, first launch
+    torch.cuda.synchronize()
+    t_capture = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ens.run(graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    n_real = sum(len(x["seeds"]) for x in spec)
+    pk = ens.items[0]["out"][1].cpu()
+    if not bool(torch.isfinite(pk).all()):
+        raise RuntimeError("non-finite ensemble spectra")
+    out = {"realizations": n_real, "seconds_per_ensemble": sec,
+           "realizations_per_hour": n_real * 3600.0 / sec,
+           "particle_steps_per_s": total_ps / sec,
+           "first_launch_with_capture_s": t_capture, "replays_timed": reps,
+           "classes": "24 x (96^3 particles, 288^3 mesh, L 300) + 24 x (128^3, 384^3, L 400), 40 nodes, "
+                      "P(k) at z=0, one hipGraph (classes on forked streams)"}
+    del ens
+    cola.ensemble_release()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -174,6 +220,16 @@ def main():
             cola.power_spectrum(prob, cosmo, st, a, n_pk, n_bins, ws, out=outs[i])
         cola.step(prob, cosmo, st, n_steps - 1, ws)
 
+    if args.profile_step:
+        print(cola.autotune(prob, ws, n_pk=n_pk, state=st).rstrip(), file=sys.stderr, flush=True)
+        cola.ic_2lpt(prob, cosmo, [seed], st, ws)
+        cola.step(prob, cosmo, st, 1, ws)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        cola.copy(a, b)  # 1 GiB read + 1 GiB write: the counter yardstick
+        torch.cuda.synchronize()
+        print("[bench] profile step done", file=sys.stderr, flush=True)
+        return
     print(f"[bench] {args.workload}: {n_part}^3 particles, {n_g}^3 mesh, {n_steps} nodes; "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     if not args.no_autotune:
@@ -248,6 +304,13 @@ def main():
                    "step_unit": "one realization (ICs + all nodes + P(k) outputs)"},
         "roofline": roofline,
     }
+    if not args.no_ensemble:
+        del st, ws, outs
+        torch.cuda.empty_cache()
+        print("[bench] ensemble: 48 seeds in two shape classes, hipGraph", file=sys.stderr, flush=True)
+        result["ensemble"] = ensemble_bench(cola, torch, reps=2)
+        print(f"[bench] ensemble: {result['ensemble']['seconds_per_ensemble']:.2f} s per 48 realizations, "
+              f"{result['ensemble']['realizations_per_hour']:.0f} realizations/hour", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline: float64 oracle, one step", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(cfg, seed)

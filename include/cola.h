@@ -140,6 +140,38 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo,
                         double* k_mean, double* pk, double* n_modes,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* ---- ensembles ------------------------------------------------------------------------- */
+
+/* One shape class of an ensemble: n_real = prob.n_real realizations of one problem. */
+typedef struct {
+    cola_problem prob;
+    const uint64_t* seeds;   /* host, n_real seeds                                          */
+    cola_particles* parts;   /* device arrays of n_real * N_p^3 floats                       */
+    void* ws;                /* device workspace of cola_workspace_bytes(&prob, n_pk) bytes  */
+    size_t ws_bytes;
+    int32_t n_out;           /* P(k) outputs at the scale factors a_out (host, ascending)    */
+    const double* a_out;
+    int32_t n_pk, n_bins;
+    double* k_mean;          /* device, [n_out][n_real][n_bins] each                         */
+    double* pk;
+    double* n_modes;
+} cola_ensemble_class;
+
+/* Mock ensembles (Sec. 2.3: realizations that differ only in their seed; the paper's purpose is
+ * ensembles of mocks, Sec. 1).  For every class: cola_ic_2lpt, then cola_step up to each output
+ * node with cola_power_spectrum at each a_out, then cola_step to the last node -- all
+ * realizations of a class advance together in batched launches.
+ *   mode 0: launch eagerly on `stream`, classes one after the other.
+ *   mode 1: capture the whole ensemble into one hipGraph, each class on its own stream forked
+ *           from `stream` so the classes overlap, instantiate it, launch it on `stream` and keep
+ *           the executable graph; a later call with identical arguments (same pointers, sizes,
+ *           seeds, outputs, cosmology) relaunches it without host work.
+ * On return every class's particles are at their last node.  cola_ensemble_release frees the
+ * cached graphs and streams. */
+int cola_ensemble_run(int32_t n_classes, cola_ensemble_class* classes, const cola_cosmology* cosmo,
+                      int32_t mode, void* stream);
+int cola_ensemble_release(void);
+
 /* FFT autotuner.  Times every admissible kernel shape (values per thread, lines or columns per
  * block) of each FFT pass at the problem's force-mesh, lattice and P(k) sizes, on `stream`, and
  * keeps the fastest for every later call in this process (until then a fixed heuristic is

@@ -198,6 +198,54 @@ def autotune(prob, ws, n_pk=0, state=None):
     return buf.value.decode()
 
 
+class Ensemble:
+    """Shape classes of seeded realizations run together (cola_ensemble_run).
+
+    classes: list of dicts with keys prob, seeds, a_out (tuple), n_pk, n_bins.  Allocates the
+    particle states, workspaces and P(k) outputs of every class.
+    """
+
+    def __init__(self, classes, cosmo, device="cuda"):
+        torch = _torch()
+        self.cosmo = cosmo
+        self.items = []
+        arr = (_lib.EnsembleClass * len(classes))()
+        for i, c in enumerate(classes):
+            prob = c["prob"]
+            st = ParticleState(prob, device)
+            ws = Workspace(prob, n_pk=c["n_pk"], device=device)
+            seeds = np.ascontiguousarray(np.asarray(c["seeds"], dtype=np.uint64))
+            a_out = np.ascontiguousarray(np.asarray(c["a_out"], dtype=np.float64))
+            n_out, n_bins = len(a_out), int(c["n_bins"])
+            out = [torch.zeros((n_out, prob.n_real, n_bins), dtype=torch.float64, device=device)
+                   for _ in range(3)]
+            e = arr[i]
+            e.prob = prob
+            e.seeds = seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+            e.parts = ctypes.pointer(st.c)
+            e.ws = ws.ptr
+            e.ws_bytes = ws.nbytes
+            e.n_out = n_out
+            e.a_out = a_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            e.n_pk = int(c["n_pk"])
+            e.n_bins = n_bins
+            e.k_mean, e.pk, e.n_modes = (_ptr(t) for t in out)
+            self.items.append(dict(prob=prob, state=st, ws=ws, seeds=seeds, a_out=a_out, out=out))
+        self.arr = arr
+
+    def autotune(self):
+        return "".join(autotune(it["prob"], it["ws"], n_pk=int(self.arr[i].n_pk), state=it["state"])
+                       for i, it in enumerate(self.items))
+
+    def run(self, graph=True):
+        _lib.check(_lib.lib().cola_ensemble_run(len(self.items), self.arr, ctypes.byref(self.cosmo),
+                                                1 if graph else 0, _stream()), "cola_ensemble_run")
+
+
+def ensemble_release():
+    _lib.check(_lib.lib().cola_ensemble_release(), "cola_ensemble_release")
+
+
 def profiler_enable(on=True):
     _lib.check(_lib.lib().cola_profiler_enable(1 if on else 0), "cola_profiler_enable")
 

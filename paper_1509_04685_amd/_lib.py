@@ -22,7 +22,7 @@ EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_fft_workspace_bytes", "cola_fft_r2c", "cola_fft_c2r", "cola_schedule_table",
            "cola_linear_power", "cola_status_string", "cola_version", "cola_profiler_enable",
            "cola_profiler_num_kinds", "cola_profiler_kind_name", "cola_profiler_read", "cola_copy",
-           "cola_last_error", "cola_autotune")
+           "cola_last_error", "cola_autotune", "cola_ensemble_run", "cola_ensemble_release")
 
 
 class ColaError(RuntimeError):
@@ -53,6 +53,14 @@ class Particles(ctypes.Structure):
     _fields_ = [("x", _F3), ("p", _F3), ("psi1", _F3), ("psi2", _F3),
                 ("node", ctypes.c_int32), ("force_node", ctypes.c_int32),
                 ("force_ws", ctypes.c_void_p)]
+
+
+class EnsembleClass(ctypes.Structure):
+    _fields_ = [("prob", Problem), ("seeds", ctypes.POINTER(ctypes.c_uint64)),
+                ("parts", ctypes.POINTER(Particles)), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("n_out", ctypes.c_int32), ("a_out", ctypes.POINTER(ctypes.c_double)),
+                ("n_pk", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("k_mean", ctypes.c_void_p), ("pk", ctypes.c_void_p), ("n_modes", ctypes.c_void_p)]
 
 
 def _load():
@@ -87,6 +95,8 @@ def _load():
         "cola_copy": (ctypes.c_int, [vp, vp, sz, vp]),
         "cola_last_error": (ctypes.c_char_p, []),
         "cola_autotune": (ctypes.c_int, [P, i32, vp, sz, vp, ctypes.c_char_p, sz]),
+        "cola_ensemble_run": (ctypes.c_int, [i32, ctypes.POINTER(EnsembleClass), C, i32, vp]),
+        "cola_ensemble_release": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

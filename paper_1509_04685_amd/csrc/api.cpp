@@ -11,16 +11,19 @@
 
 using namespace cola;
 
-namespace {
-
-constexpr int kMaxMesh = 1536;  // keeps per-realization mesh offsets below 2^31
-
 thread_local char g_last_error[512] = "";
 
+namespace cola {
 int hip_fail(hipError_t e, const char* what) {
     std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
     return COLA_ERR_HIP;
 }
+}  // namespace cola
+
+namespace {
+
+constexpr int kMaxMesh = 1536;  // keeps per-realization mesh offsets below 2^31
+
 
 #define COLA_TRY(expr)                                       \
     do {                                                     \

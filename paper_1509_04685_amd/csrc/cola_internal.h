@@ -14,6 +14,9 @@
 
 namespace cola {
 
+// Records the failing call and HIP error for cola_last_error; returns COLA_ERR_HIP.
+int hip_fail(hipError_t e, const char* what);
+
 // ------------------------------------------------------------------ profiler (profiler.cpp)
 enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
@@ -32,6 +35,7 @@ class ProfScope {
     int kind_;
     hipStream_t st_;
     hipEvent_t start_ = nullptr;
+    bool counted_ = false;
 };
 
 // ------------------------------------------------------------------ cosmology (float64, host)
@@ -160,6 +164,7 @@ struct TileGeom {
     int n = 0;             // mesh cells per side
     int tx = 1, ty = 1, tz = 1;
     int ntx = 1, nty = 1, ntz = 1;
+    int lx = 0, ly = 0, lz = 0;  // log2 of the tile sides (all powers of two)
     long ntiles = 0;
     long nkeys = 0;        // ntiles * 8 categories
 };

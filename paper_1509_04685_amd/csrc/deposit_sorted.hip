@@ -34,6 +34,10 @@ TileGeom make_tiles(int n) {
     t.ntz = n / t.tz;
     t.ntiles = (long)t.ntx * t.nty * t.ntz;
     t.nkeys = t.ntiles * 8;
+    auto lg = [](int v) { int l = 0; while ((1 << l) < v) ++l; return l; };
+    t.lx = lg(t.tx);
+    t.ly = lg(t.ty);
+    t.lz = lg(t.tz);
     return t;
 }
 
@@ -149,7 +153,7 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
         const long tile = ((long)(c[0].m / tg.tx) * tg.nty + c[1].m / tg.ty) * tg.ntz + c[2].m / tg.tz;
         const int cat = ((lx == tg.tx - 1) ? 4 : 0) | ((ly == tg.ty - 1) ? 2 : 0) | ((lz == tg.tz - 1) ? 1 : 0);
         key = (uint32_t)(tile * 8 + cat);
-        const int local = (lx * tg.ty + ly) * tg.tz + lz;
+        const int local = (((lx << tg.ly) + ly) << tg.lz) + lz;
         rec = make_float4(__int_as_float(local), c[0].f, c[1].f, c[2].f);
         sb.keys[gid] = key;
         sb.recs[gid] = rec;
@@ -298,7 +302,7 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
         const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
         const float4 rec = recs[rb[q] + (i - rlen[q])];
         const int local = __float_as_int(rec.x);
-        const int lz = local % tg.tz, ly = (local / tg.tz) % tg.ty, lx = local / (tg.tz * tg.ty);
+        const int lz = local & (tg.tz - 1), ly = (local >> tg.lz) & (tg.ty - 1), lx = local >> (tg.lz + tg.ly);
         const int hx = lx - dx * tg.tx, hy = ly - dy * tg.ty, hz = lz - dz * tg.tz;
         const float wx[2] = {1.0f - rec.y, rec.y}, wy[2] = {1.0f - rec.z, rec.z}, wz[2] = {1.0f - rec.w, rec.w};
 #pragma unroll
@@ -313,17 +317,30 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
                 for (int cz = 0; cz < 2; ++cz) {
                     const int uz = hz + cz;
                     if (uz < 0 || uz >= tg.tz) continue;
-                    atomicAdd(&acc[(ux * tg.ty + uy) * tg.tz + uz], wx[cx] * wy[cy] * wz[cz]);
+                    atomicAdd(&acc[(((ux << tg.ly) + uy) << tg.lz) + uz], wx[cx] * wy[cy] * wz[cz]);
                 }
             }
         }
     }
     __syncthreads();
     float* out = mesh + (long)r * mesh_bstride;
-    for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
-        const int uz = i % tg.tz, uy = (i / tg.tz) % tg.ty, ux = i / (tg.tz * tg.ty);
-        const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
-        out[(gx * tg.n + gy) * row + gz] = fmaf(acc[i], scale, offset);
+    if ((tg.tz & 3) == 0) {  // rows of the tile are whole float4s
+        const float4* acc4 = reinterpret_cast<const float4*>(acc);
+        for (int i4 = threadIdx.x; i4 < (ncell >> 2); i4 += blockDim.x) {
+            const int i = i4 << 2;
+            const int uz = i & (tg.tz - 1), uy = (i >> tg.lz) & (tg.ty - 1), ux = i >> (tg.lz + tg.ly);
+            const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
+            float4 a = acc4[i4];
+            a = make_float4(fmaf(a.x, scale, offset), fmaf(a.y, scale, offset), fmaf(a.z, scale, offset),
+                            fmaf(a.w, scale, offset));
+            *reinterpret_cast<float4*>(out + (gx * tg.n + gy) * row + gz) = a;
+        }
+    } else {
+        for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+            const int uz = i & (tg.tz - 1), uy = (i >> tg.lz) & (tg.ty - 1), ux = i >> (tg.lz + tg.ly);
+            const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
+            out[(gx * tg.n + gy) * row + gz] = fmaf(acc[i], scale, offset);
+        }
     }
 }
 

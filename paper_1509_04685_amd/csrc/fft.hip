@@ -206,11 +206,21 @@ struct ColGeom {
     int tiles;        // tiles per outer block
 };
 
+// Block b runs on XCD b % 8 (round-robin dispatch); hand each XCD a contiguous run of tiles so
+// that neighbouring tiles, which share 128-byte lines when a tile row is narrower than a line,
+// meet in the same L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 __device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& base, int& c) {
     const int ct = threadIdx.x % cg.tk;
     t = threadIdx.x / cg.tk;
-    const int outer = blockIdx.x / cg.tiles;
-    const int tile = blockIdx.x - outer * cg.tiles;
+    const int blk = xcd_block();
+    const int outer = blk / cg.tiles;
+    const int tile = blk - outer * cg.tiles;
     c = tile * cg.tk + ct;
     base = (uint32_t)outer * (uint32_t)cg.outer_stride + (uint32_t)c;
     return c < cg.inner && (c % cg.nzp) < cg.mvalid;

@@ -51,16 +51,21 @@ Profiler& prof() {
 ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st) {
     Profiler& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
-    if (!p.enabled || p.depth++ > 0) return;
+    if (!p.enabled) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    counted_ = true;
+    if (p.depth++ > 0) return;
     start_ = p.get();
     if (start_) (void)hipEventRecord(start_, st_);
 }
 
 ProfScope::~ProfScope() {
+    if (!counted_) return;
     Profiler& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
-    if (!p.enabled) return;
-    if (--p.depth > 0 || !start_) return;
+    --p.depth;
+    if (!p.enabled || !start_) return;
     hipEvent_t stop = p.get();
     if (!stop) return;
     (void)hipEventRecord(stop, st_);
