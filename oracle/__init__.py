@@ -15,6 +15,7 @@ lpt        Gaussian field and the first/second-order Lagrangian displacements.
 pm         cloud-in-cell assignment, the Poisson/gradient solve, CIC interpolation.
 cola       the COLA kick-drift-kick integrator in the frame comoving with 2LPT.
 power      the matter power-spectrum estimator.
+learned    the coarse-mesh force-correction network: forward, backward, particle loss.
 """
 
-from . import cosmology, noise, lpt, pm, cola, power  # noqa: F401
+from . import cosmology, noise, lpt, pm, cola, power, learned  # noqa: F401
