@@ -181,6 +181,92 @@ int cola_ensemble_release(void);
 int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_bytes, void* stream,
                   char* report, size_t report_len);
 
+/* ---- learned coarse-mesh force correction ---------------------------------------------- */
+
+/* Sec. 4.4 shows that a force mesh coarser than PM_grid = 3 biases haloes through the force
+ * resolution, and Sec. 7 keeps PM_grid >= 3 for that reason.  This library adds (its own design,
+ * not the paper's) a small periodic 3D convolutional network on the PM_grid = 1 mesh that maps the
+ * mesh fields to a force correction dF, added to the mesh force before it is interpolated:
+ *   X0 = (delta, g_x, g_y, g_z) * in_scale
+ *   A1 = silu(conv3(W1, X0) + b1),  A2 = silu(conv3(W2, A1) + b2),  dF = (W3 A2 + b3) * out_scale
+ * conv3 is the periodic 3x3x3 cross-correlation Z[o][v] = sum_i sum_d W[o][i][tap(d)] X[i][v + d],
+ * d in {-1,0,1}^3, tap(d) = (dx+1) 9 + (dy+1) 3 + (dz+1); silu(z) = z / (1 + exp(-z)); W3 is 1x1x1.
+ * The convolutions run on BF16 matrix cores with FP32 accumulation; activations are stored in
+ * BF16, parameters and the optimizer state in FP32.  Mesh sizes: multiples of 16. */
+typedef struct {
+    int32_t channels;    /* C: 16 or 32                                                       */
+    float in_scale[4];   /* input normalisation of delta, g_x, g_y, g_z                        */
+    float out_scale;     /* output scale                                                       */
+    float* params;       /* device, cola_lc_param_count(C) floats, flat in the order
+                            w1 (C,4,27) b1 (C) w2 (C,C,27) b2 (C) w3 (3,C) b3 (3), C order       */
+    float* grads;        /* device, same size: cola_lc_backward adds into it, cola_lc_adam
+                            clears it; NULL for inference                                      */
+    float* adam_m;       /* device, same size: Adam moments; NULL for inference                */
+    float* adam_v;
+    void* packed;        /* device, cola_lc_packed_bytes(C): BF16 copies of the conv weights,
+                            written by cola_lc_pack (and by cola_lc_adam after each update)    */
+} cola_lc_net;
+
+int64_t cola_lc_param_count(int32_t channels);  /* 0 for an unsupported C */
+size_t cola_lc_packed_bytes(int32_t channels);
+/* Device workspace of the network on an n_mesh^3 mesh for n_real realizations; training keeps the
+ * activations the backward pass needs. */
+size_t cola_lc_workspace_bytes(int32_t n_mesh, int32_t channels, int32_t n_real, int32_t training);
+
+/* Rewrites net->packed from net->params.  Call after writing params. */
+int cola_lc_pack(const cola_lc_net* net, void* stream);
+
+/* dF of the network on one n_mesh^3 mesh.  delta, g[3]: device, dense n_mesh^3 floats each (the
+ * fields of cola_pm_fields); df[3]: device, dense n_mesh^3, overwritten (accumulate = 0) or added
+ * into (1).  training = 1 keeps the activations in ws for one cola_lc_backward; ws holds
+ * cola_lc_workspace_bytes(n_mesh, C, 1, training) bytes. */
+int cola_lc_forward(const cola_lc_net* net, int32_t n_mesh, const float* delta, const float* g[3],
+                    float* df[3], int32_t accumulate, int32_t training, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Adds to net->grads the gradient of a loss L with respect to the parameters, given
+ * d_df = dL/d(dF) (device, dense [3][n_mesh^3]) for the last training forward pass in ws (same
+ * net, same n_mesh, parameters unchanged since). */
+int cola_lc_backward(const cola_lc_net* net, int32_t n_mesh, const float* d_df, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Training loss on particles at absolute positions pos[3] (device, n floats each):
+ *   L = sum_p |g1_p + G[dF]_p - g3_p|^2 / sum_p |g3_p - g1_p|^2
+ * with G the CIC interpolation of dF (device, dense n_mesh^3 per component) in a box of side box,
+ * g1 the coarse-mesh and g3 the target acceleration at the particles (device, n floats each).
+ * stats (device, 2 doubles): L and the denominator, overwritten.  d_df (device, dense
+ * [3][n_mesh^3]): dL/d(dF), overwritten. */
+int cola_lc_loss(int32_t n_mesh, double box, const float* pos[3], int64_t n, const float* df[3],
+                 const float* g1[3], const float* g3[3], double* stats, float* d_df, void* stream);
+
+/* One Adam step (Kingma & Ba 2015) at step number t >= 1 on net->params with net->grads, then
+ * clears net->grads and repacks the BF16 weights. */
+int cola_lc_adam(const cola_lc_net* net, int32_t t, float lr, float beta1, float beta2, float eps,
+                 void* stream);
+
+/* cola_step with the network's correction: at each force evaluation the density contrast and the
+ * mesh force of every realization feed the network and dF is added to the force mesh before the
+ * kick.  lc_ws: cola_lc_workspace_bytes(N_g, C, n_real, 0) bytes.  N_g a multiple of 16.  The
+ * cached force (force_node) is then the corrected one: reset force_node to -1 before mixing
+ * cola_step and cola_step_lc on one state, and call cola_power_spectrum between nodes only on a
+ * state whose corrected force is cached. */
+int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin,
+                 int32_t j_end, cola_particles* io, const cola_lc_net* net, void* lc_ws,
+                 size_t lc_ws_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Mesh fields of arbitrary particles: CIC of the absolute positions pos[3] (device, n floats
+ * each, any real, wrapped into the box) onto n_mesh^3 cells, delta = rho / rho_bar - 1, the force
+ * g_k = i k delta_k / k^2 as in cola_pm_force, and its CIC interpolation to the particles.  Each
+ * output may be NULL: delta (dense n_mesh^3), g[3] (dense n_mesh^3 each), acc[3] (n each), all
+ * device.  ws: cola_pm_fields_workspace_bytes(n_mesh) bytes. */
+size_t cola_pm_fields_workspace_bytes(int32_t n_mesh);
+int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, float* delta, float* g[3],
+                   float* acc[3], void* ws, size_t ws_bytes, void* stream);
+
+/* Absolute positions q + x of a batch, wrapped into [0, box): pos[d] device arrays of
+ * n_real * N_p^3 floats. */
+int cola_positions(const cola_problem* prob, const cola_particles* in, float* pos[3], void* stream);
+
 /* ---- component entry points (the stages above, exposed for parity checks) ------------- */
 
 /* CIC density contrast of arbitrary positions: pos[d] device arrays of n floats (absolute
@@ -222,6 +308,10 @@ int cola_profiler_read(int32_t n_kinds, double* total_ms, int64_t* launches);
 /* Plain device-to-device copy of `bytes` bytes with the library's streaming kernel (16-byte
  * vectors): the yardstick against which hardware byte counters are scaled. */
 int cola_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/* One BF16 matrix-core product D = A B (A 16x32, B 32x16 BF16 bit patterns, D 16x16 FP32, all
+ * row-major device arrays) through the operand layout the network's convolutions assume. */
+int cola_mfma_selftest(const uint16_t* a, const uint16_t* b, float* d, void* stream);
 
 /* Message for a cola_status value (static storage). */
 const char* cola_status_string(int status);

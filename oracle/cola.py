@@ -51,6 +51,7 @@ class Problem:
         self.a_final = float(a_final)
         self.sampling = sampling
         self.sampling_power = sampling_power
+        self.accel = None  # force law override, accel(pos, n_mesh, box) -> (3, N)
 
     @property
     def n_mesh(self):
@@ -140,7 +141,10 @@ def bracket(g, d1, d2, psi1, psi2):
 
 
 def evaluate_force(state, problem):
-    state.force = pm.pm_accel(positions(state, problem), problem.n_mesh, problem.box)
+    """Acceleration g at the particles: the PM force, or problem.accel(pos, n_mesh, box) when the
+    problem carries another force law (the learned correction)."""
+    accel = getattr(problem, "accel", None) or pm.pm_accel
+    state.force = accel(positions(state, problem), problem.n_mesh, problem.box)
     return state.force
 
 

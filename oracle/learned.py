@@ -124,3 +124,36 @@ def particle_loss(df_mesh, pos, box, g1, g3):
         vals = 2.0 * r[c] / denom
         grad[c] = np.bincount(idx.ravel(), weights=(wts * vals[None, :]).ravel(), minlength=n ** 3)
     return loss, grad.reshape(3, n, n, n)
+
+
+def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015, Algorithm 1) at step t >= 1; returns new (params, m, v).
+
+    m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+    params <- params - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+    """
+    m = beta1 * m + (1.0 - beta1) * grads
+    v = beta2 * v + (1.0 - beta2) * grads * grads
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def corrected_accel(net, pos, n_mesh, box):
+    """Mesh force plus the network's correction, interpolated to the particles (3, N)."""
+    delta = pm.density_contrast(pos, n_mesh, box)
+    g = pm.force_mesh(delta, box)
+    df, _ = forward(net, delta, g)
+    return pm.cic_gather(g + df, pos, box)
+
+
+def flat_params(net):
+    """Parameters in one flat array, in the order w1 b1 w2 b2 w3 b3 (C order within each)."""
+    return np.concatenate([p.ravel() for p in net.params()])
+
+
+def set_flat_params(net, flat):
+    off = 0
+    for p in net.params():
+        p[...] = np.asarray(flat[off:off + p.size]).reshape(p.shape)
+        off += p.size

@@ -272,3 +272,185 @@ def copy(src, dst):
 
 def linear_power(cosmo, k):
     return float(_lib.lib().cola_linear_power(ctypes.byref(cosmo), float(k)))
+
+
+# ---------------------------------------------------------------- learned force correction
+
+def _ptrs3(ts):
+    return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
+
+def lc_param_count(channels):
+    return int(_lib.lib().cola_lc_param_count(int(channels)))
+
+
+def lc_init_params(channels, seed=0):
+    """He-normal initial weights (zero biases, small output layer) as a flat float32 host array
+    in the library's order w1 (C,4,27) b1 w2 (C,C,27) b2 w3 (3,C) b3."""
+    rng = np.random.default_rng(seed)
+    c = int(channels)
+    parts = [rng.normal(0.0, np.sqrt(2.0 / 108.0), 108 * c), np.zeros(c),
+             rng.normal(0.0, np.sqrt(2.0 / (27.0 * c)), 27 * c * c), np.zeros(c),
+             rng.normal(0.0, np.sqrt(1.0 / c), 3 * c) * 0.1, np.zeros(3)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class LcNet:
+    """The correction network on the device: FP32 parameters (and, for training, gradients and
+    Adam moments) plus the BF16 weight copies the convolutions read."""
+
+    def __init__(self, channels=16, params=None, in_scale=(1.0, 1.0, 1.0, 1.0), out_scale=1.0,
+                 training=True, device="cuda"):
+        torch = _torch()
+        count = lc_param_count(channels)
+        if count == 0:
+            raise ColaError(-1, "cola_lc_param_count")
+        self.channels = int(channels)
+        self.params = torch.zeros(count, dtype=torch.float32, device=device)
+        self.grads = torch.zeros(count, dtype=torch.float32, device=device) if training else None
+        self.adam_m = torch.zeros(count, dtype=torch.float32, device=device) if training else None
+        self.adam_v = torch.zeros(count, dtype=torch.float32, device=device) if training else None
+        self.packed = torch.empty(int(_lib.lib().cola_lc_packed_bytes(self.channels)), dtype=torch.uint8,
+                                  device=device)
+        self.c = _lib.LcNet()
+        self.c.channels = self.channels
+        self.c.params = self.params.data_ptr()
+        self.c.grads = self.grads.data_ptr() if training else None
+        self.c.adam_m = self.adam_m.data_ptr() if training else None
+        self.c.adam_v = self.adam_v.data_ptr() if training else None
+        self.c.packed = self.packed.data_ptr()
+        self.set_scales(in_scale, out_scale)
+        self.set_params(lc_init_params(channels) if params is None else params)
+        self.step_count = 0
+
+    def set_scales(self, in_scale, out_scale):
+        for i in range(4):
+            self.c.in_scale[i] = float(in_scale[i])
+        self.c.out_scale = float(out_scale)
+
+    @property
+    def in_scale(self):
+        return tuple(float(self.c.in_scale[i]) for i in range(4))
+
+    @property
+    def out_scale(self):
+        return float(self.c.out_scale)
+
+    def set_params(self, flat):
+        torch = _torch()
+        flat = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(-1))
+        if flat.size != self.params.numel():
+            raise ValueError("wrong parameter count")
+        self.params.copy_(torch.from_numpy(flat))
+        self.pack()
+
+    def get_params(self):
+        return self.params.cpu().numpy().copy()
+
+    def pack(self):
+        _lib.check(_lib.lib().cola_lc_pack(ctypes.byref(self.c), _stream()), "cola_lc_pack")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        _lib.check(_lib.lib().cola_lc_adam(ctypes.byref(self.c), self.step_count, float(lr), float(beta1),
+                                           float(beta2), float(eps), _stream()), "cola_lc_adam")
+
+
+def lc_workspace(n_mesh, channels, n_real=1, training=False, device="cuda"):
+    torch = _torch()
+    nbytes = int(_lib.lib().cola_lc_workspace_bytes(int(n_mesh), int(channels), int(n_real), 1 if training else 0))
+    if nbytes == 0:
+        raise ColaError(-2, "cola_lc_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def lc_forward(net, delta, g, ws, df=None, accumulate=False, training=False):
+    """dF (3, n, n, n) of the network for delta (n, n, n) and g (3, n, n, n) device float32."""
+    torch = _torch()
+    _require_cuda_f32(delta, "delta")
+    _require_cuda_f32(g, "g")
+    n = delta.shape[0]
+    if df is None:
+        df = torch.empty((3, n, n, n), dtype=torch.float32, device=delta.device)
+    _lib.check(_lib.lib().cola_lc_forward(ctypes.byref(net.c), n, _ptr(delta), _ptrs3(g), _ptrs3(df),
+                                          1 if accumulate else 0, 1 if training else 0, _ptr(ws), ws.numel(),
+                                          _stream()), "cola_lc_forward")
+    return df
+
+
+def lc_backward(net, d_df, ws):
+    _require_cuda_f32(d_df, "d_df")
+    n = d_df.shape[-1]
+    _lib.check(_lib.lib().cola_lc_backward(ctypes.byref(net.c), n, _ptr(d_df), _ptr(ws), ws.numel(), _stream()),
+               "cola_lc_backward")
+
+
+def lc_loss(pos, box, df, g1, g3, stats=None, d_df=None):
+    """(stats, d_df): stats = [L, denominator] float64 device tensor, d_df = dL/d(dF) (3, n, n, n)."""
+    torch = _torch()
+    n = df.shape[-1]
+    if stats is None:
+        stats = torch.empty(2, dtype=torch.float64, device=df.device)
+    if d_df is None:
+        d_df = torch.empty((3, n, n, n), dtype=torch.float32, device=df.device)
+    _lib.check(_lib.lib().cola_lc_loss(n, float(box), _ptrs3(pos), pos.shape[1], _ptrs3(df), _ptrs3(g1),
+                                       _ptrs3(g3), _ptr(stats), _ptr(d_df), _stream()), "cola_lc_loss")
+    return stats, d_df
+
+
+def step_lc(prob, cosmo, state, j_end, net, lc_ws, ws):
+    _lib.check(_lib.lib().cola_step_lc(ctypes.byref(prob), ctypes.byref(cosmo), state.c.node, int(j_end),
+                                       ctypes.byref(state.c), ctypes.byref(net.c), _ptr(lc_ws), lc_ws.numel(),
+                                       ws.ptr, ws.nbytes, _stream()), "cola_step_lc")
+
+
+def pm_fields(pos, n_mesh, box, delta=True, g=True, acc=True, ws=None):
+    """Mesh fields of absolute positions pos (3, n): dict with 'delta' (n_mesh^3), 'g' (3, n_mesh^3)
+    and 'acc' (3, n) as requested."""
+    torch = _torch()
+    _require_cuda_f32(pos, "pos")
+    dev = pos.device
+    n = int(n_mesh)
+    nb = int(_lib.lib().cola_pm_fields_workspace_bytes(n))
+    if nb == 0:
+        raise ColaError(-2, "cola_pm_fields_workspace_bytes")
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    out = {}
+    if delta is True:
+        delta = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    if g is True:
+        g = torch.empty((3, n, n, n), dtype=torch.float32, device=dev)
+    if acc is True:
+        acc = torch.empty((3, pos.shape[1]), dtype=torch.float32, device=dev)
+    dp = _ptr(delta) if delta is not None and delta is not False else None
+    gp = _ptrs3(g) if g is not None and g is not False else None
+    ap = _ptrs3(acc) if acc is not None and acc is not False else None
+    _lib.check(_lib.lib().cola_pm_fields(n, float(box), _ptrs3(pos), pos.shape[1], dp, gp, ap, _ptr(ws), ws.numel(),
+                                         _stream()), "cola_pm_fields")
+    if dp is not None:
+        out["delta"] = delta
+    if gp is not None:
+        out["g"] = g
+    if ap is not None:
+        out["acc"] = acc
+    return out
+
+
+def positions(prob, state, out=None):
+    """Absolute positions (3, n_real * N_p^3) of a state, wrapped into [0, box)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((3, state.n), dtype=torch.float32, device=state.x.device)
+    _lib.check(_lib.lib().cola_positions(ctypes.byref(prob), ctypes.byref(state.c), _ptrs3(out), _stream()),
+               "cola_positions")
+    return out
+
+
+def mfma_selftest(a_bits, b_bits):
+    """a_bits (16, 32), b_bits (32, 16): int16 device tensors of BF16 bit patterns -> D (16, 16) float32."""
+    torch = _torch()
+    d = torch.empty((16, 16), dtype=torch.float32, device=a_bits.device)
+    _lib.check(_lib.lib().cola_mfma_selftest(_ptr(a_bits), _ptr(b_bits), _ptr(d), _stream()),
+               "cola_mfma_selftest")
+    return d

@@ -22,7 +22,10 @@ EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_fft_workspace_bytes", "cola_fft_r2c", "cola_fft_c2r", "cola_schedule_table",
            "cola_linear_power", "cola_status_string", "cola_version", "cola_profiler_enable",
            "cola_profiler_num_kinds", "cola_profiler_kind_name", "cola_profiler_read", "cola_copy",
-           "cola_last_error", "cola_autotune", "cola_ensemble_run", "cola_ensemble_release")
+           "cola_last_error", "cola_autotune", "cola_ensemble_run", "cola_ensemble_release",
+           "cola_lc_param_count", "cola_lc_packed_bytes", "cola_lc_workspace_bytes", "cola_lc_pack",
+           "cola_lc_forward", "cola_lc_backward", "cola_lc_loss", "cola_lc_adam", "cola_step_lc",
+           "cola_pm_fields_workspace_bytes", "cola_pm_fields", "cola_positions", "cola_mfma_selftest")
 
 
 class ColaError(RuntimeError):
@@ -63,6 +66,12 @@ class EnsembleClass(ctypes.Structure):
                 ("k_mean", ctypes.c_void_p), ("pk", ctypes.c_void_p), ("n_modes", ctypes.c_void_p)]
 
 
+class LcNet(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32), ("in_scale", ctypes.c_float * 4), ("out_scale", ctypes.c_float),
+                ("params", ctypes.c_void_p), ("grads", ctypes.c_void_p), ("adam_m", ctypes.c_void_p),
+                ("adam_v", ctypes.c_void_p), ("packed", ctypes.c_void_p)]
+
+
 def _load():
     # torch bundles its own HIP runtime under the same soname (libamdhip64.so.7).  Whichever is
     # loaded first serves the whole process, and the streams and device pointers this binding
@@ -73,6 +82,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P, C, PP = ctypes.POINTER(Problem), ctypes.POINTER(Cosmology), ctypes.POINTER(Particles)
+    N = ctypes.POINTER(LcNet)
     sig = {
         "cola_workspace_bytes": (sz, [P, i32]),
         "cola_ic_2lpt": (ctypes.c_int, [P, C, ctypes.POINTER(ctypes.c_uint64), PP, vp, sz, vp]),
@@ -97,6 +107,21 @@ def _load():
         "cola_autotune": (ctypes.c_int, [P, i32, vp, sz, vp, ctypes.c_char_p, sz]),
         "cola_ensemble_run": (ctypes.c_int, [i32, ctypes.POINTER(EnsembleClass), C, i32, vp]),
         "cola_ensemble_release": (ctypes.c_int, []),
+        "cola_lc_param_count": (i64, [i32]),
+        "cola_lc_packed_bytes": (sz, [i32]),
+        "cola_lc_workspace_bytes": (sz, [i32, i32, i32, i32]),
+        "cola_lc_pack": (ctypes.c_int, [N, vp]),
+        "cola_lc_forward": (ctypes.c_int, [N, i32, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32, vp, sz, vp]),
+        "cola_lc_backward": (ctypes.c_int, [N, i32, vp, vp, sz, vp]),
+        "cola_lc_loss": (ctypes.c_int, [i32, dbl, ctypes.POINTER(vp), i64, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), vp, vp, vp]),
+        "cola_lc_adam": (ctypes.c_int, [N, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
+        "cola_step_lc": (ctypes.c_int, [P, C, i32, i32, PP, N, vp, sz, vp, sz, vp]),
+        "cola_pm_fields_workspace_bytes": (sz, [i32]),
+        "cola_pm_fields": (ctypes.c_int, [i32, dbl, ctypes.POINTER(vp), i64, vp, ctypes.POINTER(vp),
+                                          ctypes.POINTER(vp), vp, sz, vp]),
+        "cola_positions": (ctypes.c_int, [P, PP, ctypes.POINTER(vp), vp]),
+        "cola_mfma_selftest": (ctypes.c_int, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

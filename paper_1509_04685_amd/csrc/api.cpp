@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "cola_internal.h"
+#include "lc_internal.h"
 
 using namespace cola;
 
@@ -145,10 +146,20 @@ LatticeGeom force_geom(const cola_problem& p, const Layout& L) {
     return g;
 }
 
+// The network correction at each force evaluation: its parameters, activations (x0 per
+// realization, the rest shared) and scales.
+struct LcHook {
+    LcParams P;
+    LcActs A;
+    long x0_stride;
+    float in_scale[4];
+    float out_scale;
+};
+
 // Density, forward transform and force meshes for the current positions.  Force meshes end up
-// as real rows in B (x), A (y), S (z).
+// as real rows in B (x), A (y), S (z); with a network hook, dF is added to them.
 hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, const ParticlePtrs& P,
-                         hipStream_t st) {
+                         hipStream_t st, const LcHook* lc = nullptr) {
     const long npr = (long)p.n_part * p.n_part * p.n_part;
     LatticeGeom fg = force_geom(p, L);
     const double cells = (double)L.g.n * L.g.n * L.g.n;
@@ -157,10 +168,27 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
     hipError_t e = sorted_deposit(P, npr, p.n_real, fg, false, fg, nullptr, nullptr, nullptr, none, L.tg, sb,
                                   reinterpret_cast<float*>(w.S), (float)(cells / (double)npr), -1.0f, st);
     if (e != hipSuccess) return e;
-    e = fft_zy_forward(reinterpret_cast<const float*>(w.S), 2L * L.g.nzp, 2L * L.cstride, w.S, L.cstride, L.g,
-                       w.twg, p.n_real, 1.0f, 0.0f, st);
+    const long row = 2L * L.g.nzp, bs = 2L * L.cstride;
+    if (lc)
+        for (int r = 0; r < p.n_real; ++r)
+            if ((e = lc_pack_delta(reinterpret_cast<const float*>(w.S) + r * bs, row, L.g.n, lc->in_scale[0],
+                                   lc->A.x0 + r * lc->x0_stride, st)) != hipSuccess)
+                return e;
+    e = fft_zy_forward(reinterpret_cast<const float*>(w.S), row, bs, w.S, L.cstride, L.g, w.twg, p.n_real, 1.0f,
+                       0.0f, st);
     if (e != hipSuccess) return e;
-    return pm_force_from_spectrum(w.S, w.A, w.B, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real, st);
+    e = pm_force_from_spectrum(w.S, w.A, w.B, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real, st);
+    if (e != hipSuccess || !lc) return e;
+    for (int r = 0; r < p.n_real; ++r) {
+        float* f[3] = {reinterpret_cast<float*>(w.B) + r * bs, reinterpret_cast<float*>(w.A) + r * bs,
+                       reinterpret_cast<float*>(w.S) + r * bs};
+        const float* fc[3] = {f[0], f[1], f[2]};
+        LcActs a = lc->A;
+        a.x0 = lc->A.x0 + r * lc->x0_stride;
+        if ((e = lc_pack_force(fc, row, L.g.n, lc->in_scale + 1, a.x0, st)) != hipSuccess) return e;
+        if ((e = lc_forward(lc->P, a, L.g.n, lc->out_scale, f, row, 1, false, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 struct ForceMeshes {
@@ -169,6 +197,54 @@ struct ForceMeshes {
 ForceMeshes force_meshes(const Ws& w) {
     return {reinterpret_cast<const float*>(w.B), reinterpret_cast<const float*>(w.A),
             reinterpret_cast<const float*>(w.S)};
+}
+
+int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
+              cola_particles* io, void* ws, size_t ws_bytes, void* stream, const LcHook* lc) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
+    if ((s = check_particles(io)) != COLA_OK) return s;
+    if (!ws) return COLA_ERR_INVALID_ARG;
+    if (j_begin != io->node || j_begin < 0 || j_end < j_begin || j_end >= prob->n_steps) return COLA_ERR_STATE;
+    Layout L = layout_of(*prob, 0);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    if (j_end == j_begin) return COLA_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    const cola_problem& p = *prob;
+    ParticlePtrs P = ptrs_of(io);
+    Schedule sc = make_schedule(p, *cosmo);
+    const double c32 = 1.5 * sc.omega_m;
+    const long npr = (long)p.n_part * p.n_part * p.n_part;
+    LatticeGeom fg = force_geom(p, L);
+    ForceMeshes f = force_meshes(w);
+
+    (void)hipGetLastError();
+    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
+    if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st, lc));
+    double pending = 0.0;  // kick still owed to the current node (merged with the next kick)
+    for (int j = j_begin; j < j_end; ++j) {
+        KickDrift kd;
+        kd.kick = (float)(c32 * (pending + sc.k_out[j]));
+        kd.d1 = (float)sc.d1[j];
+        kd.d2m = (float)(sc.d2[j] - sc.d1[j] * sc.d1[j]);
+        kd.drift = (float)sc.drift[j];
+        kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
+        kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
+        COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
+        COLA_TRY(compute_force(p, L, w, P, st, lc));
+        pending = sc.k_in[j];
+    }
+    KickDrift kd{};
+    kd.kick = (float)(c32 * pending);
+    kd.d1 = (float)sc.d1[j_end];
+    kd.d2m = (float)(sc.d2[j_end] - sc.d1[j_end] * sc.d1[j_end]);
+    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
+    io->node = j_end;
+    io->force_node = j_end;
+    io->force_ws = ws;
+    return COLA_OK;
 }
 
 }  // namespace
@@ -301,50 +377,27 @@ int cola_pm_force(const cola_problem* prob, const cola_particles* in, float* acc
 
 int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
               cola_particles* io, void* ws, size_t ws_bytes, void* stream) {
+    return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, nullptr);
+}
+
+int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
+                 cola_particles* io, const cola_lc_net* net, void* lc_ws, size_t lc_ws_bytes, void* ws,
+                 size_t ws_bytes, void* stream) {
     int s;
     if ((s = check_problem(prob)) != COLA_OK) return s;
-    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
-    if ((s = check_particles(io)) != COLA_OK) return s;
-    if (!ws) return COLA_ERR_INVALID_ARG;
-    if (j_begin != io->node || j_begin < 0 || j_end < j_begin || j_end >= prob->n_steps) return COLA_ERR_STATE;
-    Layout L = layout_of(*prob, 0);
-    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
-    if (j_end == j_begin) return COLA_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    Ws w = carve(ws, L);
-    const cola_problem& p = *prob;
-    ParticlePtrs P = ptrs_of(io);
-    Schedule sc = make_schedule(p, *cosmo);
-    const double c32 = 1.5 * sc.omega_m;
-    const long npr = (long)p.n_part * p.n_part * p.n_part;
-    LatticeGeom fg = force_geom(p, L);
-    ForceMeshes f = force_meshes(w);
-
-    (void)hipGetLastError();
-    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
-    if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st));
-    double pending = 0.0;  // kick still owed to the current node (merged with the next kick)
-    for (int j = j_begin; j < j_end; ++j) {
-        KickDrift kd;
-        kd.kick = (float)(c32 * (pending + sc.k_out[j]));
-        kd.d1 = (float)sc.d1[j];
-        kd.d2m = (float)(sc.d2[j] - sc.d1[j] * sc.d1[j]);
-        kd.drift = (float)sc.drift[j];
-        kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
-        kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
-        COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
-        COLA_TRY(compute_force(p, L, w, P, st));
-        pending = sc.k_in[j];
-    }
-    KickDrift kd{};
-    kd.kick = (float)(c32 * pending);
-    kd.d1 = (float)sc.d1[j_end];
-    kd.d2m = (float)(sc.d2[j_end] - sc.d1[j_end] * sc.d1[j_end]);
-    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
-    io->node = j_end;
-    io->force_node = j_end;
-    io->force_ws = ws;
-    return COLA_OK;
+    if ((s = lc_check_net(net, false)) != COLA_OK) return s;
+    const int ng = prob->n_part * prob->pm_factor;
+    if (!lc_mesh_ok(ng)) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (!lc_ws) return COLA_ERR_INVALID_ARG;
+    const LcWsLayout LL = lc_ws_layout(ng, net->channels, prob->n_real, false);
+    if (lc_ws_bytes < LL.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    LcHook h;
+    h.P = lc_params_of(net);
+    h.A = lc_carve(lc_ws, LL);
+    h.x0_stride = LL.x0_stride;
+    for (int i = 0; i < 4; ++i) h.in_scale[i] = net->in_scale[i];
+    h.out_scale = net->out_scale;
+    return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, &h);
 }
 
 int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,

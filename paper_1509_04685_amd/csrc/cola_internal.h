@@ -21,7 +21,8 @@ int hip_fail(hipError_t e, const char* what);
 enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
     PROF_Y_INV, PROF_Z_C2R, PROF_GKD, PROF_GATHER, PROF_IC, PROF_X_INV_MULT, PROF_PK, PROF_COPY,
-    PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_NUM_KINDS
+    PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_LC_CONV, PROF_LC_WGRAD, PROF_LC_MISC,
+    PROF_NUM_KINDS
 };
 // Brackets one kernel launch with an event pair when the profiler is enabled.
 class ProfScope {

@@ -1,0 +1,744 @@
+// Learned coarse-mesh force correction: a periodic 3D convolutional network on the PM_grid = 1
+// mesh fields (delta, g) -> force correction dF, with BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) for the 3x3x3 convolutions, its training kernels and Adam.  (Sec. 4.4: a force
+// mesh below PM_grid = 3 biases haloes through the force resolution.)
+//
+// Network:  X0 = [delta, g_x, g_y, g_z] * in_scale (padded to 8 channels)
+//           Z1 = conv3(W1, X0) + b1, A1 = silu(Z1);  Z2 = conv3(W2, A1) + b2, A2 = silu(Z2);
+//           dF = (W3 A2 + b3) * out_scale   (1x1x1, 3 channels)
+// conv3 is a periodic cross-correlation over the 27 offsets d in {-1,0,1}^3, tap index
+// (dx+1) 9 + (dy+1) 3 + (dz+1).
+//
+// Layouts: activations BF16, channel-last [voxel][channels], voxel = (x n + y) n + z; conv
+// weights BF16 [c_out][tap][c_in]; FP32 master parameters flat (lc_internal.h).  An MFMA
+// fragment gives lane l the row (or column) l % 16 and the eight K values 8 (l / 16) .. + 7,
+// here eight consecutive channels of one tap: 16 contiguous bytes.  The accumulator gives lane
+// l the column l % 16 and rows 4 (l / 16) .. + 3.  (A K order that differs from this one is
+// harmless: both operands index K the same way.)
+
+#include <algorithm>
+#include <cmath>
+
+#include "cola_internal.h"
+#include "lc_internal.h"
+
+namespace cola {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ uint32_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return u >> 16;  // inf / nan kept
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float((h & 0xffffu) << 16); }
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_f(float z) { return z * sigm(z); }
+__device__ __forceinline__ float silu_g(float z) {
+    const float s = sigm(z);
+    return s * (1.0f + z * (1.0f - s));
+}
+
+union Frag8 {
+    uint4 u;
+    bf16x8 v;
+    uint16_t h[8];
+};
+
+__device__ __forceinline__ uint4 pack8(const uint32_t t[8]) {
+    return make_uint4(t[0] | (t[1] << 16), t[2] | (t[3] << 16), t[4] | (t[5] << 16), t[6] | (t[7] << 16));
+}
+
+static unsigned blocks_for(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class K>
+static hipError_t allow_lds_lc(K kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+// ------------------------------------------------------------------ MFMA fragment self-test
+
+// D = A B with A 16x32 and B 32x16 (row-major BF16 bits) and D 16x16 FP32 row-major, through the
+// fragment mapping the convolutions use.
+__global__ void k_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D) {
+    const int l = threadIdx.x;
+    const int row = l & 15, kb = l >> 4;
+    uint32_t ta[8], tb[8];
+    for (int j = 0; j < 8; ++j) {
+        ta[j] = A[row * 32 + kb * 8 + j];
+        tb[j] = B[(kb * 8 + j) * 16 + row];
+    }
+    Frag8 a, b;
+    a.u = pack8(ta);
+    b.u = pack8(tb);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) D[(4 * kb + q) * 16 + row] = acc[q];
+}
+
+hipError_t lc_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, hipStream_t st) {
+    hipLaunchKernelGGL(k_mfma_selftest, dim3(1), dim3(64), 0, st, A, B, D);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ 3x3x3 convolution (implicit GEMM)
+
+constexpr int TX = 4, TY = 4, TZ = 16;                // output tile of one block
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;  // with the periodic halo
+constexpr int HVOX = HX * HY * HZ;
+constexpr int TV = TX * TY * TZ;
+
+__device__ __forceinline__ int wrap_halo(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+enum { EPI_ZA = 0, EPI_A = 1, EPI_DSILU = 2 };
+
+// out[v][co] = sum_tap sum_ci W[co][tap][ci] in[v + d_tap][ci] + bias[co], then
+//   EPI_ZA: out = Z, out2 = silu(Z);  EPI_A: out = silu(Z);  EPI_DSILU: out = Z * silu'(prev[v][co]).
+// in: [V][CINP] BF16; W: [16 NB][27][CINP] BF16; out: [V][16 NB].  Block = 4 waves on a 4x4x16
+// tile, wave w computing the rows x0 + w, y0 + 0..3 (16 voxels along z each) for all outputs.
+template <int CINP, int NB, int EPI>
+__global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias, uint16_t* out, uint16_t* out2,
+                                                    const uint16_t* __restrict__ prev, int n, int tiles) {
+    constexpr int COP = 16 * NB;
+    constexpr int KTOT = 27 * CINP;
+    constexpr int KSTEPS = (KTOT + 31) / 32;
+    constexpr int C8 = CINP / 8;
+    extern __shared__ uint4 smem[];
+    uint4* sw = smem;                      // weights, COP * 27 * C8 vectors
+    uint4* sh = smem + COP * 27 * C8;      // halo, HVOX * C8 vectors
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint4* wg = reinterpret_cast<const uint4*>(w);
+    for (int i = tid; i < COP * 27 * C8; i += 256) sw[i] = wg[i];
+    const int nty = n / TY, ntz = n / TZ;
+    const int m = lane & 15, kb = lane >> 4;
+    const uint4* ing = reinterpret_cast<const uint4*>(in);
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        __syncthreads();  // the previous tile's readers are done with the halo
+        for (int i = tid; i < HVOX * C8; i += 256) {
+            const int c8 = i % C8, hv = i / C8;
+            const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
+            const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n), gz = wrap_halo(z0 + hz - 1, n);
+            sh[i] = ing[(((long)gx * n + gy) * n + gz) * C8 + c8];
+        }
+        __syncthreads();
+        f32x4 acc[4][NB];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[r][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int k = ks * 32 + kb * 8;
+            const int tap = k / CINP, c0 = k % CINP;
+            Frag8 bf[NB], af[4];
+            if (tap < 27) {
+                const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) bf[b].u = sw[((b * 16 + m) * 27 + tap) * C8 + c0 / 8];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int hv = ((wave + 1 + dx) * HY + (r + 1 + dy)) * HZ + (m + 1 + dz);
+                    af[r].u = sh[hv * C8 + c0 / 8];
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) bf[b].u = make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) af[r].u = make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r].v, bf[b].v, acc[r][b], 0, 0, 0);
+        }
+        // lane holds voxels z0 + 4 kb + q of the row, output channel co = 16 b + m
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long vrow = ((long)(x0 + wave) * n + (y0 + r)) * n + z0 + 4 * kb;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int co = b * 16 + m;
+                const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const long o = (vrow + q) * COP + co;
+                    const float z = acc[r][b][q] + bb;
+                    if (EPI == EPI_ZA) {
+                        out[o] = (uint16_t)f2bf(z);
+                        out2[o] = (uint16_t)f2bf(silu_f(z));
+                    } else if (EPI == EPI_A) {
+                        out[o] = (uint16_t)f2bf(silu_f(z));
+                    } else {
+                        out[o] = (uint16_t)f2bf(z * silu_g(bf2f(prev[o])));
+                    }
+                }
+            }
+        }
+    }
+}
+
+static long conv_tiles(int n) { return (long)(n / TX) * (n / TY) * (n / TZ); }
+
+template <int CINP, int NB, int EPI>
+static hipError_t run_conv(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, uint16_t* out2,
+                           const uint16_t* prev, int n, hipStream_t st) {
+    const long tiles = conv_tiles(n);
+    const size_t lds = (size_t)16 * NB * 27 * CINP * 2 + (size_t)HVOX * CINP * 2;
+    auto kern = k_conv3_mfma<CINP, NB, EPI>;
+    if (hipError_t e = allow_lds_lc(kern, lds); e != hipSuccess) return e;
+    ProfScope ps(PROF_LC_CONV, st);
+    hipLaunchKernelGGL(kern, dim3((unsigned)std::min<long>(tiles, 4096)), dim3(256), lds, st, in, w, bias, out, out2,
+                       prev, n, (int)tiles);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ weight gradient
+
+constexpr int SDZ = TV + 8;       // padded channel row of the staged upstream gradient
+constexpr int SXP = HVOX + 8;     // padded channel row of the staged input halo
+
+// dW[co][ci][tap] += sum_v dZ[v][co] X[v + d_tap][ci] and db[co] += sum_v dZ[v][co] over the
+// tiles of this block: MFMA with M = output channels, N = input channels, K = 32 voxels (two
+// 16-voxel z rows); wave w owns the taps w, w + 4, ...; one atomic flush per block.
+template <int CINP, int MB>
+__global__ void __launch_bounds__(256) k_conv3_wgrad(const uint16_t* __restrict__ dz, const uint16_t* __restrict__ x,
+                                                     float* dw, float* db, int n, int cin, int tiles) {
+    constexpr int COP = 16 * MB;
+    constexpr int NBN = (CINP + 15) / 16;
+    constexpr int TPW = 7;
+    extern __shared__ uint4 smem[];
+    uint16_t* sdz = reinterpret_cast<uint16_t*>(smem);  // [COP][SDZ], channel-major
+    uint16_t* sx = sdz + COP * SDZ;                      // [CINP][SXP], channel-major
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kb = lane >> 4;
+    const int nty = n / TY, ntz = n / TZ;
+    const uint4* dzg = reinterpret_cast<const uint4*>(dz);
+    const uint4* xg = reinterpret_cast<const uint4*>(x);
+    f32x4 acc[TPW][MB][NBN];
+#pragma unroll
+    for (int a = 0; a < TPW; ++a)
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NBN; ++j) acc[a][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.0f;
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        __syncthreads();
+        for (int i = tid; i < TV * (COP / 8); i += 256) {
+            const int c8 = i % (COP / 8), tv = i / (COP / 8);
+            const int lz = tv % TZ, ly = (tv / TZ) % TY, lx = tv / (TZ * TY);
+            const long v = ((long)(x0 + lx) * n + (y0 + ly)) * n + (z0 + lz);
+            Frag8 f;
+            f.u = dzg[v * (COP / 8) + c8];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) sdz[(c8 * 8 + h) * SDZ + tv] = f.h[h];
+        }
+        for (int i = tid; i < HVOX * (CINP / 8); i += 256) {
+            const int c8 = i % (CINP / 8), hv = i / (CINP / 8);
+            const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
+            const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n), gz = wrap_halo(z0 + hz - 1, n);
+            Frag8 f;
+            f.u = xg[(((long)gx * n + gy) * n + gz) * (CINP / 8) + c8];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) sx[(c8 * 8 + h) * SXP + hv] = f.h[h];
+        }
+        __syncthreads();
+        if (tid < COP) {
+            float s = 0.0f;
+            for (int tv = 0; tv < TV; ++tv) s += bf2f(sdz[tid * SDZ + tv]);
+            bacc += s;
+        }
+        for (int ksv = 0; ksv < TV / 32; ++ksv) {
+            const int row = ksv * 2 + (kb >> 1), zh = (kb & 1) * 8;  // voxels z = zh .. zh + 7 of row
+            const int lx = row / TY, ly = row % TY;
+            Frag8 af[MB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                af[i].u = *reinterpret_cast<const uint4*>(sdz + (i * 16 + m) * SDZ + row * TZ + zh);
+#pragma unroll
+            for (int a = 0; a < TPW; ++a) {
+                const int tap = wave + 4 * a;
+                if (tap < 27) {
+                    const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dzz = tap % 3 - 1;
+                    const int hv0 = ((lx + 1 + dx) * HY + (ly + 1 + dy)) * HZ + (zh + 1 + dzz);
+#pragma unroll
+                    for (int j = 0; j < NBN; ++j) {
+                        const int ci = j * 16 + m;
+                        Frag8 bfr;
+                        if (ci < CINP) {
+                            const uint16_t* p = sx + ci * SXP + hv0;
+                            uint32_t t8[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) t8[q] = p[q];
+                            bfr.u = pack8(t8);
+                        } else {
+                            bfr.u = make_uint4(0, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int i = 0; i < MB; ++i)
+                            acc[a][i][j] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i].v, bfr.v, acc[a][i][j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // flush: lane holds rows co = 16 i + 4 kb + q, column ci = 16 j + m
+#pragma unroll
+    for (int a = 0; a < TPW; ++a) {
+        const int tap = wave + 4 * a;
+        if (tap < 27) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < NBN; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int co = i * 16 + 4 * kb + q, ci = j * 16 + m;
+                        if (ci < cin) atomicAdd(&dw[((long)co * cin + ci) * 27 + tap], acc[a][i][j][q]);
+                    }
+        }
+    }
+    if (tid < COP) atomicAdd(&db[tid], bacc);
+}
+
+template <int CINP, int MB>
+static hipError_t run_wgrad(const uint16_t* dz, const uint16_t* x, float* dw, float* db, int n, int cin,
+                            hipStream_t st) {
+    const long tiles = conv_tiles(n);
+    const size_t lds = (size_t)16 * MB * SDZ * 2 + (size_t)CINP * SXP * 2;
+    auto kern = k_conv3_wgrad<CINP, MB>;
+    if (hipError_t e = allow_lds_lc(kern, lds); e != hipSuccess) return e;
+    ProfScope ps(PROF_LC_WGRAD, st);
+    hipLaunchKernelGGL(kern, dim3((unsigned)std::min<long>(tiles, 1024)), dim3(256), lds, st, dz, x, dw, db, n, cin,
+                       (int)tiles);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ input packing, output layer
+
+__device__ __forceinline__ long mesh_off(long v, int n, long row) {
+    const long r = v / n;
+    return r * row + (v - r * n);
+}
+
+__global__ void k_lc_pack(const float* delta, const float* gx, const float* gy, const float* gz, long row, int n,
+                          float s0, float s1, float s2, float s3, uint16_t* x0) {
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long)n * n * n) return;
+    const long o = mesh_off(v, n, row);
+    reinterpret_cast<uint4*>(x0)[v] = make_uint4(f2bf(delta[o] * s0) | (f2bf(gx[o] * s1) << 16),
+                                                 f2bf(gy[o] * s2) | (f2bf(gz[o] * s3) << 16), 0u, 0u);
+}
+
+__global__ void k_lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* x0) {
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long)n * n * n) return;
+    reinterpret_cast<uint4*>(x0)[v] = make_uint4(f2bf(delta[mesh_off(v, n, row)] * s0), 0u, 0u, 0u);
+}
+
+__global__ void k_lc_pack_force(const float* gx, const float* gy, const float* gz, long row, int n, float s1,
+                                float s2, float s3, uint16_t* x0) {
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long)n * n * n) return;
+    const long o = mesh_off(v, n, row);
+    uint4* p = reinterpret_cast<uint4*>(x0) + v;
+    const uint32_t d = (*p).x & 0xffffu;
+    *p = make_uint4(d | (f2bf(gx[o] * s1) << 16), f2bf(gy[o] * s2) | (f2bf(gz[o] * s3) << 16), 0u, 0u);
+}
+
+// dF[c] = (W3 A2[v] + b3) * out_scale, written to (or added into) three meshes of `row` floats per row.
+template <int C>
+__global__ void k_lc_out(const uint16_t* a2, const float* w3, const float* b3, float out_scale, int n, long row,
+                         float* fx, float* fy, float* fz, int accumulate) {
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long)n * n * n) return;
+    float y0 = b3[0], y1 = b3[1], y2 = b3[2];
+    const uint4* p = reinterpret_cast<const uint4*>(a2 + v * C);
+#pragma unroll
+    for (int c8 = 0; c8 < C / 8; ++c8) {
+        Frag8 f;
+        f.u = p[c8];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const float a = bf2f(f.h[h]);
+            const int co = c8 * 8 + h;
+            y0 += w3[co] * a;
+            y1 += w3[C + co] * a;
+            y2 += w3[2 * C + co] * a;
+        }
+    }
+    const long o = mesh_off(v, n, row);
+    if (accumulate) {
+        fx[o] += y0 * out_scale;
+        fy[o] += y1 * out_scale;
+        fz[o] += y2 * out_scale;
+    } else {
+        fx[o] = y0 * out_scale;
+        fy[o] = y1 * out_scale;
+        fz[o] = y2 * out_scale;
+    }
+}
+
+// Backward of the output layer: dY = d_dF * out_scale; dZ2 = (W3^T dY) silu'(Z2);
+// dW3 += sum_v dY A2^T, db3 += sum_v dY (wave shuffles, then one atomic per value and block).
+template <int C>
+__global__ void __launch_bounds__(256) k_lc_out_back(const float* ddf, const uint16_t* z2, const float* w3,
+                                                     float out_scale, int n, uint16_t* dz2, float* dw3, float* db3) {
+    constexpr int NV = 3 * (C + 1);
+    __shared__ float red[4][NV];
+    const long V = (long)n * n * n;
+    float part[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) part[i] = 0.0f;
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (long)gridDim.x * blockDim.x) {
+        const float dy0 = ddf[v] * out_scale, dy1 = ddf[V + v] * out_scale, dy2 = ddf[2 * V + v] * out_scale;
+        part[0] += dy0;
+        part[C + 1] += dy1;
+        part[2 * (C + 1)] += dy2;
+        const uint4* zp = reinterpret_cast<const uint4*>(z2 + v * C);
+        uint4* dp = reinterpret_cast<uint4*>(dz2 + v * C);
+#pragma unroll
+        for (int c8 = 0; c8 < C / 8; ++c8) {
+            Frag8 f;
+            f.u = zp[c8];
+            uint32_t t[8];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const int co = c8 * 8 + h;
+                const float z = bf2f(f.h[h]);
+                const float a = silu_f(z);
+                const float da = w3[co] * dy0 + w3[C + co] * dy1 + w3[2 * C + co] * dy2;
+                t[h] = f2bf(da * silu_g(z));
+                part[1 + co] += dy0 * a;
+                part[C + 2 + co] += dy1 * a;
+                part[2 * C + 3 + co] += dy2 * a;
+            }
+            dp[c8] = pack8(t);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        float s = part[i];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) red[wave][i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NV; i += blockDim.x) {
+        const float s = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+        const int c = i / (C + 1), j = i % (C + 1);
+        if (j == 0) atomicAdd(&db3[c], s);
+        else atomicAdd(&dw3[c * C + j - 1], s);
+    }
+}
+
+// ------------------------------------------------------------------ particle loss
+
+__device__ __forceinline__ void cic_abs(float pos, float inv_h, int n, int& i0, int& i1, float& f) {
+    const float u = pos * inv_h;
+    const float fl = floorf(u);
+    f = u - fl;
+    int m = (int)fl % n;
+    m = m < 0 ? m + n : m;
+    m = min(max(m, 0), n - 1);  // a non-finite position still maps inside the mesh
+    i0 = m;
+    i1 = m + 1 == n ? 0 : m + 1;
+}
+
+// stats[1] += sum_p |g3 - g1|^2  (float64)
+__global__ void k_lc_denom(const float* g1x, const float* g1y, const float* g1z, const float* g3x,
+                           const float* g3y, const float* g3z, long np, double* stats) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (long)gridDim.x * blockDim.x) {
+        const double a = g3x[p] - g1x[p], b = g3y[p] - g1y[p], c = g3z[p] - g1z[p];
+        s += a * a + b * b + c * c;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&stats[1], red[0]);
+}
+
+// r_p = g1 + G[dF]_p - g3;  stats[0] += |r|^2 / denom;  d_dF += G^T (2 r / denom)  (G = CIC gather
+// at absolute positions on the dense n^3 mesh).
+__global__ void k_lc_loss(const float* px, const float* py, const float* pz, long np, int n, float inv_h,
+                          const float* dfx, const float* dfy, const float* dfz, const float* g1x, const float* g1y,
+                          const float* g1z, const float* g3x, const float* g3y, const float* g3z, double* stats,
+                          float* ddf) {
+    __shared__ double red[256];
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double l2 = 0.0;
+    if (p < np) {
+        int ix0, ix1, iy0, iy1, iz0, iz1;
+        float fx, fy, fz;
+        cic_abs(px[p], inv_h, n, ix0, ix1, fx);
+        cic_abs(py[p], inv_h, n, iy0, iy1, fy);
+        cic_abs(pz[p], inv_h, n, iz0, iz1, fz);
+        const int ix[2] = {ix0, ix1}, iy[2] = {iy0, iy1}, iz[2] = {iz0, iz1};
+        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const long v = ((long)ix[a] * n + iy[b]) * n + iz[c];
+                    const float w = wx[a] * wy[b] * wz[c];
+                    g0 += w * dfx[v];
+                    g1 += w * dfy[v];
+                    g2 += w * dfz[v];
+                }
+        const float r0 = g1x[p] + g0 - g3x[p], r1 = g1y[p] + g1 - g3y[p], r2 = g1z[p] + g2 - g3z[p];
+        const double inv = 1.0 / stats[1];
+        l2 = ((double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2) * inv;
+        const float s = (float)(2.0 * inv);
+        const long V = (long)n * n * n;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const long v = ((long)ix[a] * n + iy[b]) * n + iz[c];
+                    const float w = wx[a] * wy[b] * wz[c] * s;
+                    atomicAdd(&ddf[v], w * r0);
+                    atomicAdd(&ddf[V + v], w * r1);
+                    atomicAdd(&ddf[2 * V + v], w * r2);
+                }
+    }
+    red[threadIdx.x] = l2;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&stats[0], red[0]);
+}
+
+// ------------------------------------------------------------------ Adam, weight packing
+
+// Adam (Kingma & Ba 2015) on FP32 master parameters with bias corrections c1 = 1 - b1^t,
+// c2 = 1 - b2^t; the gradient is cleared for the next accumulation.
+__global__ void k_lc_adam(float* p, float* g, float* m, float* v, long np, float lr, float b1, float b2, float eps,
+                          float c1, float c2) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        g[i] = 0.0f;
+    }
+}
+
+//   wb1[co][tap][ci < 8] = w1[co][ci][tap] (0 for ci >= 4);  wb2[co][tap][ci] = w2[co][ci][tap];
+//   wt2[ci][tap][co] = w2[co][ci][26 - tap]   (offset -d: the data gradient of layer 2).
+__global__ void k_lc_pack_weights(const float* w1, const float* w2, int C, uint16_t* wb1, uint16_t* wb2,
+                                  uint16_t* wt2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C * 27 * 8) {
+        const int ci = i % 8, tap = (i / 8) % 27, co = i / (8 * 27);
+        wb1[i] = ci < 4 ? (uint16_t)f2bf(w1[(co * 4 + ci) * 27 + tap]) : (uint16_t)0;
+    }
+    if (i < C * 27 * C) {
+        const int c_in = i % C, tap = (i / C) % 27, c_out = i / (C * 27);
+        wb2[i] = (uint16_t)f2bf(w2[(c_out * C + c_in) * 27 + tap]);
+        // transposed weights: output channel c_out of the data gradient is input channel c_out of
+        // layer 2, its input channel c_in is layer 2's output channel c_in
+        wt2[i] = (uint16_t)f2bf(w2[(c_in * C + c_out) * 27 + (26 - tap)]);
+    }
+}
+
+// ------------------------------------------------------------------ positions, gather, copies
+
+__global__ void k_positions(const float* x, long n_per_real, long total, int n_part, int axis, float cell, float qoff,
+                            float box, float* pos) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const long idx = i % n_per_real;
+    const long np2 = (long)n_part * n_part;
+    const int id = axis == 0 ? (int)(idx / np2) : (axis == 1 ? (int)((idx / n_part) % n_part) : (int)(idx % n_part));
+    float u = (float)id * cell + qoff + x[i];
+    u -= box * floorf(u / box);
+    pos[i] = u >= box ? u - box : u;
+}
+
+__global__ void k_gather_abs(const float* px, const float* py, const float* pz, long np, int n, float inv_h,
+                             const float* fx, const float* fy, const float* fz, long row, float* ox, float* oy,
+                             float* oz) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    float ux, uy, uz;
+    cic_abs(px[p], inv_h, n, ix0, ix1, ux);
+    cic_abs(py[p], inv_h, n, iy0, iy1, uy);
+    cic_abs(pz[p], inv_h, n, iz0, iz1, uz);
+    const int ix[2] = {ix0, ix1}, iy[2] = {iy0, iy1}, iz[2] = {iz0, iz1};
+    const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const long o = ((long)ix[a] * n + iy[b]) * row + iz[c];
+                const float w = wx[a] * wy[b] * wz[c];
+                g0 += w * fx[o];
+                g1 += w * fy[o];
+                g2 += w * fz[o];
+            }
+    ox[p] = g0;
+    oy[p] = g1;
+    oz[p] = g2;
+}
+
+__global__ void k_mesh_unpad(const float* src, long row, int n, float* dst) {
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long)n * n * n) return;
+    dst[v] = src[mesh_off(v, n, row)];
+}
+
+// ------------------------------------------------------------------ host launchers
+
+hipError_t lc_pack_weights(const float* w1, const float* w2, int C, uint16_t* wb1, uint16_t* wb2, uint16_t* wt2,
+                           hipStream_t st) {
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_pack_weights, dim3(blocks_for((long)C * 27 * std::max(C, 8), 256)), dim3(256), 0, st,
+                       w1, w2, C, wb1, wb2, wt2);
+    return hipGetLastError();
+}
+
+hipError_t lc_pack(const float* delta, const float* const g[3], long row, int n, const float in_scale[4],
+                   uint16_t* x0, hipStream_t st) {
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_pack, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, delta, g[0], g[1], g[2],
+                       row, n, in_scale[0], in_scale[1], in_scale[2], in_scale[3], x0);
+    return hipGetLastError();
+}
+
+hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* x0, hipStream_t st) {
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_pack_delta, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, delta, row, n, s0,
+                       x0);
+    return hipGetLastError();
+}
+
+hipError_t lc_pack_force(const float* const g[3], long row, int n, const float s[3], uint16_t* x0, hipStream_t st) {
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_pack_force, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, g[0], g[1], g[2],
+                       row, n, s[0], s[1], s[2], x0);
+    return hipGetLastError();
+}
+
+template <int C>
+static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
+                            int accumulate, bool keep_z, hipStream_t st) {
+    constexpr int NB = C / 16;
+    hipError_t e = keep_z ? run_conv<8, NB, EPI_ZA>(A.x0, P.wb1, P.b1, A.z1, A.a1, nullptr, n, st)
+                          : run_conv<8, NB, EPI_A>(A.x0, P.wb1, P.b1, A.a1, nullptr, nullptr, n, st);
+    if (e != hipSuccess) return e;
+    e = keep_z ? run_conv<C, NB, EPI_ZA>(A.a1, P.wb2, P.b2, A.z2, A.a2, nullptr, n, st)
+               : run_conv<C, NB, EPI_A>(A.a1, P.wb2, P.b2, A.a2, nullptr, nullptr, n, st);
+    if (e != hipSuccess) return e;
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_out<C>, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, A.a2, P.w3, P.b3,
+                       out_scale, n, row, out[0], out[1], out[2], accumulate);
+    return hipGetLastError();
+}
+
+hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
+                      int accumulate, bool keep_z, hipStream_t st) {
+    if (P.C == 16) return forward_c<16>(P, A, n, out_scale, out, row, accumulate, keep_z, st);
+    if (P.C == 32) return forward_c<32>(P, A, n, out_scale, out, row, accumulate, keep_z, st);
+    return hipErrorInvalidValue;
+}
+
+template <int C>
+static hipError_t backward_c(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, const float* ddf,
+                             hipStream_t st) {
+    constexpr int NB = C / 16;
+    const long V = (long)n * n * n;
+    {
+        ProfScope ps(PROF_LC_MISC, st);
+        hipLaunchKernelGGL(k_lc_out_back<C>, dim3((unsigned)std::min<long>(blocks_for(V, 256), 1024)), dim3(256), 0,
+                           st, ddf, A.z2, P.w3, out_scale, n, A.dz2, G.w3, G.b3);
+        if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    }
+    if (hipError_t e = run_wgrad<C, NB>(A.dz2, A.a1, G.w2, G.b2, n, C, st); e != hipSuccess) return e;
+    if (hipError_t e = run_conv<C, NB, EPI_DSILU>(A.dz2, P.wt2, nullptr, A.dz1, nullptr, A.z1, n, st); e != hipSuccess)
+        return e;
+    return run_wgrad<8, NB>(A.dz1, A.x0, G.w1, G.b1, n, 4, st);
+}
+
+hipError_t lc_backward(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, const float* ddf,
+                       hipStream_t st) {
+    if (P.C == 16) return backward_c<16>(P, A, G, n, out_scale, ddf, st);
+    if (P.C == 32) return backward_c<32>(P, A, G, n, out_scale, ddf, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t lc_loss(const float* const pos[3], long np, int n, double box, const float* const df[3],
+                   const float* const g1[3], const float* const g3[3], double* stats, float* ddf,
+                   hipStream_t st) {
+    hipError_t e = launch_fill_d(stats, 2, 0.0, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_fill(ddf, 3L * n * n * n, 0.0f, st)) != hipSuccess) return e;
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_denom, dim3((unsigned)std::min<long>(blocks_for(np, 256), 1024)), dim3(256), 0, st,
+                       g1[0], g1[1], g1[2], g3[0], g3[1], g3[2], np, stats);
+    hipLaunchKernelGGL(k_lc_loss, dim3(blocks_for(np, 256)), dim3(256), 0, st, pos[0], pos[1], pos[2], np, n,
+                       (float)(n / box), df[0], df[1], df[2], g1[0], g1[1], g1[2], g3[0], g3[1], g3[2], stats, ddf);
+    return hipGetLastError();
+}
+
+hipError_t lc_adam(float* p, float* g, float* m, float* v, long np, float lr, float b1, float b2, float eps, int t,
+                   hipStream_t st) {
+    const float c1 = (float)(1.0 - std::pow((double)b1, t)), c2 = (float)(1.0 - std::pow((double)b2, t));
+    ProfScope ps(PROF_LC_MISC, st);
+    hipLaunchKernelGGL(k_lc_adam, dim3((unsigned)std::min<long>(blocks_for(np, 256), 4096)), dim3(256), 0, st, p, g,
+                       m, v, np, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t lc_positions(const float* const x[3], long n_per_real, int n_real, int n_part, double box, double qoff,
+                        float* const pos[3], hipStream_t st) {
+    const long total = n_per_real * n_real;
+    ProfScope ps(PROF_LC_MISC, st);
+    for (int d = 0; d < 3; ++d)
+        hipLaunchKernelGGL(k_positions, dim3(blocks_for(total, 256)), dim3(256), 0, st, x[d], n_per_real, total,
+                           n_part, d, (float)(box / n_part), (float)qoff, (float)box, pos[d]);
+    return hipGetLastError();
+}
+
+hipError_t gather_absolute(const float* const pos[3], long np, int n, double box, const float* const f[3], long row,
+                           float* const out[3], hipStream_t st) {
+    ProfScope ps(PROF_GATHER, st);
+    hipLaunchKernelGGL(k_gather_abs, dim3(blocks_for(np, 256)), dim3(256), 0, st, pos[0], pos[1], pos[2], np, n,
+                       (float)(n / box), f[0], f[1], f[2], row, out[0], out[1], out[2]);
+    return hipGetLastError();
+}
+
+hipError_t mesh_unpad(const float* src, long row, int n, float* dst, hipStream_t st) {
+    ProfScope ps(PROF_COPY, st);
+    hipLaunchKernelGGL(k_mesh_unpad, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, src, row, n, dst);
+    return hipGetLastError();
+}
+
+}  // namespace cola

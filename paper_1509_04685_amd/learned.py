@@ -1,0 +1,140 @@
+"""Training and use of the learned coarse-mesh force correction (cola_lc_* in include/cola.h).
+
+Sec. 4.4 finds that a force mesh coarser than PM_grid = 3 biases haloes through the force
+resolution; this module trains the library's correction network so that a PM_grid = 1 run
+approaches the PM_grid = 3 one.  Training pairs come from the method itself: at every chosen node
+of a plain fine-mesh run, the particle positions and the fine-mesh acceleration there (the
+target); the coarse-mesh fields of the same positions are the network's input.  The loss is the
+particle-level relative residual
+
+    L = sum_p |g1_p + G[dF]_p - g3_p|^2 / sum_p |g3_p - g1_p|^2
+
+(1 without the network).  Every computation runs in libcola's kernels; this module only chooses
+samples, holds device buffers and reads back scalars.  The input and output scales are set once
+from the first sample on the host (root mean squares).
+"""
+
+import numpy as np
+
+from . import (LcNet, ParticleState, Workspace, ic_2lpt, lc_backward, lc_forward, lc_loss, lc_workspace,
+               make_problem, pm_fields, positions, power_spectrum, schedule_table, step, step_lc)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Sample:
+    """One training pair: positions, fine-mesh acceleration, and the coarse-mesh fields."""
+
+    def __init__(self, pos, acc_fine, n_coarse, box, ws=None):
+        f = pm_fields(pos, n_coarse, box, ws=ws)
+        self.pos = pos
+        self.acc_fine = acc_fine
+        self.delta = f["delta"]
+        self.g = f["g"]
+        self.acc = f["acc"]
+
+
+def make_samples(cosmo, box, n_part, pm_fine, n_steps, z_init, seeds, nodes=None):
+    """Plain fine-mesh runs for each seed; a Sample (coarse mesh = N_p cells) at each node in
+    `nodes` (default: all)."""
+    prob = make_problem(box, n_part, pm_fine, z_init, n_steps)
+    st = ParticleState(prob)
+    ws = Workspace(prob)
+    out = []
+    for seed in seeds:
+        ic_2lpt(prob, cosmo, [int(seed)], st, ws)
+        for j in range(n_steps):
+            if j > st.node:
+                step(prob, cosmo, st, j, ws)
+            if nodes is None or j in nodes:
+                pos = positions(prob, st)
+                acc_fine = pm_fields(pos, n_part * pm_fine, box, delta=False, g=False)["acc"]
+                out.append(Sample(pos, acc_fine, n_part, box))
+    return out
+
+
+def scales_from(sample):
+    """Input scales 1/rms of delta and of each force component, output scale rms(g_fine - g)."""
+    d = sample.delta.double().cpu().numpy()
+    g = sample.g.double().cpu().numpy()
+    r = (sample.acc_fine - sample.acc).double().cpu().numpy()
+    ins = [1.0 / max(np.sqrt(np.mean(d ** 2)), 1e-30)]
+    ins += [1.0 / max(np.sqrt(np.mean(g[c] ** 2)), 1e-30) for c in range(3)]
+    return tuple(float(np.float32(s)) for s in ins), float(np.float32(np.sqrt(np.mean(r ** 2))))
+
+
+class Trainer:
+    """Adam on mini-batches of samples (gradients summed over the batch)."""
+
+    def __init__(self, net, n_coarse, box):
+        torch = _torch()
+        self.net = net
+        self.n = int(n_coarse)
+        self.box = float(box)
+        n = self.n
+        self.ws = lc_workspace(n, net.channels, 1, training=True)
+        self.df = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+        self.d_df = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+        self.stats = torch.empty(2, dtype=torch.float64, device="cuda")
+
+    def loss(self, s, training=False):
+        lc_forward(self.net, s.delta, s.g, self.ws, df=self.df, training=training)
+        lc_loss(s.pos, self.box, self.df, s.acc, s.acc_fine, self.stats, self.d_df)
+        return self.stats
+
+    def train(self, samples, iters, lr, batch=1, seed=0, lr_final=None):
+        """Returns the per-iteration mean batch loss (host array)."""
+        torch = _torch()
+        rng = np.random.default_rng(seed)
+        hist = torch.zeros(iters, dtype=torch.float64, device="cuda")
+        for it in range(iters):
+            for _ in range(batch):
+                s = samples[int(rng.integers(len(samples)))]
+                st = self.loss(s, training=True)
+                lc_backward(self.net, self.d_df, self.ws)
+                hist[it:it + 1].add_(st[0:1] / batch)
+            rate = lr if lr_final is None else lr * (lr_final / lr) ** (it / max(1, iters - 1))
+            self.net.adam(rate)
+        return hist.cpu().numpy()
+
+    def evaluate(self, samples):
+        """Mean loss over samples (no parameter change)."""
+        vals = []
+        for s in samples:
+            vals.append(float(self.loss(s).cpu()[0]))
+        return float(np.mean(vals))
+
+
+def new_net(sample, channels=16, seed=0):
+    from . import lc_init_params
+    ins, outs = scales_from(sample)
+    return LcNet(channels, params=lc_init_params(channels, seed), in_scale=ins, out_scale=outs)
+
+
+def run_spectra(prob, cosmo, seed, a_out, n_pk, n_bins, net=None):
+    """One realization from its 2LPT ICs to the last node, with the network's correction when
+    `net` is given; returns the P(k) (k_mean, pk) at each a_out as host arrays."""
+    st = ParticleState(prob)
+    ws = Workspace(prob, n_pk=n_pk)
+    lws = lc_workspace(prob.n_part * prob.pm_factor, net.channels, prob.n_real) if net is not None else None
+    ic_2lpt(prob, cosmo, [int(seed)], st, ws)
+    tab = schedule_table(prob, cosmo)
+    out = []
+
+    def advance(j):
+        if j > st.node:
+            if net is None:
+                step(prob, cosmo, st, j, ws)
+            else:
+                step_lc(prob, cosmo, st, j, net, lws, ws)
+
+    for a in a_out:
+        j = int((tab[:, 0] <= a * (1 + 1e-12)).sum()) - 1
+        advance(j)
+        km, pk, _ = power_spectrum(prob, cosmo, st, a, n_pk, n_bins, ws)
+        out.append((km.cpu().numpy()[0], pk.cpu().numpy()[0]))
+    advance(prob.n_steps - 1)
+    return out

@@ -85,3 +85,58 @@ def test_loss_is_one_without_correction():
     net, delta, g, box, pos, g1, g3 = _setup()
     zero = np.zeros((3,) + delta.shape)
     assert L.particle_loss(zero, pos, box, g1, g3)[0] == pytest.approx(1.0)
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    # From m = v = 0 the bias corrections give m_hat = g and v_hat = g^2 exactly, so the first
+    # update is -lr g / (|g| + eps): a step of lr against the sign of each gradient.
+    rng = np.random.default_rng(11)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50) * 10.0 ** rng.uniform(-3, 3, size=50)
+    lr, eps = 1e-2, 1e-15
+    p1, m, v = L.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr, eps=eps)
+    assert np.allclose(p1 - p, -lr * np.sign(g), rtol=1e-7, atol=0)
+
+
+def test_adam_constant_gradient_keeps_unit_steps():
+    # With the same gradient at every step, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    # bias-corrected ratio is g / |g| at every t.
+    rng = np.random.default_rng(12)
+    p = rng.normal(size=20)
+    g = rng.normal(size=20)
+    m = np.zeros(20)
+    v = np.zeros(20)
+    lr = 3e-3
+    for t in range(1, 30):
+        p_new, m, v = L.adam_step(p, g, m, v, t, lr, eps=1e-14)
+        assert np.allclose(p_new - p, -lr * np.sign(g), rtol=1e-8, atol=0), t
+        p = p_new
+
+
+def test_corrected_accel_reduces_to_pm_force():
+    from oracle import pm
+    rng = np.random.default_rng(13)
+    n, box = 8, 20.0
+    pos = rng.uniform(0, box, size=(3, 300))
+    net = L.Net(channels=4, seed=5, out_scale=0.5)
+    net.w3[:] = 0.0
+    base = pm.pm_accel(pos, n, box)
+    assert np.allclose(L.corrected_accel(net, pos, n, box), base, rtol=0, atol=1e-12)
+    # a constant output (bias only) shifts every particle's force by bias * out_scale, since the
+    # CIC weights of each particle sum to one
+    net.b3[:] = [1.0, -2.0, 0.25]
+    shifted = L.corrected_accel(net, pos, n, box)
+    assert np.allclose(shifted - base, (net.b3 * 0.5)[:, None], rtol=0, atol=1e-12)
+
+
+def test_flat_params_roundtrip_and_order():
+    net = L.Net(channels=4, seed=6)
+    flat = L.flat_params(net)
+    c = 4
+    assert flat.size == 27 * c * c + 113 * c + 3
+    assert np.array_equal(flat[:108 * c], net.w1.ravel())
+    assert np.array_equal(flat[-3:], net.b3)
+    other = L.Net(channels=4, seed=7)
+    L.set_flat_params(other, flat)
+    for a, b in zip(net.params(), other.params()):
+        assert np.array_equal(a, b)
