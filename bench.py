@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--workload", default="plain_256_768")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-seed ensemble measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
     ap.add_argument("--profile-step", action="store_true",
                     help="for hardware counters: autotune, ICs, one COLA step, one 1 GiB copy; no timing")
@@ -59,7 +60,9 @@ def algorithmic_bytes(kind, n_g, n_part, n_pk):
     Gk = n_pk ** 3
     Ck = n_pk * n_pk * (n_pk // 2 + 1)
     table = {
-        "cic_deposit": 12 * N + 4 * G,          # displacements in, density mesh out
+        "cic_deposit": 32 * N,                  # binning: displacements in; tile key + cell record out
+        "cic_sort": 36 * N,                     # scatter: key + record in, record out (scans: O(G/512))
+        "cic_tile": 16 * N + 4 * G,             # sorted records in, density mesh out
         "fft_z_r2c": 4 * G + 8 * C,
         "fft_y_forward": 16 * C,
         "fft_x_green": 8 * C + 16 * C,          # one spectrum in, two x-transformed outputs
@@ -68,7 +71,8 @@ def algorithmic_bytes(kind, n_g, n_part, n_pk):
         "fft_z_c2r": 8 * C + 4 * G,
         "gather_kick_drift": 12 * G + 72 * N,   # 3 force meshes; x,p,psi1,psi2 in; x,p out
         "gather_kick": 12 * G + 60 * N,
-        "pk_deposit": 12 * G + 84 * N + 4 * Gk,
+        "pk_deposit": 12 * G + 68 * N,          # binning with the partial drift: x, p, psi1, psi2 and
+                                                # the force meshes in; key + record out
     }
     if n_pk == n_g:
         table["fft_x_forward"] = 16 * C
@@ -182,6 +186,67 @@ def ensemble_bench(cola, torch, reps):
     cola.ensemble_release()
     torch.cuda.empty_cache()
     return out
+
+
+def learned_bench(cola, torch, cfg_plain, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps):
+    """The learned-correction form: 256^3 particles on the 256^3 (PM_grid = 1) mesh with the trained
+    network, against the plain 3x realization timed above (same seed, same outputs) and the plain
+    1x run without the network."""
+    from paper_1509_04685_amd import learned as L
+    path = os.path.join(ROOT, "paper_1509_04685_amd", "lc_weights_c16.json")
+    if not os.path.exists(path):
+        return {"skipped": "no trained weights (run paper_1509_04685_amd/train_lc.py)"}
+    net, doc = L.load_net(path)
+    c = W.CONFIGS["learned_256_256"]
+    prob = cola.make_problem(c["box"], c["n_part"], c["pm_factor"], c["z_init"], c["n_steps"])
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    table = cola.schedule_table(prob, cosmo)
+    plan = [(a, node_index(table, a)) for a in sorted(a_outs)]
+    st = cola.ParticleState(prob)
+    ws = cola.Workspace(prob, n_pk=n_pk)
+    lws = cola.lc_workspace(c["n_part"] * c["pm_factor"], net.channels, 1)
+    outs = [tuple(torch.empty((1, n_bins), dtype=torch.float64, device="cuda") for _ in range(3))
+            for _ in a_outs]
+
+    def realization(use_net):
+        cola.ic_2lpt(prob, cosmo, [c["seeds"][0]], st, ws)
+
+        def adv(j):
+            if use_net:
+                cola.step_lc(prob, cosmo, st, j, net, lws, ws)
+            else:
+                cola.step(prob, cosmo, st, j, ws)
+        for i, (a, j) in enumerate(plan):
+            adv(j)
+            cola.power_spectrum(prob, cosmo, st, a, n_pk, n_bins, ws, out=outs[i])
+        adv(c["n_steps"] - 1)
+
+    res = {}
+    stream = torch.cuda.current_stream()
+    for name, use_net in (("plain_1x", False), ("learned_1x", True)):
+        cola.autotune(prob, ws, n_pk=n_pk, state=st)
+        realization(use_net)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            realization(use_net)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        k = outs[-1][0].cpu().numpy()[0]
+        pk = outs[-1][1].cpu().numpy()[0]
+        res[name] = {"ms_per_realization": round(ms, 2), "realizations_per_hour": round(3.6e6 / ms, 1),
+                     "max_pk_error_k_lt_1": round(L.max_error(k, pk, pk_plain3), 4)}
+    res["plain_3x"] = {"ms_per_realization": round(ms_plain3, 2), "realizations_per_hour": round(3.6e6 / ms_plain3, 1)}
+    res["speedup_vs_plain_3x"] = round(ms_plain3 / res["learned_1x"]["ms_per_realization"], 3)
+    res["network"] = (f"C={net.channels}: two 3x3x3 conv layers + SiLU, 1x1x1 output; BF16 matrix cores, "
+                      f"FP32 accumulation; validation loss {doc['val_loss_initial']:.3f} -> "
+                      f"{doc['val_loss_trained']:.3f}")
+    res["workload"] = (f"256^3 particles, 256^3 mesh (PM_grid 1), box 768, 40 nodes from z=19, seed "
+                       f"{c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = max over 0<k<1 h/Mpc "
+                       f"of |P/P_plain3x - 1| at z=0")
+    return res
 
 
 def main():
@@ -304,6 +369,11 @@ def main():
                    "step_unit": "one realization (ICs + all nodes + P(k) outputs)"},
         "roofline": roofline,
     }
+    if not args.no_learned:
+        print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
+        result["learned"] = learned_bench(cola, torch, cfg, outs[-1][1].cpu().numpy()[0], a_outs, n_pk, n_bins,
+                                          ms_per_step, reps=2)
+        print(f"[bench] learned: {json.dumps(result['learned'])}", file=sys.stderr, flush=True)
     if not args.no_ensemble:
         del st, ws, outs
         torch.cuda.empty_cache()

@@ -58,9 +58,9 @@ def make_samples(cosmo, box, n_part, pm_fine, n_steps, z_init, seeds, nodes=None
 
 def scales_from(sample):
     """Input scales 1/rms of delta and of each force component, output scale rms(g_fine - g)."""
-    d = sample.delta.double().cpu().numpy()
-    g = sample.g.double().cpu().numpy()
-    r = (sample.acc_fine - sample.acc).double().cpu().numpy()
+    d = sample.delta.cpu().numpy().astype(np.float64)
+    g = sample.g.cpu().numpy().astype(np.float64)
+    r = sample.acc_fine.cpu().numpy().astype(np.float64) - sample.acc.cpu().numpy().astype(np.float64)
     ins = [1.0 / max(np.sqrt(np.mean(d ** 2)), 1e-30)]
     ins += [1.0 / max(np.sqrt(np.mean(g[c] ** 2)), 1e-30) for c in range(3)]
     return tuple(float(np.float32(s)) for s in ins), float(np.float32(np.sqrt(np.mean(r ** 2))))
@@ -87,18 +87,17 @@ class Trainer:
 
     def train(self, samples, iters, lr, batch=1, seed=0, lr_final=None):
         """Returns the per-iteration mean batch loss (host array)."""
-        torch = _torch()
         rng = np.random.default_rng(seed)
-        hist = torch.zeros(iters, dtype=torch.float64, device="cuda")
+        hist = np.zeros(iters)
         for it in range(iters):
             for _ in range(batch):
                 s = samples[int(rng.integers(len(samples)))]
                 st = self.loss(s, training=True)
                 lc_backward(self.net, self.d_df, self.ws)
-                hist[it:it + 1].add_(st[0:1] / batch)
+                hist[it] += float(st.cpu()[0]) / batch
             rate = lr if lr_final is None else lr * (lr_final / lr) ** (it / max(1, iters - 1))
             self.net.adam(rate)
-        return hist.cpu().numpy()
+        return hist
 
     def evaluate(self, samples):
         """Mean loss over samples (no parameter change)."""
@@ -138,3 +137,18 @@ def run_spectra(prob, cosmo, seed, a_out, n_pk, n_bins, net=None):
         out.append((km.cpu().numpy()[0], pk.cpu().numpy()[0]))
     advance(prob.n_steps - 1)
     return out
+
+
+def load_net(path, training=False):
+    """A network from a weights file written by train_lc.py."""
+    import json
+    with open(path) as fh:
+        doc = json.load(fh)
+    return LcNet(int(doc["channels"]), params=np.asarray(doc["params"], dtype=np.float32),
+                 in_scale=doc["in_scale"], out_scale=doc["out_scale"], training=training), doc
+
+
+def max_error(k, pk, pk_ref, k_max=1.0):
+    """max over bins with 0 < k < k_max of |pk / pk_ref - 1| (host arrays)."""
+    sel = (k > 0) & (k < k_max) & (pk_ref > 0)
+    return float(np.abs(pk[sel] / pk_ref[sel] - 1.0).max())
