@@ -51,20 +51,21 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(kind, n_g, n_part, n_pk):
+def algorithmic_bytes(kind, tag, n_g, n_part):
     """Bytes one launch of a kernel kind must move at minimum (one read of its inputs, one
-    write of its outputs), float32 fields, half spectra counted without padding."""
-    G = n_g ** 3
-    C = n_g * n_g * (n_g // 2 + 1)
+    write of its outputs), float32 fields, half spectra counted without padding.  FFT passes are
+    tagged with their mesh side; the other kernels work on the force mesh n_g."""
+    n = tag if tag else n_g
+    G = n ** 3
+    C = n * n * (n // 2 + 1)
     N = n_part ** 3
-    Gk = n_pk ** 3
-    Ck = n_pk * n_pk * (n_pk // 2 + 1)
     table = {
         "cic_deposit": 32 * N,                  # binning: displacements in; tile key + cell record out
         "cic_sort": 36 * N,                     # scatter: key + record in, record out (scans: O(G/512))
         "cic_tile": 16 * N + 4 * G,             # sorted records in, density mesh out
         "fft_z_r2c": 4 * G + 8 * C,
         "fft_y_forward": 16 * C,
+        "fft_x_forward": 16 * C,
         "fft_x_green": 8 * C + 16 * C,          # one spectrum in, two x-transformed outputs
         "fft_y_split": 8 * C + 16 * C,          # one in, two out
         "fft_y_inverse": 16 * C,
@@ -74,10 +75,6 @@ def algorithmic_bytes(kind, n_g, n_part, n_pk):
         "pk_deposit": 12 * G + 68 * N,          # binning with the partial drift: x, p, psi1, psi2 and
                                                 # the force meshes in; key + record out
     }
-    if n_pk == n_g:
-        table["fft_x_forward"] = 16 * C
-    else:
-        table["fft_x_forward"] = 16 * Ck
     return table.get(kind)
 
 
@@ -87,19 +84,28 @@ def node_index(table, a_out):
     return max(0, min(j, len(a) - 1))
 
 
-def source_hash():
+KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h"), "cic": ("deposit_sorted.hip",),
+                  "pk_deposit": ("deposit_sorted.hip",), "gather": ("pm_kernels.hip",), "lc": ("lc_kernels.hip",)}
+
+
+def source_hash(kind):
+    """Hash of the source files of a kernel kind: counters taken on other sources are stale."""
+    files = next((v for k, v in KERNEL_SOURCES.items() if kind.startswith(k)), None)
+    if files is None:
+        return None
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1509_04685_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in files:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(kind, launches_per_step):
-    """HBM bytes per launch from the committed counter summary, if it was taken on this source."""
-    path = os.path.join(ROOT, "profiles", f"{kind}_counters.txt")
+def read_traffic(kind, tag):
+    """HBM bytes per launch from the committed counter summary of this kernel and mesh size, if it
+    was taken on the current source of the kernel."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{tag}_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -108,7 +114,7 @@ def read_traffic(kind, launches_per_step):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != source_hash():
+    if vals.get("source_hash") != source_hash(kind):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -292,6 +298,18 @@ def main():
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         cola.copy(a, b)  # 1 GiB read + 1 GiB write: the counter yardstick
+        del a, b
+        path = os.path.join(ROOT, "paper_1509_04685_amd", "lc_weights_c16.json")
+        if os.path.exists(path):  # one step of the learned 1x form
+            from paper_1509_04685_amd import learned as L
+            net, _ = L.load_net(path)
+            c = W.CONFIGS["learned_256_256"]
+            p1 = cola.make_problem(c["box"], c["n_part"], c["pm_factor"], c["z_init"], c["n_steps"])
+            s1 = cola.ParticleState(p1)
+            w1 = cola.Workspace(p1)
+            lws = cola.lc_workspace(c["n_part"] * c["pm_factor"], net.channels, 1)
+            cola.ic_2lpt(p1, cosmo, [c["seeds"][0]], s1, w1)
+            cola.step_lc(p1, cosmo, s1, 1, net, lws, w1)
         torch.cuda.synchronize()
         print("[bench] profile step done", file=sys.stderr, flush=True)
         return
@@ -317,7 +335,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
-    kernels = cola.profiler_read() if not args.no_profiler else {}
+    kernels = cola.profiler_read_groups() if not args.no_profiler else {}
     cola.profiler_enable(False)
     pk_final = outs[-1][1].cpu().numpy()[0]
     if not np.all(np.isfinite(pk_final)):
@@ -332,21 +350,22 @@ def main():
     roofline = None
     if kernels:
         ranked = sorted(kernels.items(), key=lambda kv: -kv[1][0])
-        for name, (ms, cnt) in ranked:
-            b = algorithmic_bytes(name, n_g, n_part, n_pk)
+        for (name, tag), (ms, cnt) in ranked:
+            b = algorithmic_bytes(name, tag, n_g, n_part)
             gbs = (b / (ms / cnt / 1e3) / 1e9) if b else float("nan")
-            print(f"[bench]   {name:20s} {ms / args.steps:9.2f} ms/step  {cnt // args.steps:5d} launches/step"
+            label = f"{name}@{tag}" if tag else name
+            print(f"[bench]   {label:22s} {ms / args.steps:9.2f} ms/step  {cnt / args.steps:7.1f} launches/step"
                   f"  {ms / cnt:8.3f} ms/launch  {gbs:8.1f} GB/s", file=sys.stderr, flush=True)
-        dom = next((kv for kv in ranked if algorithmic_bytes(kv[0], n_g, n_part, n_pk)), None)
+        dom = next((kv for kv in ranked if algorithmic_bytes(kv[0][0], kv[0][1], n_g, n_part)), None)
         if dom:
-            name, (ms, cnt) = dom
-            b = algorithmic_bytes(name, n_g, n_part, n_pk)
+            (name, tag), (ms, cnt) = dom
+            b = algorithmic_bytes(name, tag, n_g, n_part)
             achieved = b / (ms / cnt / 1e3) / 1e9
-            traffic = read_traffic(name, cnt / args.steps)
+            traffic = read_traffic(name, tag)
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": traffic, "kernel": name, "bytes_per_launch": b,
-                        "ms_per_launch": round(ms / cnt, 4),
+                        "traffic": traffic, "kernel": name, "mesh": tag or n_g, "bytes_per_launch": b,
+                        "ms_per_launch": round(ms / cnt, 4), "launches_per_step": cnt / args.steps,
                         "share_of_step": round(ms / ms_total, 4)}
 
     result = {

@@ -304,6 +304,11 @@ int cola_profiler_enable(int on);
 int cola_profiler_num_kinds(void);
 const char* cola_profiler_kind_name(int kind);
 int cola_profiler_read(int32_t n_kinds, double* total_ms, int64_t* launches);
+/* The same records grouped by (kind, tag), where the tag is a size label (the mesh side for FFT
+ * passes, else 0): up to cap groups written to the host arrays kinds, tags, total_ms, launches.
+ * Returns the number of groups (>= 0) or a negative status; forgets the records like
+ * cola_profiler_read. */
+int cola_profiler_read_groups(int32_t cap, int32_t* kinds, int64_t* tags, double* total_ms, int64_t* launches);
 
 /* Plain device-to-device copy of `bytes` bytes with the library's streaming kernel (16-byte
  * vectors): the yardstick against which hardware byte counters are scaled. */

@@ -262,6 +262,23 @@ def profiler_read():
             for i in range(n) if cnt[i] > 0}
 
 
+def profiler_read_groups():
+    """{(kernel kind, size tag): (total ms, launches)}; the tag is the mesh side for FFT passes."""
+    cap = 512
+    kinds = np.zeros(cap, dtype=np.int32)
+    tags = np.zeros(cap, dtype=np.int64)
+    ms = np.zeros(cap, dtype=np.float64)
+    cnt = np.zeros(cap, dtype=np.int64)
+    n = _lib.lib().cola_profiler_read_groups(cap, kinds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             tags.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                             ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if n < 0:
+        raise ColaError(n, "cola_profiler_read_groups")
+    name = _lib.lib().cola_profiler_kind_name
+    return {(name(int(kinds[i])).decode(), int(tags[i])): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
 def copy(src, dst):
     """Device copy with the library's streaming kernel (counter yardstick)."""
     nbytes = src.numel() * src.element_size()

@@ -25,7 +25,8 @@ EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_last_error", "cola_autotune", "cola_ensemble_run", "cola_ensemble_release",
            "cola_lc_param_count", "cola_lc_packed_bytes", "cola_lc_workspace_bytes", "cola_lc_pack",
            "cola_lc_forward", "cola_lc_backward", "cola_lc_loss", "cola_lc_adam", "cola_step_lc",
-           "cola_pm_fields_workspace_bytes", "cola_pm_fields", "cola_positions", "cola_mfma_selftest")
+           "cola_pm_fields_workspace_bytes", "cola_pm_fields", "cola_positions", "cola_mfma_selftest",
+           "cola_profiler_read_groups")
 
 
 class ColaError(RuntimeError):
@@ -122,6 +123,8 @@ def _load():
                                           ctypes.POINTER(vp), vp, sz, vp]),
         "cola_positions": (ctypes.c_int, [P, PP, ctypes.POINTER(vp), vp]),
         "cola_mfma_selftest": (ctypes.c_int, [vp, vp, vp, vp]),
+        "cola_profiler_read_groups": (ctypes.c_int, [i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                                     ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -24,16 +24,18 @@ enum ProfKind {
     PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_LC_CONV, PROF_LC_WGRAD, PROF_LC_MISC,
     PROF_NUM_KINDS
 };
-// Brackets one kernel launch with an event pair when the profiler is enabled.
+// Brackets one kernel launch with an event pair when the profiler is enabled.  tag: a size label
+// (the mesh side for FFT passes) so that reads can separate launches of different sizes.
 class ProfScope {
   public:
-    ProfScope(int kind, hipStream_t st);
+    ProfScope(int kind, hipStream_t st, long tag = 0);
     ~ProfScope();
     ProfScope(const ProfScope&) = delete;
     ProfScope& operator=(const ProfScope&) = delete;
 
   private:
     int kind_;
+    long tag_;
     hipStream_t st_;
     hipEvent_t start_ = nullptr;
     bool counted_ = false;

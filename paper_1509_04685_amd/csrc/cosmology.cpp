@@ -50,28 +50,57 @@ GrowthState growth_rhs(double y, const GrowthState& s, double om) {
             s.v2, -(2.0 + dlne) * s.v2 + coef * (s.d2 - s.d1 * s.d1)};
 }
 
-// Classic RK4 in y = ln a from deep matter domination (a = 1e-6: growing modes D1 = a,
-// D2 = -3/7 a^2) to ln(a_target); step <= 5e-4 in ln a.
-GrowthState integrate_growth(double a_target, double om) {
-    const double a_start = 1e-6;
-    double y0 = std::log(a_start), y1 = std::log(a_target);
-    int n = std::max(64, static_cast<int>(std::ceil((y1 - y0) / 5e-4)));
-    double h = (y1 - y0) / n;
-    GrowthState s{a_start, a_start, -3.0 / 7.0 * a_start * a_start, -6.0 / 7.0 * a_start * a_start};
-    double y = y0;
+GrowthState rk4_step(const GrowthState& s, double y, double h, double om) {
     auto axpy = [](const GrowthState& a, double c, const GrowthState& b) {
         return GrowthState{a.d1 + c * b.d1, a.v1 + c * b.v1, a.d2 + c * b.d2, a.v2 + c * b.v2};
     };
-    for (int i = 0; i < n; ++i) {
-        GrowthState k1 = growth_rhs(y, s, om);
-        GrowthState k2 = growth_rhs(y + 0.5 * h, axpy(s, 0.5 * h, k1), om);
-        GrowthState k3 = growth_rhs(y + 0.5 * h, axpy(s, 0.5 * h, k2), om);
-        GrowthState k4 = growth_rhs(y + h, axpy(s, h, k3), om);
-        s.d1 += h / 6.0 * (k1.d1 + 2 * k2.d1 + 2 * k3.d1 + k4.d1);
-        s.v1 += h / 6.0 * (k1.v1 + 2 * k2.v1 + 2 * k3.v1 + k4.v1);
-        s.d2 += h / 6.0 * (k1.d2 + 2 * k2.d2 + 2 * k3.d2 + k4.d2);
-        s.v2 += h / 6.0 * (k1.v2 + 2 * k2.v2 + 2 * k3.v2 + k4.v2);
-        y += h;
+    GrowthState k1 = growth_rhs(y, s, om);
+    GrowthState k2 = growth_rhs(y + 0.5 * h, axpy(s, 0.5 * h, k1), om);
+    GrowthState k3 = growth_rhs(y + 0.5 * h, axpy(s, 0.5 * h, k2), om);
+    GrowthState k4 = growth_rhs(y + h, axpy(s, h, k3), om);
+    GrowthState r = s;
+    r.d1 += h / 6.0 * (k1.d1 + 2 * k2.d1 + 2 * k3.d1 + k4.d1);
+    r.v1 += h / 6.0 * (k1.v1 + 2 * k2.v1 + 2 * k3.v1 + k4.v1);
+    r.d2 += h / 6.0 * (k1.d2 + 2 * k2.d2 + 2 * k3.d2 + k4.d2);
+    r.v2 += h / 6.0 * (k1.v2 + 2 * k2.v2 + 2 * k3.v2 + k4.v2);
+    return r;
+}
+
+// Classic RK4 in y = ln a from deep matter domination (a = 1e-6: growing modes D1 = a,
+// D2 = -3/7 a^2) with steps of 5e-4 in ln a.  The states on that grid are kept per Omega_m (and
+// per thread) up to a = 2, so a value at any a costs one table lookup and at most a few steps.
+constexpr double kGrowthStart = 1e-6, kGrowthStep = 5e-4;
+
+struct GrowthTable {
+    double om = -1.0;
+    std::vector<GrowthState> s;  // state at y = ln(1e-6) + i * kGrowthStep
+};
+
+const GrowthTable& growth_table(double om) {
+    static thread_local GrowthTable t;
+    if (t.om != om) {
+        const double y0 = std::log(kGrowthStart);
+        const int n = static_cast<int>(std::ceil((std::log(2.0) - y0) / kGrowthStep)) + 1;
+        t.s.resize(n);
+        t.s[0] = GrowthState{kGrowthStart, kGrowthStart, -3.0 / 7.0 * kGrowthStart * kGrowthStart,
+                             -6.0 / 7.0 * kGrowthStart * kGrowthStart};
+        for (int i = 1; i < n; ++i) t.s[i] = rk4_step(t.s[i - 1], y0 + (i - 1) * kGrowthStep, kGrowthStep, om);
+        t.om = om;
+    }
+    return t;
+}
+
+GrowthState integrate_growth(double a_target, double om) {
+    const GrowthTable& t = growth_table(om);
+    const double y0 = std::log(kGrowthStart), y = std::log(a_target);
+    long i = static_cast<long>(std::floor((y - y0) / kGrowthStep));
+    i = std::max(0L, std::min(i, static_cast<long>(t.s.size()) - 1));
+    GrowthState s = t.s[i];
+    double yi = y0 + i * kGrowthStep;
+    const int n = std::max(0, static_cast<int>(std::ceil((y - yi) / kGrowthStep - 1e-12)));
+    if (n > 0) {
+        const double h = (y - yi) / n;
+        for (int k = 0; k < n; ++k, yi += h) s = rk4_step(s, yi, h, om);
     }
     return s;
 }
@@ -79,12 +108,7 @@ GrowthState integrate_growth(double a_target, double om) {
 }  // namespace
 
 Growth growth(double a, double om) {
-    static thread_local double cached_om = -1.0;
-    static thread_local GrowthState norm{};
-    if (cached_om != om) {
-        norm = integrate_growth(1.0, om);
-        cached_om = om;
-    }
+    const GrowthState norm = integrate_growth(1.0, om);
     GrowthState s = integrate_growth(a, om);
     double n1 = norm.d1;
     Growth g;

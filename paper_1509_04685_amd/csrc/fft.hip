@@ -539,7 +539,7 @@ static hipError_t run_cols_shape(float2* data, long bstride, const Mesh3& g, boo
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_cols<decltype(rr)::value, INV>;
         if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(INV ? (y_axis ? PROF_Y_INV : PROF_OTHER) : (y_axis ? PROF_Y_FWD : PROF_X_FWD), st);
+        ProfScope ps(INV ? (y_axis ? PROF_Y_INV : PROF_OTHER) : (y_axis ? PROF_Y_FWD : PROF_X_FWD), st, g.n);
         hipLaunchKernelGGL(kern, grid, block, lds, st, data, bstride, cg, pl, tw);
     });
     if (err != hipSuccess) return err;
@@ -566,7 +566,7 @@ static hipError_t run_z_r2c_shape(const float* in, long in_row, long in_bstride,
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_z_r2c<decltype(rr)::value>;
         if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_Z_R2C, st);
+        ProfScope ps(PROF_Z_R2C, st, g.n);
         hipLaunchKernelGGL(kern, grid, block, lds, st, in, in_row, in_bstride, out, (long)g.nzp,
                            out_bstride, nrows, pl, tw, pa, pb);
     });
@@ -594,7 +594,7 @@ static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out,
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_z_c2r<decltype(rr)::value, MUL>;
         if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_Z_C2R, st);
+        ProfScope ps(PROF_Z_C2R, st, g.n);
         hipLaunchKernelGGL(kern, grid, block, lds, st, in, (long)g.nzp, in_bstride, out, out_row,
                            out_bstride, nrows, pl, tw, kf, scale);
     });
@@ -621,7 +621,7 @@ static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstrid
     hipError_t de = dispatch_r(pf.R, [&](auto rr) {
         auto kern = k_fft_x_green<decltype(rr)::value>;
         if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_X_GREEN, st);
+        ProfScope ps(PROF_X_GREEN, st, g.n);
         hipLaunchKernelGGL(kern, grid, block, lds, st, S, A, B, bstride, cg, pf, pi, tw, kf, gscale);
     });
     if (err != hipSuccess) return err;
@@ -638,7 +638,7 @@ static hipError_t run_y_split_shape(float2* A, float2* S, long bstride, const Me
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_y_split<decltype(rr)::value>;
         if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_Y_SPLIT, st);
+        ProfScope ps(PROF_Y_SPLIT, st, g.n);
         hipLaunchKernelGGL(kern, grid, block, lds, st, A, S, bstride, cg, pl, tw, kf);
     });
     if (err != hipSuccess) return err;
@@ -656,7 +656,7 @@ static hipError_t run_x_mult_shape(const float2* spec, long spec_bstride, float2
     hipError_t de = dispatch_r(pl.R, [&](auto rr) {
         auto kern = k_fft_x_mult<decltype(rr)::value>;
         if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_X_INV_MULT, st);
+        ProfScope ps(PROF_X_INV_MULT, st, g.n);
         hipLaunchKernelGGL(kern, grid, block, lds, st, spec, spec_bstride, work, work_bstride, cg, pl, tw,
                            mtype, axis_a, axis_b, kf, scale);
     });

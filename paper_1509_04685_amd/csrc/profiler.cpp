@@ -21,6 +21,7 @@ const char* const kKindNames[PROF_NUM_KINDS] = {
 
 struct Record {
     int kind;
+    long tag;
     hipEvent_t start, stop;
 };
 
@@ -49,7 +50,7 @@ Profiler& prof() {
 
 }  // namespace
 
-ProfScope::ProfScope(int kind, hipStream_t st) : kind_(kind), st_(st) {
+ProfScope::ProfScope(int kind, hipStream_t st, long tag) : kind_(kind), tag_(tag), st_(st) {
     Profiler& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
     if (!p.enabled) return;
@@ -70,7 +71,7 @@ ProfScope::~ProfScope() {
     hipEvent_t stop = p.get();
     if (!stop) return;
     (void)hipEventRecord(stop, st_);
-    p.records.push_back({kind_, start_, stop});
+    p.records.push_back({kind_, tag_, start_, stop});
 }
 
 }  // namespace cola
@@ -120,6 +121,36 @@ int cola_profiler_read(int32_t n_kinds, double* total_ms, int64_t* launches) {
     }
     p.records.clear();
     return COLA_OK;
+}
+
+int cola_profiler_read_groups(int32_t cap, int32_t* kinds, int64_t* tags, double* total_ms, int64_t* launches) {
+    if (cap < 1 || !kinds || !tags || !total_ms || !launches) return COLA_ERR_INVALID_ARG;
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    int n = 0;
+    for (auto& r : p.records) {
+        if (hipEventSynchronize(r.stop) != hipSuccess) return COLA_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return COLA_ERR_HIP;
+        int i = 0;
+        while (i < n && !(kinds[i] == r.kind && tags[i] == r.tag)) ++i;
+        if (i == n) {
+            if (n == cap) return COLA_ERR_INVALID_ARG;
+            kinds[i] = r.kind;
+            tags[i] = r.tag;
+            total_ms[i] = 0.0;
+            launches[i] = 0;
+            ++n;
+        }
+        total_ms[i] += ms;
+        launches[i] += 1;
+    }
+    for (auto& r : p.records) {
+        p.pool.push_back(r.start);
+        p.pool.push_back(r.stop);
+    }
+    p.records.clear();
+    return n;
 }
 
 }  // extern "C"
