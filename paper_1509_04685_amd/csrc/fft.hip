@@ -10,7 +10,8 @@
 // The particle-mesh force fuses the forward x transform, the Green's function and the inverse x
 // transform in one pass that writes two outputs, so the full spectrum never goes to HBM.
 
-#include "cola_internal.h"
+#include "fft_kernels.h"
+
 
 #include <algorithm>
 #include <cstdio>
@@ -69,13 +70,6 @@ static int pick_tk(int n, int T) {
     return tk;
 }
 
-template <class K>
-static hipError_t allow_lds(K kernel, size_t bytes) {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
 // ------------------------------------------------------------------ twiddles
 
 __global__ void k_twiddles(float2* tw, int len) {
@@ -90,288 +84,6 @@ hipError_t launch_twiddles(float2* tw, int len, hipStream_t st) {
     ProfScope ps(PROF_OTHER, st);
     hipLaunchKernelGGL(k_twiddles, dim3((len + 255) / 256), dim3(256), 0, st, tw, len);
     return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ z pass: real -> half complex
-
-// Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
-// X_k = (Z_k + conj Z_{M-k})/2 - i W_n^k (Z_k - conj Z_{M-k})/2, k = 0..M.
-template <int R>
-__global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row, long in_bstride,
-                                                   float2* out, long out_row, long out_bstride,
-                                                   long nrows, FftPlan pl, const float2* tw,
-                                                   float pa, float pb) {
-    extern __shared__ float2 lds[];
-    const int T = pl.T, M = pl.n;
-    const int lpb = blockDim.x / T;
-    const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const long row = (long)blockIdx.x * lpb + line;
-    const bool active = row < nrows;
-    in += (long)blockIdx.y * in_bstride;
-    out += (long)blockIdx.y * out_bstride;
-    float2* L = lds + line * (M + 1);
-    float2 v[R];
-    if (active) {
-        const float2* src = reinterpret_cast<const float2*>(in + row * in_row);
-        for_pattern<R>(pl.radix[0], t, T, pl.nr[0], [&](int q, int e) {
-            float2 z = src[e];
-            v[q] = make_float2(fmaf(z.x, pa, pb), fmaf(z.y, pa, pb));
-        });
-    }
-    fft_line<R, false>(v, pl, L, 1, t, tw, active);
-    if (active) for_pattern<R>(pl.radix[pl.nst - 1], t, T, pl.nr[pl.nst - 1], [&](int q, int e) { L[e] = v[q]; });
-    __syncthreads();
-    if (!active) return;
-    float2* dst = out + row * out_row;
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-        int k = t + u * T;
-        float2 zk = L[k];
-        float2 zc = cconj(L[k == 0 ? 0 : M - k]);
-        float2 e = cscale(cadd(zk, zc), 0.5f);
-        float2 d = csub(zk, zc);
-        float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
-        dst[k] = cadd(e, cmul(tw[k], o));
-    }
-    if (t == 0) {
-        float2 z0 = L[0];
-        dst[M] = make_float2(z0.x - z0.y, 0.0f);
-    }
-}
-
-// ------------------------------------------------------------------ z pass: half complex -> real
-
-// Z_k = (X_k + conj X_{M-k}) + i conj(W_n^k) (X_k - conj X_{M-k}); x_{2j} + i x_{2j+1} = IFFT_M(Z)_j.
-// MUL_IKZ multiplies X by i k_z first (the kz = M Nyquist column becomes 0).
-template <int R, bool MUL_IKZ>
-__global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row, long in_bstride,
-                                                   float* out, long out_row, long out_bstride,
-                                                   long nrows, FftPlan pl, const float2* tw,
-                                                   float kf, float scale) {
-    extern __shared__ float2 lds[];
-    const int T = pl.T, M = pl.n;
-    const int lpb = blockDim.x / T;
-    const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const long row = (long)blockIdx.x * lpb + line;
-    const bool active = row < nrows;
-    in += (long)blockIdx.y * in_bstride;
-    out += (long)blockIdx.y * out_bstride;
-    float2* L = lds + line * (M + 1);
-    if (active) {
-        // issue all R loads of this thread before the first LDS store
-        const float2* src = in + row * in_row;
-        float2 x[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) x[u] = src[t + u * T];
-        float2 xm = (t == 0) ? src[M] : make_float2(0.0f, 0.0f);
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-            int e = t + u * T;
-            float2 y = x[u];
-            if (MUL_IKZ) {
-                float kz = kf * (float)e;
-                y = make_float2(-kz * y.y, kz * y.x);
-            }
-            L[e] = cscale(y, scale);
-        }
-        if (t == 0) L[M] = MUL_IKZ ? make_float2(0.0f, 0.0f) : cscale(xm, scale);  // kz Nyquist
-    }
-    __syncthreads();
-    float2 v[R];
-    if (active) {
-        for_pattern<R>(pl.radix[0], t, T, pl.nr[0], [&](int q, int k) {
-            float2 xk = L[k];
-            float2 xc = cconj(L[M - k]);
-            float2 d = cmul(cconj(tw[k]), csub(xk, xc));
-            v[q] = make_float2(xk.x + xc.x - d.y, xk.y + xc.y + d.x);  // (xk + xc) + i d
-        });
-    }
-    __syncthreads();
-    fft_line<R, true>(v, pl, L, 1, t, tw, active);
-    if (!active) return;
-    float2* dst = reinterpret_cast<float2*>(out + row * out_row);
-    for_pattern<R>(pl.radix[pl.nst - 1], t, T, pl.nr[pl.nst - 1], [&](int q, int e) { dst[e] = v[q]; });
-}
-
-// ------------------------------------------------------------------ strided column passes
-
-// Columns of a realization's padded spectrum (offsets fit 32 bits: meshes up to 1536^3).
-struct ColGeom {
-    int es;           // element stride along the transform axis (float2)
-    int inner;        // contiguous columns per outer block
-    int outer_stride;
-    int nzp;          // columns c are valid when c % nzp < mvalid
-    int mvalid;
-    int tk;           // columns per tile
-    int tiles;        // tiles per outer block
-};
-
-// Block b runs on XCD b % 8 (round-robin dispatch); hand each XCD a contiguous run of tiles so
-// that neighbouring tiles, which share 128-byte lines when a tile row is narrower than a line,
-// meet in the same L2.
-__device__ __forceinline__ int xcd_block() {
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
-__device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& base, int& c) {
-    const int ct = threadIdx.x % cg.tk;
-    t = threadIdx.x / cg.tk;
-    const int blk = xcd_block();
-    const int outer = blk / cg.tiles;
-    const int tile = blk - outer * cg.tiles;
-    c = tile * cg.tk + ct;
-    base = (uint32_t)outer * (uint32_t)cg.outer_stride + (uint32_t)c;
-    return c < cg.inner && (c % cg.nzp) < cg.mvalid;
-}
-
-template <int R, bool INV>
-__global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, ColGeom cg, FftPlan pl,
-                                                  const float2* tw) {
-    extern __shared__ float2 lds[];
-    int t, c;
-    uint32_t base;
-    const bool active = col_setup(cg, t, base, c);
-    data += (long)blockIdx.y * bstride;
-    const uint32_t es = (uint32_t)cg.es;
-    float2 v[R];
-    if (active)
-        for_pattern<R>(pl.radix[0], t, pl.T, pl.nr[0], [&](int q, int e) { v[q] = data[base + (uint32_t)e * es]; });
-    fft_line<R, INV>(v, pl, lds + threadIdx.x % cg.tk, cg.tk, t, tw, active);
-    if (!active) return;
-    for_pattern<R>(pl.radix[pl.nst - 1], t, pl.T, pl.nr[pl.nst - 1],
-                   [&](int q, int e) { data[base + (uint32_t)e * es] = v[q]; });
-}
-
-__device__ __forceinline__ int signed_mode(int e, int n) { return e < n / 2 ? e : e - n; }
-
-// Fused x pass of the particle-mesh force.  Columns are (y, kz); the transform axis is x.
-// Forward x FFT, V = S / (k^2 n^3) (k = 0 -> 0), then A = IFFT_x[V] and B = IFFT_x[i k_x V]
-// (the k_x Nyquist plane of B set to 0).  pf: forward plan; pi: the same radices reversed, so
-// the inverse starts from the forward's output pattern without an LDS round trip.
-template <int R>
-__global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A, float2* B, long bstride,
-                                                     ColGeom cg, FftPlan pf, FftPlan pi,
-                                                     const float2* tw, float kf, float gscale) {
-    extern __shared__ float2 lds[];
-    int t, c;
-    uint32_t base;
-    const bool active = col_setup(cg, t, base, c);
-    const long boff = (long)blockIdx.y * bstride;
-    S += boff;
-    A += boff;
-    B += boff;
-    const uint32_t es = (uint32_t)cg.es;
-    const int n = pf.n;
-    const int yrow = c / cg.nzp;
-    const int my = signed_mode(yrow, n), mz = c - yrow * cg.nzp;
-    float2* L = lds + threadIdx.x % cg.tk;
-    float2 v[R], h[R];
-    if (active)
-        for_pattern<R>(pf.radix[0], t, pf.T, pf.nr[0], [&](int q, int e) { v[q] = S[base + (uint32_t)e * es]; });
-    fft_line<R, false>(v, pf, L, cg.tk, t, tw, active);
-    const float kyz2 = (float)(my * my + mz * mz);
-    for_pattern<R>(pf.radix[pf.nst - 1], t, pf.T, pf.nr[pf.nst - 1], [&](int q, int e) {
-        int mx = signed_mode(e, n);
-        float m2 = (float)(mx * mx) + kyz2;
-        float gk = (m2 > 0.0f) ? gscale / (kf * kf * m2) : 0.0f;
-        v[q] = cscale(v[q], gk);
-        float kx = (2 * mx == -n) ? 0.0f : kf * (float)mx;
-        h[q] = make_float2(-kx * v[q].y, kx * v[q].x);  // i k_x V
-    });
-    fft_line<R, true>(v, pi, L, cg.tk, t, tw, active);
-    if (active)
-        for_pattern<R>(pi.radix[pi.nst - 1], t, pi.T, pi.nr[pi.nst - 1],
-                       [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
-    fft_line<R, true>(h, pi, L, cg.tk, t, tw, active);
-    if (!active) return;
-    for_pattern<R>(pi.radix[pi.nst - 1], t, pi.T, pi.nr[pi.nst - 1],
-                   [&](int q, int e) { B[base + (uint32_t)e * es] = h[q]; });
-}
-
-// y inverse of A giving two outputs: A <- IFFT_y[i k_y A] (Nyquist of k_y set to 0) and
-// S <- IFFT_y[A].  Columns are kz within one x plane.
-template <int R>
-__global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long bstride, ColGeom cg,
-                                                     FftPlan pl, const float2* tw, float kf) {
-    extern __shared__ float2 lds[];
-    int t, c;
-    uint32_t base;
-    const bool active = col_setup(cg, t, base, c);
-    const long boff = (long)blockIdx.y * bstride;
-    A += boff;
-    S += boff;
-    const uint32_t es = (uint32_t)cg.es;
-    const int n = pl.n;
-    float2* L = lds + threadIdx.x % cg.tk;
-    float2 v[R], h[R];
-    if (active) {
-        for_pattern<R>(pl.radix[0], t, pl.T, pl.nr[0], [&](int q, int e) {
-            float2 a = A[base + (uint32_t)e * es];
-            h[q] = a;
-            int my = signed_mode(e, n);
-            float ky = (2 * my == -n) ? 0.0f : kf * (float)my;
-            v[q] = make_float2(-ky * a.y, ky * a.x);
-        });
-    }
-    fft_line<R, true>(v, pl, L, cg.tk, t, tw, active);
-    if (active)
-        for_pattern<R>(pl.radix[pl.nst - 1], t, pl.T, pl.nr[pl.nst - 1],
-                       [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
-    fft_line<R, true>(h, pl, L, cg.tk, t, tw, active);
-    if (!active) return;
-    for_pattern<R>(pl.radix[pl.nst - 1], t, pl.T, pl.nr[pl.nst - 1],
-                   [&](int q, int e) { S[base + (uint32_t)e * es] = h[q]; });
-}
-
-// x inverse with a multiplier taken from the full spectrum: W = IFFT_x[M(k) spec].
-//   MUL_SCALE: M = scale;  MUL_IK: M = i k_a / k^2 * scale;  MUL_KK: M = k_a k_b / k^2 * scale.
-// A factor k_d is zeroed on the Nyquist plane of axis d when it appears to an odd power.
-template <int R>
-__global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spec_bstride, float2* W,
-                                                    long w_bstride, ColGeom cg, FftPlan pl,
-                                                    const float2* tw, int mtype, int ax_a, int ax_b,
-                                                    float kf, float scale) {
-    extern __shared__ float2 lds[];
-    int t, c;
-    uint32_t base;
-    const bool active = col_setup(cg, t, base, c);
-    spec += (long)blockIdx.y * spec_bstride;
-    W += (long)blockIdx.y * w_bstride;
-    const uint32_t es = (uint32_t)cg.es;
-    const int n = pl.n;
-    const int yrow = c / cg.nzp;
-    const int my = signed_mode(yrow, n);
-    const int mzr = c - yrow * cg.nzp;
-    const int mz = (2 * mzr == n) ? -mzr : mzr;  // the kz = n/2 column is the Nyquist plane
-    float2 v[R];
-    if (active) {
-        for_pattern<R>(pl.radix[0], t, pl.T, pl.nr[0], [&](int q, int e) {
-            float2 x = spec[base + (uint32_t)e * es];
-            const int mx = signed_mode(e, n);
-            const int ma = ax_a == 0 ? mx : (ax_a == 1 ? my : mz);
-            const int mb = ax_b == 0 ? mx : (ax_b == 1 ? my : mz);
-            const float m2 = (float)(mx * mx + my * my + mz * mz);
-            float f = scale;
-            if (mtype == MUL_IK) {
-                const bool nyq = (2 * ma == -n);
-                f = (m2 > 0.0f && !nyq) ? scale * (float)ma / (kf * m2) : 0.0f;
-                x = make_float2(-f * x.y, f * x.x);
-            } else if (mtype == MUL_KK) {
-                const bool nyq = (ax_a != ax_b) && ((2 * ma == -n) || (2 * mb == -n));
-                f = (m2 > 0.0f && !nyq) ? scale * (float)ma * (float)mb / m2 : 0.0f;
-                x = cscale(x, f);
-            } else {
-                x = cscale(x, f);
-            }
-            v[q] = x;
-        });
-    }
-    fft_line<R, true>(v, pl, lds + threadIdx.x % cg.tk, cg.tk, t, tw, active);
-    if (!active) return;
-    for_pattern<R>(pl.radix[pl.nst - 1], t, pl.T, pl.nr[pl.nst - 1],
-                   [&](int q, int e) { W[base + (uint32_t)e * es] = v[q]; });
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -398,11 +110,12 @@ static hipError_t dispatch_r(int R, F&& f) {
 
 // ------------------------------------------------------------------ kernel shapes and autotuning
 
-// Shape of one FFT kernel launch: R values per thread and `width` lines per block (z passes)
-// or columns per tile (y/x passes).
+// Shape of one FFT kernel launch: R values per thread, `width` lines per block (z passes) or
+// columns per tile (y/x passes), and whether the compile-time plan of that shape is used.
 struct FftShape {
     int R = 0;
     int width = 0;
+    bool stat = false;
 };
 
 enum FftKind { FK_Z_R2C = 0, FK_Z_C2R, FK_COLS_Y, FK_COLS_X, FK_X_GREEN, FK_Y_SPLIT, FK_X_MULT, FK_NUM };
@@ -448,6 +161,39 @@ static bool is_z(FftKind k) { return k == FK_Z_R2C || k == FK_Z_C2R; }
 // Line length the kernel transforms: n/2 for the z passes, n otherwise.
 static int line_len(FftKind k, int n) { return is_z(k) ? n / 2 : n; }
 
+static FftOp op_of(FftKind k) {
+    switch (k) {
+        case FK_Z_R2C: return OP_Z_R2C;
+        case FK_Z_C2R: return OP_Z_C2R;
+        case FK_COLS_Y:
+        case FK_COLS_X: return OP_COLS_FWD;
+        case FK_X_GREEN: return OP_X_GREEN;
+        case FK_Y_SPLIT: return OP_Y_SPLIT;
+        default: return OP_X_MULT;
+    }
+}
+
+// Routes a launch to the static kernels of its mesh size (n: the mesh side).
+static hipError_t launch_static(const FftLaunch& L, int n) {
+    switch (n) {
+        case 768: return fft_static_768(L);
+        case 384: return fft_static_384(L);
+        case 288: return fft_static_288(L);
+        case 256: return fft_static_256(L);
+        default: return hipErrorNotSupported;
+    }
+}
+
+static bool static_available(FftKind k, int n, int R, int width) {
+    FftLaunch L;
+    L.op = op_of(k);
+    L.n = line_len(k, n);
+    L.R = R;
+    L.width = width;
+    L.probe = true;
+    return launch_static(L, n) == hipSuccess;
+}
+
 static size_t shape_lds(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
     return is_z(k) ? (size_t)sh.width * (L + 1) * sizeof(float2) : (size_t)sh.width * L * sizeof(float2);
@@ -472,6 +218,7 @@ static FftShape default_shape(FftKind k, int n) {
     } else {
         sh.width = pick_tk(n, pl.T);
     }
+    sh.stat = static_available(k, n, sh.R, sh.width);
     return sh;
 }
 
@@ -492,10 +239,6 @@ static FftShape shape_for(FftKind k, int n) {
     auto it = c.tuned.find({(int)k, n});
     if (it != c.tuned.end()) return it->second;
     return default_shape(k, n);
-}
-
-static FftPlan plan_for(FftKind k, int n, bool reverse = false) {
-    return make_plan_r(line_len(k, n), shape_for(k, n).R, reverse);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -528,22 +271,57 @@ static long col_blocks(const ColGeom& cg, const Mesh3& g, bool y_axis) {
     return (y_axis ? (long)g.n : 1L) * cg.tiles;
 }
 
+// Launches L with the shape's static kernel or the dynamic kernel of the same shape.
+static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
+    L.n = L.op <= OP_Z_C2R_IKZ ? mesh_n / 2 : mesh_n;
+    L.R = sh.R;
+    L.width = sh.width;
+    if (sh.stat) {
+        hipError_t e = launch_static(L, mesh_n);
+        if (e != hipErrorNotSupported) return e;
+    }
+    const bool z = L.op <= OP_Z_C2R_IKZ;
+    FftPlan pl = make_plan_r(L.n, sh.R, false);
+    if (z) finish_plan(pl, 2);
+    const int les = z ? 1 : sh.width;
+    hipError_t err = hipSuccess;
+    hipError_t de = dispatch_r(sh.R, [&](auto rr) {
+        constexpr int R = decltype(rr)::value;
+        using D = DynLine<R>;
+        D e{pl, les};
+        switch (L.op) {
+            case OP_Z_R2C: err = go_z_r2c<D>(L, e); break;
+            case OP_Z_C2R: err = go_z_c2r<D, false>(L, e); break;
+            case OP_Z_C2R_IKZ: err = go_z_c2r<D, true>(L, e); break;
+            case OP_COLS_FWD: err = go_cols<D, 0, false>(L, e); break;
+            case OP_COLS_INV: err = go_cols<D, 0, true>(L, e); break;
+            case OP_X_GREEN: {
+                D ei{make_plan_r(L.n, R, true), les};
+                err = go_x_green<D, D, 0>(L, e, ei);
+                break;
+            }
+            case OP_Y_SPLIT: err = go_y_split<D, 0>(L, e); break;
+            case OP_X_MULT: err = go_x_mult<D, 0>(L, e); break;
+        }
+    });
+    return err != hipSuccess ? err : de;
+}
+
 template <bool INV>
 static hipError_t run_cols_shape(float2* data, long bstride, const Mesh3& g, bool y_axis, const float2* tw,
                                  int n_real, const FftShape& sh, hipStream_t st) {
-    FftPlan pl = make_plan_r(g.n, sh.R, false);
-    ColGeom cg = y_axis ? cols_y(g, sh.width) : cols_x(g, sh.width);
-    size_t lds = (size_t)sh.width * g.n * sizeof(float2);
-    dim3 grid((unsigned)col_blocks(cg, g, y_axis), n_real), block(sh.width * pl.T);
-    hipError_t err = hipSuccess;
-    hipError_t de = dispatch_r(pl.R, [&](auto rr) {
-        auto kern = k_fft_cols<decltype(rr)::value, INV>;
-        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(INV ? (y_axis ? PROF_Y_INV : PROF_OTHER) : (y_axis ? PROF_Y_FWD : PROF_X_FWD), st, g.n);
-        hipLaunchKernelGGL(kern, grid, block, lds, st, data, bstride, cg, pl, tw);
-    });
-    if (err != hipSuccess) return err;
-    return de;
+    FftLaunch L;
+    L.op = INV ? OP_COLS_INV : OP_COLS_FWD;
+    L.cg = y_axis ? cols_y(g, sh.width) : cols_x(g, sh.width);
+    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.grid = dim3((unsigned)col_blocks(L.cg, g, y_axis), n_real);
+    L.block = dim3(sh.width * (g.n / sh.R));
+    L.st = st;
+    L.d0 = data;
+    L.b0 = bstride;
+    L.tw = tw;
+    ProfScope ps(INV ? (y_axis ? PROF_Y_INV : PROF_OTHER) : (y_axis ? PROF_Y_FWD : PROF_X_FWD), st, g.n);
+    return launch_shape(L, g.n, sh);
 }
 
 template <bool INV>
@@ -556,22 +334,25 @@ static hipError_t run_cols(float2* data, long bstride, const Mesh3& g, bool y_ax
 static hipError_t run_z_r2c_shape(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                                   const Mesh3& g, const float2* tw, int n_real, float pa, float pb,
                                   const FftShape& sh, hipStream_t st) {
-    FftPlan pl = make_plan_r(g.m, sh.R, false);
-    finish_plan(pl, 2);
-    int lpb = sh.width;
-    long nrows = (long)g.n * g.n;
-    size_t lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
-    dim3 grid((unsigned)((nrows + lpb - 1) / lpb), n_real), block(lpb * pl.T);
-    hipError_t err = hipSuccess;
-    hipError_t de = dispatch_r(pl.R, [&](auto rr) {
-        auto kern = k_fft_z_r2c<decltype(rr)::value>;
-        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_Z_R2C, st, g.n);
-        hipLaunchKernelGGL(kern, grid, block, lds, st, in, in_row, in_bstride, out, (long)g.nzp,
-                           out_bstride, nrows, pl, tw, pa, pb);
-    });
-    if (err != hipSuccess) return err;
-    return de;
+    FftLaunch L;
+    L.op = OP_Z_R2C;
+    const int lpb = sh.width;
+    L.nrows = (long)g.n * g.n;
+    L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
+    L.grid = dim3((unsigned)((L.nrows + lpb - 1) / lpb), n_real);
+    L.block = dim3(lpb * (g.m / sh.R));
+    L.st = st;
+    L.rin = in;
+    L.in_row = in_row;
+    L.in_bstride = in_bstride;
+    L.cout = out;
+    L.out_row = g.nzp;
+    L.out_bstride = out_bstride;
+    L.tw = tw;
+    L.pa = pa;
+    L.pb = pb;
+    ProfScope ps(PROF_Z_R2C, st, g.n);
+    return launch_shape(L, g.n, sh);
 }
 
 static hipError_t run_z_r2c(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
@@ -584,22 +365,25 @@ template <bool MUL>
 static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out, long out_row, long out_bstride,
                                   const Mesh3& g, const float2* tw, int n_real, float kf, float scale,
                                   const FftShape& sh, hipStream_t st) {
-    FftPlan pl = make_plan_r(g.m, sh.R, false);
-    finish_plan(pl, 2);
-    int lpb = sh.width;
-    long nrows = (long)g.n * g.n;
-    size_t lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
-    dim3 grid((unsigned)((nrows + lpb - 1) / lpb), n_real), block(lpb * pl.T);
-    hipError_t err = hipSuccess;
-    hipError_t de = dispatch_r(pl.R, [&](auto rr) {
-        auto kern = k_fft_z_c2r<decltype(rr)::value, MUL>;
-        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_Z_C2R, st, g.n);
-        hipLaunchKernelGGL(kern, grid, block, lds, st, in, (long)g.nzp, in_bstride, out, out_row,
-                           out_bstride, nrows, pl, tw, kf, scale);
-    });
-    if (err != hipSuccess) return err;
-    return de;
+    FftLaunch L;
+    L.op = MUL ? OP_Z_C2R_IKZ : OP_Z_C2R;
+    const int lpb = sh.width;
+    L.nrows = (long)g.n * g.n;
+    L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
+    L.grid = dim3((unsigned)((L.nrows + lpb - 1) / lpb), n_real);
+    L.block = dim3(lpb * (g.m / sh.R));
+    L.st = st;
+    L.cin = in;
+    L.in_row = g.nzp;
+    L.in_bstride = in_bstride;
+    L.rout = out;
+    L.out_row = out_row;
+    L.out_bstride = out_bstride;
+    L.tw = tw;
+    L.kf = kf;
+    L.scale = scale;
+    ProfScope ps(PROF_Z_C2R, st, g.n);
+    return launch_shape(L, g.n, sh);
 }
 
 template <bool MUL>
@@ -612,56 +396,64 @@ static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long 
 
 static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstride, const Mesh3& g,
                                     const float2* tw, float kf, int n_real, const FftShape& sh, hipStream_t st) {
-    FftPlan pf = make_plan_r(g.n, sh.R, false), pi = make_plan_r(g.n, sh.R, true);
-    size_t lds = (size_t)sh.width * g.n * sizeof(float2);
-    ColGeom cg = cols_x(g, sh.width);
-    dim3 grid((unsigned)col_blocks(cg, g, false), n_real), block(sh.width * pf.T);
-    float gscale = 1.0f / ((float)g.n * (float)g.n * (float)g.n);
-    hipError_t err = hipSuccess;
-    hipError_t de = dispatch_r(pf.R, [&](auto rr) {
-        auto kern = k_fft_x_green<decltype(rr)::value>;
-        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_X_GREEN, st, g.n);
-        hipLaunchKernelGGL(kern, grid, block, lds, st, S, A, B, bstride, cg, pf, pi, tw, kf, gscale);
-    });
-    if (err != hipSuccess) return err;
-    return de;
+    FftLaunch L;
+    L.op = OP_X_GREEN;
+    L.cg = cols_x(g, sh.width);
+    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.grid = dim3((unsigned)col_blocks(L.cg, g, false), n_real);
+    L.block = dim3(sh.width * (g.n / sh.R));
+    L.st = st;
+    L.c0 = S;
+    L.d0 = A;
+    L.d1 = B;
+    L.b0 = bstride;
+    L.tw = tw;
+    L.kf = kf;
+    L.scale = 1.0f / ((float)g.n * (float)g.n * (float)g.n);
+    ProfScope ps(PROF_X_GREEN, st, g.n);
+    return launch_shape(L, g.n, sh);
 }
 
 static hipError_t run_y_split_shape(float2* A, float2* S, long bstride, const Mesh3& g, const float2* tw,
                                     float kf, int n_real, const FftShape& sh, hipStream_t st) {
-    FftPlan pl = make_plan_r(g.n, sh.R, false);
-    size_t lds = (size_t)sh.width * g.n * sizeof(float2);
-    ColGeom cg = cols_y(g, sh.width);
-    dim3 grid((unsigned)col_blocks(cg, g, true), n_real), block(sh.width * pl.T);
-    hipError_t err = hipSuccess;
-    hipError_t de = dispatch_r(pl.R, [&](auto rr) {
-        auto kern = k_fft_y_split<decltype(rr)::value>;
-        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_Y_SPLIT, st, g.n);
-        hipLaunchKernelGGL(kern, grid, block, lds, st, A, S, bstride, cg, pl, tw, kf);
-    });
-    if (err != hipSuccess) return err;
-    return de;
+    FftLaunch L;
+    L.op = OP_Y_SPLIT;
+    L.cg = cols_y(g, sh.width);
+    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.grid = dim3((unsigned)col_blocks(L.cg, g, true), n_real);
+    L.block = dim3(sh.width * (g.n / sh.R));
+    L.st = st;
+    L.d0 = A;
+    L.d1 = S;
+    L.b0 = bstride;
+    L.tw = tw;
+    L.kf = kf;
+    ProfScope ps(PROF_Y_SPLIT, st, g.n);
+    return launch_shape(L, g.n, sh);
 }
 
 static hipError_t run_x_mult_shape(const float2* spec, long spec_bstride, float2* work, long work_bstride,
                                    const Mesh3& g, const float2* tw, int n_real, int mtype, int axis_a,
                                    int axis_b, float kf, float scale, const FftShape& sh, hipStream_t st) {
-    FftPlan pl = make_plan_r(g.n, sh.R, false);
-    size_t lds = (size_t)sh.width * g.n * sizeof(float2);
-    ColGeom cg = cols_x(g, sh.width);
-    dim3 grid((unsigned)col_blocks(cg, g, false), n_real), block(sh.width * pl.T);
-    hipError_t err = hipSuccess;
-    hipError_t de = dispatch_r(pl.R, [&](auto rr) {
-        auto kern = k_fft_x_mult<decltype(rr)::value>;
-        if (hipError_t ea = allow_lds(kern, lds); ea != hipSuccess) { err = ea; return; }
-        ProfScope ps(PROF_X_INV_MULT, st, g.n);
-        hipLaunchKernelGGL(kern, grid, block, lds, st, spec, spec_bstride, work, work_bstride, cg, pl, tw,
-                           mtype, axis_a, axis_b, kf, scale);
-    });
-    if (err != hipSuccess) return err;
-    return de;
+    FftLaunch L;
+    L.op = OP_X_MULT;
+    L.cg = cols_x(g, sh.width);
+    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.grid = dim3((unsigned)col_blocks(L.cg, g, false), n_real);
+    L.block = dim3(sh.width * (g.n / sh.R));
+    L.st = st;
+    L.c0 = spec;
+    L.b0 = spec_bstride;
+    L.d0 = work;
+    L.b1 = work_bstride;
+    L.tw = tw;
+    L.mtype = mtype;
+    L.ax_a = axis_a;
+    L.ax_b = axis_b;
+    L.kf = kf;
+    L.scale = scale;
+    ProfScope ps(PROF_X_INV_MULT, st, g.n);
+    return launch_shape(L, g.n, sh);
 }
 
 hipError_t fft_zy_forward(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
@@ -723,11 +515,12 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
         std::vector<FftShape> cands;
         for (int R : valid_rs(L))
             for (int w : {1, 2, 4, 8, 16, 32, 64}) {
-                FftShape sh{R, w};
+                FftShape sh{R, w, false};
                 if (!shape_ok(kind, n, sh)) continue;
                 long threads = (long)w * (L / R);
                 if (threads < 64 && w < 64) continue;
                 cands.push_back(sh);
+                if (static_available(kind, n, R, w)) cands.push_back(FftShape{R, w, true});
             }
         if (cands.empty()) continue;
         auto launch = [&](const FftShape& sh) -> hipError_t {
@@ -774,8 +567,9 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
         }
         if (report) {
             char line[160];
-            std::snprintf(line, sizeof(line), "n=%d %s: R=%d width=%d %.3f ms (%zu shapes)\n", n,
-                          kFftKindName[k], best_sh.R, best_sh.width, best, cands.size());
+            std::snprintf(line, sizeof(line), "n=%d %s: R=%d width=%d %s %.3f ms (%zu shapes)\n", n,
+                          kFftKindName[k], best_sh.R, best_sh.width, best_sh.stat ? "static" : "dynamic", best,
+                          cands.size());
             *report += line;
         }
     }

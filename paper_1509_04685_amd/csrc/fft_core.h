@@ -239,4 +239,149 @@ __device__ __forceinline__ void fft_line(float2 (&v)[R], const FftPlan& pl, floa
     }
 }
 
+// ------------------------------------------------------------------ line engines
+//
+// The kernels are written against a line engine that owns the plan: DynLine runs a plan built on
+// the host (any size), StatLine a plan fixed at compile time for one line length N, values per
+// thread R and LDS element stride LES.  With every stage's radix, product ns and LDS offset known
+// to the compiler, the static engine's index arithmetic folds into constants and LDS instruction
+// offsets; its radix order is the host plan's (3s first, then 8s, 4s, 2s; reversed for REV).
+
+template <int R>
+struct DynLine {
+    static constexpr int kR = R;
+    static constexpr bool kStatic = false;
+    FftPlan p;
+    int les;
+    __device__ int T() const { return p.T; }
+    __device__ int n() const { return p.n; }
+    template <class F>
+    __device__ __forceinline__ void first(int t, F&& f) const { for_pattern<R>(p.radix[0], t, p.T, p.nr[0], f); }
+    template <class F>
+    __device__ __forceinline__ void last(int t, F&& f) const {
+        for_pattern<R>(p.radix[p.nst - 1], t, p.T, p.nr[p.nst - 1], f);
+    }
+    template <bool INV>
+    __device__ __forceinline__ void run(float2 (&v)[R], float2* lds, int t, const float2* tw, bool active) const {
+        fft_line<R, INV>(v, p, lds, les, t, tw, active);
+    }
+};
+
+struct Radices {
+    int nst;
+    int r[kMaxStages];
+};
+
+constexpr Radices static_radices(int n, int R, bool rev) {
+    Radices s{0, {}};
+    int m = n, k = 0;
+    while (m % 3 == 0) { s.r[k++] = 3; m /= 3; }
+    while (R % 8 == 0 && m % 8 == 0) { s.r[k++] = 8; m /= 8; }
+    while (R % 4 == 0 && m % 4 == 0) { s.r[k++] = 4; m /= 4; }
+    while (m % 2 == 0) { s.r[k++] = 2; m /= 2; }
+    s.nst = k;
+    if (rev)
+        for (int i = 0; i < k / 2; ++i) {
+            int tmp = s.r[i];
+            s.r[i] = s.r[k - 1 - i];
+            s.r[k - 1 - i] = tmp;
+        }
+    return s;
+}
+
+constexpr int radices_ns(const Radices& s, int st) {
+    int ns = 1;
+    for (int i = 0; i < st; ++i) ns *= s.r[i];
+    return ns;
+}
+
+constexpr bool static_plan_ok(int n, int R) {
+    if (R < 2 || n % R) return false;
+    Radices s = static_radices(n, R, false);
+    int prod = 1;
+    for (int i = 0; i < s.nst; ++i) {
+        if (R % s.r[i]) return false;
+        prod *= s.r[i];
+    }
+    return prod == n;
+}
+
+// N: line length; R: values per thread; LES: LDS element stride (float2); TWS: twiddle table
+// stride (the table holds exp(-2 pi i m / (N TWS))); REV: reversed radix order.
+template <int N, int R, int LES, int TWS, bool REV>
+struct StatLine {
+    static_assert(static_plan_ok(N, R), "no static plan for this line length and R");
+    static constexpr int kR = R;
+    static constexpr bool kStatic = true;
+    static constexpr int kT = N / R;
+    static constexpr Radices kRad = static_radices(N, R, REV);
+    static constexpr int kFirst = kRad.r[0];
+    static constexpr int kLast = kRad.r[kRad.nst - 1];
+    __device__ static constexpr int T() { return kT; }
+    __device__ static constexpr int n() { return N; }
+
+    template <int r, class F>
+    __device__ __forceinline__ static void pattern(int t, F&& f) {
+#pragma unroll
+        for (int s = 0; s < R / r; ++s)
+#pragma unroll
+            for (int i = 0; i < r; ++i) f(s * r + i, t + s * kT + i * (N / r));
+    }
+    template <class F>
+    __device__ __forceinline__ void first(int t, F&& f) const { pattern<kFirst>(t, f); }
+    template <class F>
+    __device__ __forceinline__ void last(int t, F&& f) const { pattern<kLast>(t, f); }
+
+    template <bool INV, int ST>
+    __device__ __forceinline__ static void stage(float2 (&v)[R], float2* lds, int t, const float2* tw,
+                                                 bool active) {
+        if constexpr (ST < kRad.nst) {
+            constexpr int r = kRad.r[ST];
+            constexpr int ns = radices_ns(kRad, ST);
+            constexpr int tstep = (N / (ns * r)) * TWS;
+            if (active) {
+#pragma unroll
+                for (int s = 0; s < R / r; ++s) {
+                    float2* a = &v[s * r];
+                    if constexpr (ns > 1) {
+                        const int j = t + s * kT;
+                        const int step = tstep * (j % ns);
+#pragma unroll
+                        for (int i = 1; i < r; ++i) a[i] = twiddle<INV>(a[i], tw[i * step]);
+                    }
+                    if constexpr (r == 2) dft2<INV>(a[0], a[1]);
+                    if constexpr (r == 3) dft3<INV>(a[0], a[1], a[2]);
+                    if constexpr (r == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
+                    if constexpr (r == 8) dft8<INV>(a);
+                }
+            }
+            if constexpr (ST + 1 < kRad.nst) {
+                constexpr int rn = kRad.r[ST + 1];
+                if (active) {
+#pragma unroll
+                    for (int s = 0; s < R / r; ++s) {
+                        const int j = t + s * kT;
+                        const int base = (j / ns) * ns * (r - 1) + j;  // (j/ns) ns r + j%ns
+#pragma unroll
+                        for (int i = 0; i < r; ++i) lds[(base + i * ns) * LES] = v[s * r + i];
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int s = 0; s < R / rn; ++s)
+#pragma unroll
+                        for (int i = 0; i < rn; ++i) v[s * rn + i] = lds[(t + s * kT + i * (N / rn)) * LES];
+                }
+                __syncthreads();
+                stage<INV, ST + 1>(v, lds, t, tw, active);
+            }
+        }
+    }
+    template <bool INV>
+    __device__ __forceinline__ void run(float2 (&v)[R], float2* lds, int t, const float2* tw, bool active) const {
+        stage<INV, 0>(v, lds, t, tw, active);
+    }
+};
+
 }  // namespace cola

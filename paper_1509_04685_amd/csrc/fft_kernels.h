@@ -1,0 +1,425 @@
+// FFT pass kernels, written against a line engine (DynLine: host-built plan, any size;
+// StatLine: plan fixed at compile time), and their launch helpers.  Included by fft.hip (the
+// host logic and the dynamic instantiations) and by the fft_static_*.hip files (the static
+// instantiations for the mesh sizes of the workloads).
+//
+// Layout: a half spectrum [x][y][kz] of float2 with kz rows padded to nzp (a multiple of 16, so
+// rows start on 128-byte lines); the same memory holds the real field as [x][y][2 nzp] floats.
+//   z: contiguous rows, real <-> half complex via an n/2-point complex FFT plus a split step;
+//   y, x: strided columns, a tile of TK adjacent columns per block so that every row access
+//         moves TK * 8 contiguous bytes.
+#pragma once
+
+#include "cola_internal.h"
+
+namespace cola {
+
+// ------------------------------------------------------------------ column geometry
+
+// Columns of a realization's padded spectrum (offsets fit 32 bits: meshes up to 1536^3).
+struct ColGeom {
+    int es;           // element stride along the transform axis (float2)
+    int inner;        // contiguous columns per outer block
+    int outer_stride;
+    int nzp;          // columns c are valid when c % nzp < mvalid
+    int mvalid;
+    int tk;           // columns per tile
+    int tiles;        // tiles per outer block
+};
+
+// Block b runs on XCD b % 8 (round-robin dispatch); hand each XCD a contiguous run of tiles so
+// that neighbouring tiles, which share 128-byte lines when a tile row is narrower than a line,
+// meet in the same L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// TK > 0: columns per tile fixed at compile time (cg.tk is then equal to it).
+template <int TK>
+__device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& base, int& c) {
+    const int tk = TK > 0 ? TK : cg.tk;
+    const int ct = threadIdx.x % tk;
+    t = threadIdx.x / tk;
+    const int blk = xcd_block();
+    const int outer = blk / cg.tiles;
+    const int tile = blk - outer * cg.tiles;
+    c = tile * tk + ct;
+    base = (uint32_t)outer * (uint32_t)cg.outer_stride + (uint32_t)c;
+    return c < cg.inner && (c % cg.nzp) < cg.mvalid;
+}
+
+__device__ __forceinline__ int signed_mode(int e, int n) { return e < n / 2 ? e : e - n; }
+
+// ------------------------------------------------------------------ z pass: real -> half complex
+
+// Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
+// X_k = (Z_k + conj Z_{M-k})/2 - i W_n^k (Z_k - conj Z_{M-k})/2, k = 0..M.
+template <class LE>
+__global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row, long in_bstride,
+                                                   float2* out, long out_row, long out_bstride,
+                                                   long nrows, LE eng, const float2* tw,
+                                                   float pa, float pb) {
+    constexpr int R = LE::kR;
+    extern __shared__ float2 lds[];
+    const int T = eng.T(), M = eng.n();
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const long row = (long)blockIdx.x * (blockDim.x / T) + line;
+    const bool active = row < nrows;
+    in += (long)blockIdx.y * in_bstride;
+    out += (long)blockIdx.y * out_bstride;
+    float2* L = lds + line * (M + 1);
+    float2 v[R];
+    if (active) {
+        const float2* src = reinterpret_cast<const float2*>(in + row * in_row);
+        eng.first(t, [&](int q, int e) {
+            float2 z = src[e];
+            v[q] = make_float2(fmaf(z.x, pa, pb), fmaf(z.y, pa, pb));
+        });
+    }
+    eng.template run<false>(v, L, t, tw, active);
+    if (active) eng.last(t, [&](int q, int e) { L[e] = v[q]; });
+    __syncthreads();
+    if (!active) return;
+    float2* dst = out + row * out_row;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        int k = t + u * T;
+        float2 zk = L[k];
+        float2 zc = cconj(L[k == 0 ? 0 : M - k]);
+        float2 e = cscale(cadd(zk, zc), 0.5f);
+        float2 d = csub(zk, zc);
+        float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
+        dst[k] = cadd(e, cmul(tw[k], o));
+    }
+    if (t == 0) {
+        float2 z0 = L[0];
+        dst[M] = make_float2(z0.x - z0.y, 0.0f);
+    }
+}
+
+// ------------------------------------------------------------------ z pass: half complex -> real
+
+// Z_k = (X_k + conj X_{M-k}) + i conj(W_n^k) (X_k - conj X_{M-k}); x_{2j} + i x_{2j+1} = IFFT_M(Z)_j.
+// MUL_IKZ multiplies X by i k_z first (the kz = M Nyquist column becomes 0).
+template <class LE, bool MUL_IKZ>
+__global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row, long in_bstride,
+                                                   float* out, long out_row, long out_bstride,
+                                                   long nrows, LE eng, const float2* tw,
+                                                   float kf, float scale) {
+    constexpr int R = LE::kR;
+    extern __shared__ float2 lds[];
+    const int T = eng.T(), M = eng.n();
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const long row = (long)blockIdx.x * (blockDim.x / T) + line;
+    const bool active = row < nrows;
+    in += (long)blockIdx.y * in_bstride;
+    out += (long)blockIdx.y * out_bstride;
+    float2* L = lds + line * (M + 1);
+    if (active) {
+        // issue all R loads of this thread before the first LDS store
+        const float2* src = in + row * in_row;
+        float2 x[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) x[u] = src[t + u * T];
+        float2 xm = (t == 0) ? src[M] : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            int e = t + u * T;
+            float2 y = x[u];
+            if (MUL_IKZ) {
+                float kz = kf * (float)e;
+                y = make_float2(-kz * y.y, kz * y.x);
+            }
+            L[e] = cscale(y, scale);
+        }
+        if (t == 0) L[M] = MUL_IKZ ? make_float2(0.0f, 0.0f) : cscale(xm, scale);  // kz Nyquist
+    }
+    __syncthreads();
+    float2 v[R];
+    if (active) {
+        eng.first(t, [&](int q, int k) {
+            float2 xk = L[k];
+            float2 xc = cconj(L[M - k]);
+            float2 d = cmul(cconj(tw[k]), csub(xk, xc));
+            v[q] = make_float2(xk.x + xc.x - d.y, xk.y + xc.y + d.x);  // (xk + xc) + i d
+        });
+    }
+    __syncthreads();
+    eng.template run<true>(v, L, t, tw, active);
+    if (!active) return;
+    float2* dst = reinterpret_cast<float2*>(out + row * out_row);
+    eng.last(t, [&](int q, int e) { dst[e] = v[q]; });
+}
+
+// ------------------------------------------------------------------ strided column passes
+
+template <class LE, int TK, bool INV>
+__global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, ColGeom cg, LE eng,
+                                                  const float2* tw) {
+    constexpr int R = LE::kR;
+    extern __shared__ float2 lds[];
+    int t, c;
+    uint32_t base;
+    const bool active = col_setup<TK>(cg, t, base, c);
+    data += (long)blockIdx.y * bstride;
+    const uint32_t es = (uint32_t)cg.es;
+    float2 v[R];
+    if (active) eng.first(t, [&](int q, int e) { v[q] = data[base + (uint32_t)e * es]; });
+    eng.template run<INV>(v, lds + threadIdx.x % (TK > 0 ? TK : cg.tk), t, tw, active);
+    if (!active) return;
+    eng.last(t, [&](int q, int e) { data[base + (uint32_t)e * es] = v[q]; });
+}
+
+// Fused x pass of the particle-mesh force.  Columns are (y, kz); the transform axis is x.
+// Forward x FFT, V = S / (k^2 n^3) (k = 0 -> 0), then A = IFFT_x[V] and B = IFFT_x[i k_x V]
+// (the k_x Nyquist plane of B set to 0).  ef: forward engine; ei: the same radices reversed, so
+// the inverse starts from the forward's output pattern without an LDS round trip.
+template <class LF, class LI, int TK>
+__global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A, float2* B, long bstride,
+                                                     ColGeom cg, LF ef, LI ei, const float2* tw, float kf,
+                                                     float gscale) {
+    constexpr int R = LF::kR;
+    extern __shared__ float2 lds[];
+    int t, c;
+    uint32_t base;
+    const bool active = col_setup<TK>(cg, t, base, c);
+    const long boff = (long)blockIdx.y * bstride;
+    S += boff;
+    A += boff;
+    B += boff;
+    const uint32_t es = (uint32_t)cg.es;
+    const int n = ef.n();
+    const int yrow = c / cg.nzp;
+    const int my = signed_mode(yrow, n), mz = c - yrow * cg.nzp;
+    float2* L = lds + threadIdx.x % (TK > 0 ? TK : cg.tk);
+    float2 v[R], h[R];
+    if (active) ef.first(t, [&](int q, int e) { v[q] = S[base + (uint32_t)e * es]; });
+    ef.template run<false>(v, L, t, tw, active);
+    const float kyz2 = (float)(my * my + mz * mz);
+    const float g0 = gscale / (kf * kf);
+    ef.last(t, [&](int q, int e) {
+        int mx = signed_mode(e, n);
+        float m2 = (float)(mx * mx) + kyz2;
+        float gk = (m2 > 0.0f) ? g0 * __frcp_rn(m2) : 0.0f;
+        v[q] = cscale(v[q], gk);
+        float kx = (2 * mx == -n) ? 0.0f : kf * (float)mx;
+        h[q] = make_float2(-kx * v[q].y, kx * v[q].x);  // i k_x V
+    });
+    ei.template run<true>(v, L, t, tw, active);
+    if (active) ei.last(t, [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
+    ei.template run<true>(h, L, t, tw, active);
+    if (!active) return;
+    ei.last(t, [&](int q, int e) { B[base + (uint32_t)e * es] = h[q]; });
+}
+
+// y inverse of A giving two outputs: A <- IFFT_y[i k_y A] (Nyquist of k_y set to 0) and
+// S <- IFFT_y[A].  Columns are kz within one x plane.
+template <class LE, int TK>
+__global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long bstride, ColGeom cg, LE eng,
+                                                     const float2* tw, float kf) {
+    constexpr int R = LE::kR;
+    extern __shared__ float2 lds[];
+    int t, c;
+    uint32_t base;
+    const bool active = col_setup<TK>(cg, t, base, c);
+    const long boff = (long)blockIdx.y * bstride;
+    A += boff;
+    S += boff;
+    const uint32_t es = (uint32_t)cg.es;
+    const int n = eng.n();
+    float2* L = lds + threadIdx.x % (TK > 0 ? TK : cg.tk);
+    float2 v[R], h[R];
+    if (active) {
+        eng.first(t, [&](int q, int e) {
+            float2 a = A[base + (uint32_t)e * es];
+            h[q] = a;
+            int my = signed_mode(e, n);
+            float ky = (2 * my == -n) ? 0.0f : kf * (float)my;
+            v[q] = make_float2(-ky * a.y, ky * a.x);
+        });
+    }
+    eng.template run<true>(v, L, t, tw, active);
+    if (active) eng.last(t, [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
+    eng.template run<true>(h, L, t, tw, active);
+    if (!active) return;
+    eng.last(t, [&](int q, int e) { S[base + (uint32_t)e * es] = h[q]; });
+}
+
+// x inverse with a multiplier taken from the full spectrum: W = IFFT_x[M(k) spec].
+//   MUL_SCALE: M = scale;  MUL_IK: M = i k_a / k^2 * scale;  MUL_KK: M = k_a k_b / k^2 * scale.
+// A factor k_d is zeroed on the Nyquist plane of axis d when it appears to an odd power.
+template <class LE, int TK>
+__global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spec_bstride, float2* W,
+                                                    long w_bstride, ColGeom cg, LE eng, const float2* tw,
+                                                    int mtype, int ax_a, int ax_b, float kf, float scale) {
+    constexpr int R = LE::kR;
+    extern __shared__ float2 lds[];
+    int t, c;
+    uint32_t base;
+    const bool active = col_setup<TK>(cg, t, base, c);
+    spec += (long)blockIdx.y * spec_bstride;
+    W += (long)blockIdx.y * w_bstride;
+    const uint32_t es = (uint32_t)cg.es;
+    const int n = eng.n();
+    const int yrow = c / cg.nzp;
+    const int my = signed_mode(yrow, n);
+    const int mzr = c - yrow * cg.nzp;
+    const int mz = (2 * mzr == n) ? -mzr : mzr;  // the kz = n/2 column is the Nyquist plane
+    float2 v[R];
+    if (active) {
+        eng.first(t, [&](int q, int e) {
+            float2 x = spec[base + (uint32_t)e * es];
+            const int mx = signed_mode(e, n);
+            const int ma = ax_a == 0 ? mx : (ax_a == 1 ? my : mz);
+            const int mb = ax_b == 0 ? mx : (ax_b == 1 ? my : mz);
+            const float m2 = (float)(mx * mx + my * my + mz * mz);
+            float f = scale;
+            if (mtype == MUL_IK) {
+                const bool nyq = (2 * ma == -n);
+                f = (m2 > 0.0f && !nyq) ? scale * (float)ma / (kf * m2) : 0.0f;
+                x = make_float2(-f * x.y, f * x.x);
+            } else if (mtype == MUL_KK) {
+                const bool nyq = (ax_a != ax_b) && ((2 * ma == -n) || (2 * mb == -n));
+                f = (m2 > 0.0f && !nyq) ? scale * (float)ma * (float)mb / m2 : 0.0f;
+                x = cscale(x, f);
+            } else {
+                x = cscale(x, f);
+            }
+            v[q] = x;
+        });
+    }
+    eng.template run<true>(v, lds + threadIdx.x % (TK > 0 ? TK : cg.tk), t, tw, active);
+    if (!active) return;
+    eng.last(t, [&](int q, int e) { W[base + (uint32_t)e * es] = v[q]; });
+}
+
+// ------------------------------------------------------------------ launches
+
+enum FftOp { OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ, OP_COLS_FWD, OP_COLS_INV, OP_X_GREEN, OP_Y_SPLIT, OP_X_MULT };
+
+// Everything one pass launch needs; each op reads its own subset.
+struct FftLaunch {
+    FftOp op;
+    int n = 0;      // line length of the kernel's transform (n/2 for the z passes)
+    int R = 0;      // values per thread
+    int width = 0;  // lines per block (z) or columns per tile
+    bool probe = false;  // static launchers: only report whether the shape exists
+    dim3 grid, block;
+    size_t lds = 0;
+    hipStream_t st = nullptr;
+    // z passes
+    const float* rin = nullptr;
+    float* rout = nullptr;
+    const float2* cin = nullptr;
+    float2* cout = nullptr;
+    long in_row = 0, in_bstride = 0, out_row = 0, out_bstride = 0, nrows = 0;
+    float pa = 1.0f, pb = 0.0f;
+    // column passes: x_green (S = c0, A = d0, B = d1), y_split (A = d0, S = d1), cols (d0),
+    // x_mult (spec = c0, W = d0)
+    const float2* c0 = nullptr;
+    float2* d0 = nullptr;
+    float2* d1 = nullptr;
+    long b0 = 0, b1 = 0;
+    ColGeom cg{};
+    const float2* tw = nullptr;
+    float kf = 0.0f, scale = 1.0f;
+    int mtype = 0, ax_a = 0, ax_b = 0;
+};
+
+template <class K>
+inline hipError_t allow_lds_fft(K kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+template <class LE>
+inline hipError_t go_z_r2c(const FftLaunch& L, LE e) {
+    auto kern = k_fft_z_r2c<LE>;
+    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.rin, L.in_row, L.in_bstride, L.cout, L.out_row,
+                       L.out_bstride, L.nrows, e, L.tw, L.pa, L.pb);
+    return hipGetLastError();
+}
+
+template <class LE, bool MUL>
+inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
+    auto kern = k_fft_z_c2r<LE, MUL>;
+    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.cin, L.in_row, L.in_bstride, L.rout, L.out_row,
+                       L.out_bstride, L.nrows, e, L.tw, L.kf, L.scale);
+    return hipGetLastError();
+}
+
+template <class LE, int TK, bool INV>
+inline hipError_t go_cols(const FftLaunch& L, LE e) {
+    auto kern = k_fft_cols<LE, TK, INV>;
+    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.d0, L.b0, L.cg, e, L.tw);
+    return hipGetLastError();
+}
+
+template <class LF, class LI, int TK>
+inline hipError_t go_x_green(const FftLaunch& L, LF f, LI i) {
+    auto kern = k_fft_x_green<LF, LI, TK>;
+    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.c0, L.d0, L.d1, L.b0, L.cg, f, i, L.tw, L.kf, L.scale);
+    return hipGetLastError();
+}
+
+template <class LE, int TK>
+inline hipError_t go_y_split(const FftLaunch& L, LE e) {
+    auto kern = k_fft_y_split<LE, TK>;
+    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.d0, L.d1, L.b0, L.cg, e, L.tw, L.kf);
+    return hipGetLastError();
+}
+
+template <class LE, int TK>
+inline hipError_t go_x_mult(const FftLaunch& L, LE e) {
+    auto kern = k_fft_x_mult<LE, TK>;
+    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.c0, L.b0, L.d0, L.b1, L.cg, e, L.tw, L.mtype, L.ax_a,
+                       L.ax_b, L.kf, L.scale);
+    return hipGetLastError();
+}
+
+// Static-plan launchers for column passes of line length N with R values per thread and TK
+// columns per tile, and for z passes of line length M with R values per thread.
+template <int N, int R, int TK>
+inline hipError_t static_cols_ops(const FftLaunch& L) {
+    using F = StatLine<N, R, TK, 1, false>;
+    using I = StatLine<N, R, TK, 1, true>;
+    if (L.probe) return hipSuccess;
+    switch (L.op) {
+        case OP_COLS_FWD: return go_cols<F, TK, false>(L, F{});
+        case OP_COLS_INV: return go_cols<F, TK, true>(L, F{});
+        case OP_X_GREEN: return go_x_green<F, I, TK>(L, F{}, I{});
+        case OP_Y_SPLIT: return go_y_split<F, TK>(L, F{});
+        case OP_X_MULT: return go_x_mult<F, TK>(L, F{});
+        default: return hipErrorNotSupported;
+    }
+}
+
+template <int M, int R>
+inline hipError_t static_z_ops(const FftLaunch& L) {
+    using E = StatLine<M, R, 1, 2, false>;
+    if (L.probe) return hipSuccess;
+    switch (L.op) {
+        case OP_Z_R2C: return go_z_r2c<E>(L, E{});
+        case OP_Z_C2R: return go_z_c2r<E, false>(L, E{});
+        case OP_Z_C2R_IKZ: return go_z_c2r<E, true>(L, E{});
+        default: return hipErrorNotSupported;
+    }
+}
+
+// Static kernels of the workload mesh sizes (fft_static_<n>.hip): hipErrorNotSupported when the
+// file has no kernel of the launch's op, size and shape; with L.probe set nothing is launched.
+hipError_t fft_static_768(const FftLaunch& L);
+hipError_t fft_static_384(const FftLaunch& L);
+hipError_t fft_static_288(const FftLaunch& L);
+hipError_t fft_static_256(const FftLaunch& L);
+
+}  // namespace cola
