@@ -196,7 +196,9 @@ int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_by
 typedef struct {
     int32_t channels;    /* C: 16 or 32                                                       */
     float in_scale[4];   /* input normalisation of delta, g_x, g_y, g_z                        */
-    float out_scale;     /* output scale                                                       */
+    float out_scale;     /* output scale (at a = 1)                                            */
+    float out_scale_slope; /* in the step the scale at a node is out_scale (1 + slope (1 - a)); the
+                            other entry points use out_scale                                   */
     float* params;       /* device, cola_lc_param_count(C) floats, flat in the order
                             w1 (C,4,27) b1 (C) w2 (C,C,27) b2 (C) w3 (3,C) b3 (3), C order       */
     float* grads;        /* device, same size: cola_lc_backward adds into it, cola_lc_adam

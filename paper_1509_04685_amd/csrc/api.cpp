@@ -154,12 +154,14 @@ struct LcHook {
     long x0_stride;
     float in_scale[4];
     float out_scale;
+    float out_scale_slope;
+    float scale_at(double a) const { return (float)(out_scale * (1.0 + out_scale_slope * (1.0 - a))); }
 };
 
 // Density, forward transform and force meshes for the current positions.  Force meshes end up
 // as real rows in B (x), A (y), S (z); with a network hook, dF is added to them.
 hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, const ParticlePtrs& P,
-                         hipStream_t st, const LcHook* lc = nullptr) {
+                         hipStream_t st, const LcHook* lc = nullptr, double a_node = 1.0) {
     const long npr = (long)p.n_part * p.n_part * p.n_part;
     LatticeGeom fg = force_geom(p, L);
     const double cells = (double)L.g.n * L.g.n * L.g.n;
@@ -186,7 +188,7 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
         LcActs a = lc->A;
         a.x0 = lc->A.x0 + r * lc->x0_stride;
         if ((e = lc_pack_force(fc, row, L.g.n, lc->in_scale + 1, a.x0, st)) != hipSuccess) return e;
-        if ((e = lc_forward(lc->P, a, L.g.n, lc->out_scale, f, row, 1, false, st)) != hipSuccess) return e;
+        if ((e = lc_forward(lc->P, a, L.g.n, lc->scale_at(a_node), f, row, 1, false, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -222,7 +224,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
 
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
-    if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st, lc));
+    if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j_begin]));
     double pending = 0.0;  // kick still owed to the current node (merged with the next kick)
     for (int j = j_begin; j < j_end; ++j) {
         KickDrift kd;
@@ -233,7 +235,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
         kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
         kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
         COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
-        COLA_TRY(compute_force(p, L, w, P, st, lc));
+        COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j + 1]));
         pending = sc.k_in[j];
     }
     KickDrift kd{};
@@ -397,6 +399,7 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
     h.x0_stride = LL.x0_stride;
     for (int i = 0; i < 4; ++i) h.in_scale[i] = net->in_scale[i];
     h.out_scale = net->out_scale;
+    h.out_scale_slope = net->out_scale_slope;
     return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, &h);
 }
 

@@ -52,7 +52,7 @@ int lc_check_net(const cola_lc_net* net, bool training) {
     if (net->channels != 16 && net->channels != 32) return COLA_ERR_INVALID_ARG;
     for (int i = 0; i < 4; ++i)
         if (!std::isfinite(net->in_scale[i])) return COLA_ERR_INVALID_ARG;
-    if (!std::isfinite(net->out_scale)) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(net->out_scale) || !std::isfinite(net->out_scale_slope)) return COLA_ERR_INVALID_ARG;
     if (training && (!net->grads || !net->adam_m || !net->adam_v)) return COLA_ERR_INVALID_ARG;
     return COLA_OK;
 }

@@ -144,11 +144,44 @@ def load_net(path, training=False):
     import json
     with open(path) as fh:
         doc = json.load(fh)
-    return LcNet(int(doc["channels"]), params=np.asarray(doc["params"], dtype=np.float32),
-                 in_scale=doc["in_scale"], out_scale=doc["out_scale"], training=training), doc
+    net = LcNet(int(doc["channels"]), params=np.asarray(doc["params"], dtype=np.float32),
+                in_scale=doc["in_scale"], out_scale=doc["out_scale"], training=training)
+    net.set_scales(net.in_scale, net.out_scale, doc.get("out_scale_slope", 0.0))
+    return net, doc
 
 
 def max_error(k, pk, pk_ref, k_max=1.0):
     """max over bins with 0 < k < k_max of |pk / pk_ref - 1| (host arrays)."""
     sel = (k > 0) & (k < k_max) & (pk_ref > 0)
     return float(np.abs(pk[sel] / pk_ref[sel] - 1.0).max())
+
+
+def calibrate_out_scale(net, cosmo, box, n_part, z_init, n_steps, seeds, factors, slopes=(0.0,), n_pk=None,
+                        k_max=1.0, log=None):
+    """Trajectory-level calibration of the output scale on training realizations.  For each factor
+    f and slope s the step uses out_scale * f * (1 + s (1 - a)) at a node of scale factor a; every
+    seed's corrected PM_grid = 1 realization is compared at the last node with the plain
+    PM_grid = 3 run of the same seed, by max over 0 < k < k_max of |P / P_3x - 1|, and the pair
+    with the smallest worst case wins.  A network fitted to noisy force residuals underestimates
+    the correction (regression dilution); this picks the scale on the training seeds only.  Sets
+    the best scale on the network and returns (out_scale, slope, table of (f, s, error))."""
+    n_pk = n_pk or n_part * 3
+    n_bins = n_pk // 2
+    base = net.out_scale
+    prob1 = make_problem(box, n_part, 1, z_init, n_steps)
+    prob3 = make_problem(box, n_part, 3, z_init, n_steps)
+    refs = [run_spectra(prob3, cosmo, s, (1.0,), n_pk, n_bins)[0] for s in seeds]
+    table = []
+    for f in factors:
+        for sl in slopes:
+            net.set_scales(net.in_scale, base * f, sl)
+            worst = 0.0
+            for s, (k, p3) in zip(seeds, refs):
+                _, plc = run_spectra(prob1, cosmo, s, (1.0,), n_pk, n_bins, net=net)[0]
+                worst = max(worst, max_error(k, plc, p3, k_max))
+            table.append((float(f), float(sl), worst))
+            if log:
+                log(f"[calibrate] factor {f:.3f} slope {sl:+.2f}: worst max |P/P_3x - 1| {worst:.4f}")
+    best = min(table, key=lambda x: x[2])
+    net.set_scales(net.in_scale, base * best[0], best[1])
+    return net.out_scale, net.out_scale_slope, table
