@@ -84,7 +84,8 @@ def node_index(table, a_out):
     return max(0, min(j, len(a) - 1))
 
 
-KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h"), "cic": ("deposit_sorted.hip",),
+KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h", "fft_kernels.h", "fft_static_768.hip", "fft_static_384.hip",
+                          "fft_static_288.hip", "fft_static_256.hip"), "cic": ("deposit_sorted.hip",),
                   "pk_deposit": ("deposit_sorted.hip",), "gather": ("pm_kernels.hip",), "lc": ("lc_kernels.hip",)}
 
 
