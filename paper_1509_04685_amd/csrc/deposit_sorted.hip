@@ -295,8 +295,15 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
     }
     __syncthreads();
     const uint32_t total = rlen[14];
+    // Each thread sweeps a contiguous chunk of the concatenated records, so that the lanes of a
+    // wave work on records far apart in the sorted order: records of one key range are in
+    // Lagrangian order, and neighbouring particles hit the same cells -- consecutive records on
+    // consecutive lanes would serialise the LDS atomics.
+    const uint32_t chunk = (total + blockDim.x - 1) / blockDim.x;
+    const uint32_t i0 = threadIdx.x * chunk;
+    const uint32_t i1 = min(total, i0 + chunk);
     int q = 0;
-    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) {
+    for (uint32_t i = i0; i < i1; ++i) {
         while (q < 13 && i >= rlen[q + 1]) ++q;  // i only grows, so q only moves forward
         const int d = kPulls[q].d;
         const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
