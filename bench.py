@@ -84,8 +84,8 @@ def node_index(table, a_out):
     return max(0, min(j, len(a) - 1))
 
 
-KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h", "fft_kernels.h", "fft_static_768.hip", "fft_static_384.hip",
-                          "fft_static_288.hip", "fft_static_256.hip"), "cic": ("deposit_sorted.hip",),
+KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h", "fft_kernels.h", "fft_static_1536.hip", "fft_static_768.hip",
+                          "fft_static_512.hip", "fft_static_384.hip", "fft_static_288.hip", "fft_static_256.hip"), "cic": ("deposit_sorted.hip",),
                   "pk_deposit": ("deposit_sorted.hip",), "gather": ("pm_kernels.hip",), "lc": ("lc_kernels.hip",)}
 
 
@@ -215,7 +215,7 @@ def ensemble_bench(cola, torch, reps):
     return out
 
 
-def learned_bench(cola, torch, cfg_plain, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps):
+def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps):
     """The learned-correction form: 256^3 particles on the 256^3 (PM_grid = 1) mesh with the trained
     network, against the plain 3x realization timed above (same seed, same outputs) and the plain
     1x run without the network."""
@@ -224,7 +224,10 @@ def learned_bench(cola, torch, cfg_plain, pk_plain3, a_outs, n_pk, n_bins, ms_pl
     if not os.path.exists(path):
         return {"skipped": "no trained weights (run paper_1509_04685_amd/train_lc.py)"}
     net, doc = L.load_net(path)
-    c = W.CONFIGS["learned_256_256"]
+    lname = {"plain_256_768": "learned_256_256", "plain_512_1536": "learned_512_512"}.get(cfg_name)
+    if lname is None:
+        return {"skipped": f"no learned workload beside {cfg_name}"}
+    c = W.CONFIGS[lname]
     prob = cola.make_problem(c["box"], c["n_part"], c["pm_factor"], c["z_init"], c["n_steps"])
     cosmo = cola.make_cosmology(**W.COSMOLOGY)
     table = cola.schedule_table(prob, cosmo)
@@ -273,9 +276,9 @@ def learned_bench(cola, torch, cfg_plain, pk_plain3, a_outs, n_pk, n_bins, ms_pl
                       f"scale calibrated on training seeds 3001-3002: factor "
                       f"{net.out_scale / doc.get('out_scale_fitted', net.out_scale):.2f}, slope "
                       f"{net.out_scale_slope:+.2f} in (1 - a); evaluation seed {c['seeds'][0]} held out")
-    res["workload"] = (f"256^3 particles, 256^3 mesh (PM_grid 1), box 768, 40 nodes from z=19, seed "
-                       f"{c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = max over 0<k<1 h/Mpc "
-                       f"of |P/P_plain3x - 1| at z=0")
+    res["workload"] = (f"{lname}: {c['n_part']}^3 particles, {c['n_part']}^3 mesh (PM_grid 1), box {c['box']:g}, "
+                       f"40 nodes from z=19, seed {c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = "
+                       f"max over 0<k<1 h/Mpc of |P/P_plain3x - 1| at z=0")
     return res
 
 
@@ -416,8 +419,8 @@ def main():
         roofline["copy_ceiling_gbs"] = copy_ceiling(cola, torch)
     if not args.no_learned:
         print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
-        result["learned"] = learned_bench(cola, torch, cfg, outs[-1][1].cpu().numpy()[0], a_outs, n_pk, n_bins,
-                                          ms_per_step, reps=2)
+        result["learned"] = learned_bench(cola, torch, args.workload, outs[-1][1].cpu().numpy()[0], a_outs, n_pk,
+                                          n_bins, ms_per_step, reps=2)
         print(f"[bench] learned: {json.dumps(result['learned'])}", file=sys.stderr, flush=True)
     if not args.no_ensemble:
         del st, ws, outs

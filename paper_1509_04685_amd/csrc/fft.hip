@@ -176,7 +176,9 @@ static FftOp op_of(FftKind k) {
 // Routes a launch to the static kernels of its mesh size (n: the mesh side).
 static hipError_t launch_static(const FftLaunch& L, int n) {
     switch (n) {
+        case 1536: return fft_static_1536(L);
         case 768: return fft_static_768(L);
+        case 512: return fft_static_512(L);
         case 384: return fft_static_384(L);
         case 288: return fft_static_288(L);
         case 256: return fft_static_256(L);

@@ -417,7 +417,9 @@ inline hipError_t static_z_ops(const FftLaunch& L) {
 
 // Static kernels of the workload mesh sizes (fft_static_<n>.hip): hipErrorNotSupported when the
 // file has no kernel of the launch's op, size and shape; with L.probe set nothing is launched.
+hipError_t fft_static_1536(const FftLaunch& L);
 hipError_t fft_static_768(const FftLaunch& L);
+hipError_t fft_static_512(const FftLaunch& L);
 hipError_t fft_static_384(const FftLaunch& L);
 hipError_t fft_static_288(const FftLaunch& L);
 hipError_t fft_static_256(const FftLaunch& L);

@@ -31,6 +31,8 @@ CONFIGS = {
     # large: 512^3 particles, 1536^3 mesh
     "plain_512_1536": dict(box=1536.0, n_part=512, pm_factor=3, z_init=19.0, n_steps=40, seeds=(1,),
                            a_out=(1.0,)),
+    # the learned form beside it: 512^3 particles on the 512^3 mesh (same 3 h^-1 Mpc cells)
+    "learned_512_512": dict(box=1536.0, n_part=512, pm_factor=1, z_init=19.0, n_steps=40, seeds=(1,)),
 }
 
 
