@@ -264,6 +264,14 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
+        cola.profiler_enable(True)
+        realization(use_net)
+        groups = cola.profiler_read_groups()
+        cola.profiler_enable(False)
+        for (kname, tag), (kms, cnt) in sorted(groups.items(), key=lambda kv: -kv[1][0])[:10]:
+            label = f"{kname}@{tag}" if tag else kname
+            print(f"[bench]   {name:10s} {label:22s} {kms:8.2f} ms/realization  {cnt:5d} launches  "
+                  f"{kms / cnt:7.3f} ms/launch", file=sys.stderr, flush=True)
         k = outs[-1][0].cpu().numpy()[0]
         pk = outs[-1][1].cpu().numpy()[0]
         res[name] = {"ms_per_realization": round(ms, 2), "realizations_per_hour": round(3.6e6 / ms, 1),

@@ -261,12 +261,16 @@ __constant__ Pull kPulls[14] = {{0, 0, 8}, {4, 4, 8}, {2, 2, 4}, {2, 6, 8}, {1, 
 // fetched in parallel first, then all threads sweep their concatenation.
 __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long npr, float* mesh, long row,
                                                   long mesh_bstride, float scale, float offset) {
-    extern __shared__ float acc[];
+    // Cell masses accumulate as 32.32 fixed point in 64-bit integers: LDS integer atomics run at
+    // tens of times the rate of LDS float atomics on this hardware, and integer sums do not depend
+    // on the order of the adds (the deposit is bitwise reproducible).  A CIC weight is rounded to
+    // 2^-32; a cell overflows only beyond 2^32 particles.
+    extern __shared__ unsigned long long acc[];
     __shared__ uint32_t rb[14], rlen[15];
     const int r = blockIdx.y;
     const long tile = blockIdx.x;
     const int ncell = tg.tx * tg.ty * tg.tz;
-    for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = 0.0f;
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = 0ull;
     const int tzi = (int)(tile % tg.ntz);
     const int tyi = (int)((tile / tg.ntz) % tg.nty);
     const int txi = (int)(tile / ((long)tg.ntz * tg.nty));
@@ -324,29 +328,29 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
                 for (int cz = 0; cz < 2; ++cz) {
                     const int uz = hz + cz;
                     if (uz < 0 || uz >= tg.tz) continue;
-                    atomicAdd(&acc[(((ux << tg.ly) + uy) << tg.lz) + uz], wx[cx] * wy[cy] * wz[cz]);
+                    atomicAdd(&acc[(((ux << tg.ly) + uy) << tg.lz) + uz],
+                              __float2ull_rn(wx[cx] * wy[cy] * wz[cz] * 4294967296.0f));
                 }
             }
         }
     }
     __syncthreads();
     float* out = mesh + (long)r * mesh_bstride;
+    const double unit = 2.3283064365386962890625e-10;  // 2^-32
+    auto cell = [&](int i) { return fmaf((float)((double)acc[i] * unit), scale, offset); };
     if ((tg.tz & 3) == 0) {  // rows of the tile are whole float4s
-        const float4* acc4 = reinterpret_cast<const float4*>(acc);
         for (int i4 = threadIdx.x; i4 < (ncell >> 2); i4 += blockDim.x) {
             const int i = i4 << 2;
             const int uz = i & (tg.tz - 1), uy = (i >> tg.lz) & (tg.ty - 1), ux = i >> (tg.lz + tg.ly);
             const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
-            float4 a = acc4[i4];
-            a = make_float4(fmaf(a.x, scale, offset), fmaf(a.y, scale, offset), fmaf(a.z, scale, offset),
-                            fmaf(a.w, scale, offset));
+            const float4 a = make_float4(cell(i), cell(i + 1), cell(i + 2), cell(i + 3));
             *reinterpret_cast<float4*>(out + (gx * tg.n + gy) * row + gz) = a;
         }
     } else {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
             const int uz = i & (tg.tz - 1), uy = (i >> tg.lz) & (tg.ty - 1), ux = i >> (tg.lz + tg.ly);
             const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
-            out[(gx * tg.n + gy) * row + gz] = fmaf(acc[i], scale, offset);
+            out[(gx * tg.n + gy) * row + gz] = cell(i);
         }
     }
 }
@@ -407,7 +411,7 @@ hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const Lat
     if (e != hipSuccess) return e;
     {
         ProfScope ps(PROF_DEP_TILE, st);
-        size_t lds = (size_t)tg.tx * tg.ty * tg.tz * sizeof(float);
+        size_t lds = (size_t)tg.tx * tg.ty * tg.tz * sizeof(unsigned long long);
         hipLaunchKernelGGL(k_dep_tile, dim3((unsigned)tg.ntiles, n_real), dim3(256), lds, st, tg, sb, npr, mesh,
                            dg.row, dg.mesh_bstride, scale, offset);
     }
