@@ -27,14 +27,11 @@ namespace cola {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-__device__ __forceinline__ uint32_t f2bf(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return u >> 16;  // inf / nan kept
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
+// BF16 bits of a float, rounded to nearest even (the hardware conversion, v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float((h & 0xffffu) << 16); }
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware reciprocal (1 ulp): its result is stored in BF16
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_f(float z) { return z * sigm(z); }
 __device__ __forceinline__ float silu_g(float z) {
     const float s = sigm(z);
@@ -121,11 +118,17 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
         const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
         __syncthreads();  // the previous tile's readers are done with the halo
-        for (int i = tid; i < HVOX * C8; i += 256) {
-            const int c8 = i % C8, hv = i / C8;
-            const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
-            const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n), gz = wrap_halo(z0 + hz - 1, n);
-            sh[i] = ing[(((long)gx * n + gy) * n + gz) * C8 + c8];
+#pragma unroll
+        for (int k = 0; k < (HVOX + 255) / 256; ++k) {  // one halo voxel (all its channels) per thread
+            const int hv = tid + k * 256;
+            if (hv < HVOX) {
+                const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
+                const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n);
+                const int gz = wrap_halo(z0 + hz - 1, n);
+                const uint4* src = ing + (((long)gx * n + gy) * n + gz) * C8;
+#pragma unroll
+                for (int c8 = 0; c8 < C8; ++c8) sh[hv * C8 + c8] = src[c8];
+            }
         }
         __syncthreads();
         f32x4 acc[4][NB];
@@ -242,14 +245,22 @@ __global__ void __launch_bounds__(256) k_conv3_wgrad(const uint16_t* __restrict_
 #pragma unroll
             for (int h = 0; h < 8; ++h) sdz[(c8 * 8 + h) * SDZ + tv] = f.h[h];
         }
-        for (int i = tid; i < HVOX * (CINP / 8); i += 256) {
-            const int c8 = i % (CINP / 8), hv = i / (CINP / 8);
-            const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
-            const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n), gz = wrap_halo(z0 + hz - 1, n);
-            Frag8 f;
-            f.u = xg[(((long)gx * n + gy) * n + gz) * (CINP / 8) + c8];
 #pragma unroll
-            for (int h = 0; h < 8; ++h) sx[(c8 * 8 + h) * SXP + hv] = f.h[h];
+        for (int k = 0; k < (HVOX + 255) / 256; ++k) {
+            const int hv = tid + k * 256;
+            if (hv < HVOX) {
+                const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
+                const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n);
+                const int gz = wrap_halo(z0 + hz - 1, n);
+                const uint4* src = xg + (((long)gx * n + gy) * n + gz) * (CINP / 8);
+#pragma unroll
+                for (int c8 = 0; c8 < CINP / 8; ++c8) {
+                    Frag8 f;
+                    f.u = src[c8];
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) sx[(c8 * 8 + h) * SXP + hv] = f.h[h];
+                }
+            }
         }
         __syncthreads();
         if (tid < COP) {
