@@ -184,11 +184,9 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
     for (int r = 0; r < p.n_real; ++r) {
         float* f[3] = {reinterpret_cast<float*>(w.B) + r * bs, reinterpret_cast<float*>(w.A) + r * bs,
                        reinterpret_cast<float*>(w.S) + r * bs};
-        const float* fc[3] = {f[0], f[1], f[2]};
-        LcActs a = lc->A;
-        a.x0 = lc->A.x0 + r * lc->x0_stride;
-        if ((e = lc_pack_force(fc, row, L.g.n, lc->in_scale + 1, a.x0, st)) != hipSuccess) return e;
-        if ((e = lc_forward(lc->P, a, L.g.n, lc->scale_at(a_node), f, row, 1, false, st)) != hipSuccess) return e;
+        if ((e = lc_forward_fields(lc->P, lc->A.a1, lc->A.x0 + r * lc->x0_stride, f, row, L.g.n, lc->in_scale,
+                                   lc->scale_at(a_node), st)) != hipSuccess)
+            return e;
     }
     return hipSuccess;
 }

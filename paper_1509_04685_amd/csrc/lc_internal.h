@@ -60,9 +60,12 @@ hipError_t lc_pack_weights(const float* w1, const float* w2, int C, uint16_t* wb
 // X0 = (delta, g) * in_scale from meshes with `row` floats per (x, y) row.
 hipError_t lc_pack(const float* delta, const float* const g[3], long row, int n, const float in_scale[4],
                    uint16_t* x0, hipStream_t st);
-// Two halves of lc_pack for the step, where delta is overwritten by the transform before g exists.
-hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* x0, hipStream_t st);
-hipError_t lc_pack_force(const float* const g[3], long row, int n, const float s[3], uint16_t* x0, hipStream_t st);
+// The step's input path: delta * s0 saved as compact BF16 (d0, n^3 values) before the transform
+// overwrites the density; later the network reads d0 and the force meshes directly and adds dF
+// to the force meshes (a1: [n^3][C] BF16 scratch).
+hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* d0, hipStream_t st);
+hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row, int n,
+                             const float in_scale[4], float out_scale, hipStream_t st);
 // dF (times out_scale) written to, or added into, three meshes with `row` floats per row.  keep_z
 // stores z1, z2 for the backward pass.
 hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
@@ -89,7 +92,7 @@ hipError_t mesh_unpad(const float* src, long row, int n, float* dst, hipStream_t
 // training z1, z2, dz1, dz2.
 struct LcWsLayout {
     size_t x0 = 0, a1 = 0, a2 = 0, z1 = 0, z2 = 0, dz1 = 0, dz2 = 0, total = 0;
-    long x0_stride = 0;  // uint16 per realization
+    long x0_stride = 0;  // uint16 per realization (x0 holds n_real compact deltas in the step)
 };
 LcWsLayout lc_ws_layout(int n, int C, int n_real, bool training);
 LcActs lc_carve(void* ws, const LcWsLayout& L);

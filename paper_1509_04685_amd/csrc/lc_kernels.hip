@@ -91,16 +91,37 @@ constexpr int TV = TX * TY * TZ;
 
 __device__ __forceinline__ int wrap_halo(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-enum { EPI_ZA = 0, EPI_A = 1, EPI_DSILU = 2 };
+enum { EPI_ZA = 0, EPI_A = 1, EPI_DSILU = 2, EPI_OUT = 3 };
+
+// Inputs of the first layer taken straight from the step's fields (instead of a packed X0):
+// delta as BF16 (already scaled) and the three force meshes with `row` floats per row.
+struct FieldSrc {
+    const uint16_t* d0;
+    const float* g[3];
+    long row;
+    float s[3];
+};
+// The output layer fused into the second convolution: dF = (W3 silu(Z2) + b3) * scale added to
+// three meshes with `row` floats per row.
+struct OutDst {
+    float* f[3];
+    long row;
+    const float* w3;
+    const float* b3;
+    float scale;
+};
 
 // out[v][co] = sum_tap sum_ci W[co][tap][ci] in[v + d_tap][ci] + bias[co], then
 //   EPI_ZA: out = Z, out2 = silu(Z);  EPI_A: out = silu(Z);  EPI_DSILU: out = Z * silu'(prev[v][co]).
 // in: [V][CINP] BF16; W: [16 NB][27][CINP] BF16; out: [V][16 NB].  Block = 4 waves on a 4x4x16
 // tile, wave w computing the rows x0 + w, y0 + 0..3 (16 voxels along z each) for all outputs.
-template <int CINP, int NB, int EPI>
+//   EPI_OUT: the output layer, dF = (W3 silu(Z) + b3) * scale, added to the meshes of `od`.
+// FIELDS (first layer only, CINP = 8): the halo is built from `fs` instead of `in`.
+template <int CINP, int NB, int EPI, bool FIELDS = false>
 __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                                     const float* __restrict__ bias, uint16_t* out, uint16_t* out2,
-                                                    const uint16_t* __restrict__ prev, int n, int tiles) {
+                                                    const uint16_t* __restrict__ prev, int n, int tiles, FieldSrc fs,
+                                                    OutDst od) {
     constexpr int COP = 16 * NB;
     constexpr int KTOT = 27 * CINP;
     constexpr int KSTEPS = (KTOT + 31) / 32;
@@ -117,6 +138,7 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        const int y0v = y0;
         __syncthreads();  // the previous tile's readers are done with the halo
 #pragma unroll
         for (int k = 0; k < (HVOX + 255) / 256; ++k) {  // one halo voxel (all its channels) per thread
@@ -125,9 +147,17 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
                 const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
                 const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n);
                 const int gz = wrap_halo(z0 + hz - 1, n);
-                const uint4* src = ing + (((long)gx * n + gy) * n + gz) * C8;
+                if constexpr (FIELDS) {
+                    static_assert(C8 == 1, "field input has 4 channels (padded to 8)");
+                    const long v = ((long)gx * n + gy) * n + gz;
+                    const long o = ((long)gx * n + gy) * fs.row + gz;
+                    sh[hv] = make_uint4(fs.d0[v] | (f2bf(fs.g[0][o] * fs.s[0]) << 16),
+                                        f2bf(fs.g[1][o] * fs.s[1]) | (f2bf(fs.g[2][o] * fs.s[2]) << 16), 0u, 0u);
+                } else {
+                    const uint4* src = ing + (((long)gx * n + gy) * n + gz) * C8;
 #pragma unroll
-                for (int c8 = 0; c8 < C8; ++c8) sh[hv * C8 + c8] = src[c8];
+                    for (int c8 = 0; c8 < C8; ++c8) sh[hv * C8 + c8] = src[c8];
+                }
             }
         }
         __syncthreads();
@@ -162,6 +192,39 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
                     acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r].v, bf[b].v, acc[r][b], 0, 0, 0);
         }
         // lane holds voxels z0 + 4 kb + q of the row, output channel co = 16 b + m
+        if constexpr (EPI == EPI_OUT) {
+            // A2 (rounded to BF16 as in the stored-activation path) goes to LDS as [voxel][COP + 1]
+            // floats in the halo's space; then one thread per voxel forms the three outputs
+            constexpr int SP = COP + 1;
+            static_assert(TV * SP * 4 <= HVOX * CINP * 2, "staging must fit in the halo space");
+            float* stage = reinterpret_cast<float*>(sh);
+            __syncthreads();  // every wave is done reading the halo
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float bb = bias[b * 16 + m];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        stage[((wave * 4 + r) * 16 + 4 * kb + q) * SP + b * 16 + m] =
+                            bf2f(f2bf(silu_f(acc[r][b][q] + bb)));
+                }
+            __syncthreads();
+            float y0 = od.b3[0], y1 = od.b3[1], y2 = od.b3[2];
+#pragma unroll
+            for (int co = 0; co < COP; ++co) {
+                const float a = stage[tid * SP + co];
+                y0 += od.w3[co] * a;
+                y1 += od.w3[COP + co] * a;
+                y2 += od.w3[2 * COP + co] * a;
+            }
+            const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
+            const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + z0 + lz;
+            od.f[0][o] += y0 * od.scale;
+            od.f[1][o] += y1 * od.scale;
+            od.f[2][o] += y2 * od.scale;
+            continue;
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long vrow = ((long)(x0 + wave) * n + (y0 + r)) * n + z0 + 4 * kb;
@@ -189,16 +252,17 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
 
 static long conv_tiles(int n) { return (long)(n / TX) * (n / TY) * (n / TZ); }
 
-template <int CINP, int NB, int EPI>
+template <int CINP, int NB, int EPI, bool FIELDS = false>
 static hipError_t run_conv(const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, uint16_t* out2,
-                           const uint16_t* prev, int n, hipStream_t st) {
+                           const uint16_t* prev, int n, hipStream_t st, const FieldSrc& fs = FieldSrc{},
+                           const OutDst& od = OutDst{}) {
     const long tiles = conv_tiles(n);
     const size_t lds = (size_t)16 * NB * 27 * CINP * 2 + (size_t)HVOX * CINP * 2;
-    auto kern = k_conv3_mfma<CINP, NB, EPI>;
+    auto kern = k_conv3_mfma<CINP, NB, EPI, FIELDS>;
     if (hipError_t e = allow_lds_lc(kern, lds); e != hipSuccess) return e;
     ProfScope ps(PROF_LC_CONV, st);
     hipLaunchKernelGGL(kern, dim3((unsigned)std::min<long>(tiles, 4096)), dim3(256), lds, st, in, w, bias, out, out2,
-                       prev, n, (int)tiles);
+                       prev, n, (int)tiles, fs, od);
     return hipGetLastError();
 }
 
@@ -351,20 +415,12 @@ __global__ void k_lc_pack(const float* delta, const float* gx, const float* gy, 
                                                  f2bf(gy[o] * s2) | (f2bf(gz[o] * s3) << 16), 0u, 0u);
 }
 
-__global__ void k_lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* x0) {
+// delta * s0 as compact BF16 (one value per voxel), the first-layer input saved before the
+// transform overwrites the density
+__global__ void k_lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* d0) {
     const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= (long)n * n * n) return;
-    reinterpret_cast<uint4*>(x0)[v] = make_uint4(f2bf(delta[mesh_off(v, n, row)] * s0), 0u, 0u, 0u);
-}
-
-__global__ void k_lc_pack_force(const float* gx, const float* gy, const float* gz, long row, int n, float s1,
-                                float s2, float s3, uint16_t* x0) {
-    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= (long)n * n * n) return;
-    const long o = mesh_off(v, n, row);
-    uint4* p = reinterpret_cast<uint4*>(x0) + v;
-    const uint32_t d = (*p).x & 0xffffu;
-    *p = make_uint4(d | (f2bf(gx[o] * s1) << 16), f2bf(gy[o] * s2) | (f2bf(gz[o] * s3) << 16), 0u, 0u);
+    d0[v] = (uint16_t)f2bf(delta[mesh_off(v, n, row)] * s0);
 }
 
 // dF[c] = (W3 A2[v] + b3) * out_scale, written to (or added into) three meshes of `row` floats per row.
@@ -651,13 +707,6 @@ hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t
     return hipGetLastError();
 }
 
-hipError_t lc_pack_force(const float* const g[3], long row, int n, const float s[3], uint16_t* x0, hipStream_t st) {
-    ProfScope ps(PROF_LC_MISC, st);
-    hipLaunchKernelGGL(k_lc_pack_force, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, g[0], g[1], g[2],
-                       row, n, s[0], s[1], s[2], x0);
-    return hipGetLastError();
-}
-
 template <int C>
 static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
                             int accumulate, bool keep_z, hipStream_t st) {
@@ -672,6 +721,24 @@ static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out
     hipLaunchKernelGGL(k_lc_out<C>, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, A.a2, P.w3, P.b3,
                        out_scale, n, row, out[0], out[1], out[2], accumulate);
     return hipGetLastError();
+}
+
+template <int C>
+static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row,
+                                   int n, const float in_scale[4], float out_scale, hipStream_t st) {
+    constexpr int NB = C / 16;
+    FieldSrc fs{d0, {g[0], g[1], g[2]}, row, {in_scale[1], in_scale[2], in_scale[3]}};
+    hipError_t e = run_conv<8, NB, EPI_A, true>(nullptr, P.wb1, P.b1, a1, nullptr, nullptr, n, st, fs);
+    if (e != hipSuccess) return e;
+    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale};
+    return run_conv<C, NB, EPI_OUT>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
+}
+
+hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row, int n,
+                             const float in_scale[4], float out_scale, hipStream_t st) {
+    if (P.C == 16) return forward_fields_c<16>(P, a1, d0, g, row, n, in_scale, out_scale, st);
+    if (P.C == 32) return forward_fields_c<32>(P, a1, d0, g, row, n, in_scale, out_scale, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
