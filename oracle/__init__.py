@@ -16,6 +16,7 @@ pm         cloud-in-cell assignment, the Poisson/gradient solve, CIC interpolati
 cola       the COLA kick-drift-kick integrator in the frame comoving with 2LPT.
 power      the matter power-spectrum estimator.
 learned    the coarse-mesh force-correction network: forward, backward, particle loss.
+fof        friends-of-friends groups, the halo catalogue and the binned Warren mass function.
 """
 
-from . import cosmology, noise, lpt, pm, cola, power, learned  # noqa: F401
+from . import cosmology, noise, lpt, pm, cola, power, learned, fof  # noqa: F401

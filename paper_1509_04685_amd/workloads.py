@@ -62,3 +62,36 @@ def random_displacements(n_part, scale, seed):
     """(3, n_part^3) displacements, Gaussian with the given rms per axis."""
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, scale, size=(3, n_part ** 3))
+
+
+def halo_positions(n, box, seed, n_halo, halo_frac=0.5, halo_radius=1.0, slope=-1.9, min_members=2):
+    """(3, n) float32 positions in [0, box) with a halo population: a fraction halo_frac of the
+    particles in n_halo spherical clumps whose member counts follow a power law dN/dm ~ m^slope
+    (as a halo mass function does below its knee) and whose Plummer-like profiles have scale
+    radius halo_radius * (m / mean m)^(1/3); the rest uniform.  Particle order is shuffled so that
+    members of one clump are not neighbours in index."""
+    rng = np.random.default_rng(seed)
+    n_in = int(halo_frac * n)
+    # power-law weights by inverse transform on [1, 1000], then scaled to n_in members in total
+    u = rng.uniform(size=n_halo)
+    e = slope + 1.0
+    w = (1.0 + u * (1000.0 ** e - 1.0)) ** (1.0 / e)
+    m = np.maximum(min_members, np.floor(w / w.sum() * n_in)).astype(np.int64)
+    while m.sum() > n_in and m.max() > min_members:
+        m[np.argmax(m)] -= m.sum() - n_in if m.max() - (m.sum() - n_in) >= min_members else 1
+    m = m[np.cumsum(m) <= n_in]
+    n_in = int(m.sum())
+    centres = rng.uniform(0.0, box, size=(3, len(m)))
+    scale = halo_radius * (m / m.mean()) ** (1.0 / 3.0)
+    owner = np.repeat(np.arange(len(m)), m)
+    x = rng.uniform(size=n_in) * 0.98 + 0.01
+    r = scale[owner] / np.sqrt(x ** (-2.0 / 3.0) - 1.0)  # Plummer enclosed-mass inverse
+    r = np.minimum(r, 6.0 * scale[owner])
+    v = rng.normal(size=(3, n_in))
+    v /= np.linalg.norm(v, axis=0)
+    pos = np.empty((3, n))
+    pos[:, :n_in] = centres[:, owner] + v * r
+    pos[:, n_in:] = rng.uniform(0.0, box, size=(3, n - n_in))
+    pos = np.mod(pos, box)[:, rng.permutation(n)].astype(np.float32)
+    pos[pos >= np.float32(box)] = 0.0
+    return pos
