@@ -269,6 +269,55 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
  * n_real * N_p^3 floats. */
 int cola_positions(const cola_problem* prob, const cola_particles* in, float* pos[3], void* stream);
 
+/* ---- friends-of-friends haloes (Sec. 2.1, Sec. 2.5) ---------------------------------------
+ *
+ * Haloes are friends-of-friends groups (Davis et al. 1985) at a linking length b, 0.2 of the mean
+ * inter-particle separation in the paper (Sec. 2.1; b = 0.2 * box / N_p).  Two particles are
+ * friends when their periodic distance is below b; groups are the connected components of that
+ * graph.  The test is taken in float32, each operation rounded on its own:
+ *   d = x_j - x_i, then d -= box if d > box/2, d += box if d < -box/2 (each axis);
+ *   d2 = (dx*dx + dy*dy) + dz*dz;  friends iff d2 < float32(b) * float32(b).
+ * Groups of at least n_min particles (100 in Sec. 2.5) are haloes with the Warren et al. mass
+ * M = m_p N (1 - N^-0.6) (Sec. 2.5). */
+
+/* Workspace for cola_fof and cola_fof_catalogue with n particles in a box of side box at linking
+ * length link (0 for invalid arguments).  About 24 n bytes plus 12 bytes per cell of a grid of at
+ * most n cells. */
+size_t cola_fof_workspace_bytes(int64_t n, double box, double link);
+
+/* Groups of n particles.  pos[d]: device arrays of n floats (absolute positions, any real; cells
+ * are taken modulo the box), 1 <= n < 2^31, 0 < link < box / 2.  group: device n int32, out:
+ * group[i] = the smallest particle index in i's group (so group[i] <= i, and group[i] == i marks
+ * a group's label).  group_size: device n int32, out: at a label r the number of members of its
+ * group, 0 at every other index.  The result is deterministic.  Errors: COLA_ERR_INVALID_ARG,
+ * COLA_ERR_WORKSPACE_TOO_SMALL, COLA_ERR_HIP. */
+int cola_fof(const float* pos[3], int64_t n, double box, double link, int32_t* group, int32_t* group_size,
+             void* ws, size_t ws_bytes, void* stream);
+
+/* Halo catalogue of the groups of cola_fof with at least n_min members, ordered by label:
+ * halo_root[h] (label), halo_n[h] (members), halo_mass[h] (Warren mass with particle mass
+ * particle_mass), halo_com[d][h] (centre of mass: the label particle's position plus the mean of
+ * the members' float32 minimum-image offsets from it, accumulated in float64, wrapped into
+ * [0, box)).  All outputs are device arrays of max_halos entries; max_halos must be at least
+ * n / n_min (the most haloes there can be).  n_halos: device int64, out: the number of haloes.
+ * ws: as for cola_fof (its contents from cola_fof are not used). */
+int cola_fof_catalogue(const float* pos[3], int64_t n, double box, const int32_t* group,
+                       const int32_t* group_size, int32_t n_min, double particle_mass, int64_t max_halos,
+                       int32_t* halo_root, int32_t* halo_n, double* halo_mass, double* halo_com[3],
+                       int64_t* n_halos, void* ws, size_t ws_bytes, void* stream);
+
+/* Binned halo mass function: counts[b] (device, n_bins uint64, overwritten) = the number of
+ * groups with N >= n_min members whose Warren mass lies in [10^e_b, 10^e_{b+1}), e = the host
+ * array log10_mass_edges of n_bins + 1 strictly increasing values, 1 <= n_bins <= 64.  The mass
+ * increases with N, so the host turns each edge into the smallest N whose float64 Warren mass
+ * reaches it and the device bins the integer sizes.  dn/dlog10 M = counts / (box^3 * width). */
+int cola_fof_mass_histogram(const int32_t* group_size, int64_t n, int32_t n_min, double particle_mass,
+                            const double* log10_mass_edges, int32_t n_bins, uint64_t* counts, void* stream);
+
+/* Particle mass m_p = Omega_m rho_crit (box / n_part)^3 in h^-1 M_sun, rho_crit = 2.775e11
+ * h^2 M_sun Mpc^-3 (0 for invalid arguments). */
+double cola_particle_mass(const cola_cosmology* cosmo, double box, int32_t n_part);
+
 /* ---- component entry points (the stages above, exposed for parity checks) ------------- */
 
 /* CIC density contrast of arbitrary positions: pos[d] device arrays of n floats (absolute

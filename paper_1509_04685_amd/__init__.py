@@ -477,3 +477,68 @@ def mfma_selftest(a_bits, b_bits):
     _lib.check(_lib.lib().cola_mfma_selftest(_ptr(a_bits), _ptr(b_bits), _ptr(d), _stream()),
                "cola_mfma_selftest")
     return d
+
+
+# ---------------------------------------------------------------- friends-of-friends haloes
+
+def linking_length(box, n_part, b=0.2):
+    """b times the mean inter-particle separation box / N_p (Sec. 2.1)."""
+    return b * float(box) / int(n_part)
+
+
+def particle_mass(cosmo, box, n_part):
+    return float(_lib.lib().cola_particle_mass(ctypes.byref(cosmo), float(box), int(n_part)))
+
+
+def fof_workspace(n, box, link, device="cuda"):
+    torch = _torch()
+    nb = int(_lib.lib().cola_fof_workspace_bytes(int(n), float(box), float(link)))
+    if nb == 0:
+        raise ColaError(-1, "cola_fof_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def fof(pos, box, link, ws=None):
+    """Friends-of-friends groups of positions pos (3, n) float32: (group, group_size) int32 (n,)
+    device tensors; group[i] = smallest index in i's group, group_size[r] = members at a label r."""
+    torch = _torch()
+    _require_cuda_f32(pos, "pos")
+    n = int(pos.shape[1])
+    if ws is None:
+        ws = fof_workspace(n, box, link, pos.device)
+    group = torch.empty(n, dtype=torch.int32, device=pos.device)
+    size = torch.empty(n, dtype=torch.int32, device=pos.device)
+    _lib.check(_lib.lib().cola_fof(_ptrs3(pos), n, float(box), float(link), _ptr(group), _ptr(size), _ptr(ws),
+                                   ws.numel(), _stream()), "cola_fof")
+    return group, size
+
+
+def fof_catalogue(pos, box, group, size, n_min, m_p, ws):
+    """Haloes with at least n_min members, by label: dict of device tensors root, n (int32), mass
+    and com (3, n_halo) (float64)."""
+    torch = _torch()
+    _require_cuda_f32(pos, "pos")
+    n = int(pos.shape[1])
+    cap = max(1, n // int(n_min))
+    dev = pos.device
+    root = torch.empty(cap, dtype=torch.int32, device=dev)
+    cnt = torch.empty(cap, dtype=torch.int32, device=dev)
+    mass = torch.empty(cap, dtype=torch.float64, device=dev)
+    com = torch.empty((3, cap), dtype=torch.float64, device=dev)
+    nh = torch.empty(1, dtype=torch.int64, device=dev)
+    _lib.check(_lib.lib().cola_fof_catalogue(_ptrs3(pos), n, float(box), _ptr(group), _ptr(size), int(n_min),
+                                             float(m_p), cap, _ptr(root), _ptr(cnt), _ptr(mass), _ptrs3(com),
+                                             _ptr(nh), _ptr(ws), ws.numel(), _stream()), "cola_fof_catalogue")
+    k = int(nh.item())
+    return dict(root=root[:k], n=cnt[:k], mass=mass[:k], com=com[:, :k])
+
+
+def fof_mass_histogram(size, n_min, m_p, log10_edges):
+    """Groups with N >= n_min per Warren-mass bin [10^e_b, 10^e_{b+1}): int64 device tensor."""
+    torch = _torch()
+    e = [float(v) for v in log10_edges]
+    counts = torch.empty(len(e) - 1, dtype=torch.int64, device=size.device)
+    arr = (ctypes.c_double * len(e))(*e)
+    _lib.check(_lib.lib().cola_fof_mass_histogram(_ptr(size), int(size.numel()), int(n_min), float(m_p), arr,
+                                                  len(e) - 1, _ptr(counts), _stream()), "cola_fof_mass_histogram")
+    return counts

@@ -26,7 +26,8 @@ EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_lc_param_count", "cola_lc_packed_bytes", "cola_lc_workspace_bytes", "cola_lc_pack",
            "cola_lc_forward", "cola_lc_backward", "cola_lc_loss", "cola_lc_adam", "cola_step_lc",
            "cola_pm_fields_workspace_bytes", "cola_pm_fields", "cola_positions", "cola_mfma_selftest",
-           "cola_profiler_read_groups")
+           "cola_profiler_read_groups", "cola_fof_workspace_bytes", "cola_fof", "cola_fof_catalogue",
+           "cola_fof_mass_histogram", "cola_particle_mass")
 
 
 class ColaError(RuntimeError):
@@ -126,6 +127,12 @@ def _load():
         "cola_mfma_selftest": (ctypes.c_int, [vp, vp, vp, vp]),
         "cola_profiler_read_groups": (ctypes.c_int, [i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
                                                      ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "cola_fof_workspace_bytes": (sz, [i64, dbl, dbl]),
+        "cola_fof": (ctypes.c_int, [ctypes.POINTER(vp), i64, dbl, dbl, vp, vp, vp, sz, vp]),
+        "cola_fof_catalogue": (ctypes.c_int, [ctypes.POINTER(vp), i64, dbl, vp, vp, i32, dbl, i64, vp, vp, vp,
+                                              ctypes.POINTER(vp), vp, vp, sz, vp]),
+        "cola_fof_mass_histogram": (ctypes.c_int, [vp, i64, i32, dbl, ctypes.POINTER(dbl), i32, vp, vp]),
+        "cola_particle_mass": (dbl, [C, dbl, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

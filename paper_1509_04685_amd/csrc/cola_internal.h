@@ -22,6 +22,7 @@ enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
     PROF_Y_INV, PROF_Z_C2R, PROF_GKD, PROF_GATHER, PROF_IC, PROF_X_INV_MULT, PROF_PK, PROF_COPY,
     PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_LC_CONV, PROF_LC_WGRAD, PROF_LC_MISC,
+    PROF_FOF,
     PROF_NUM_KINDS
 };
 // Brackets one kernel launch with an event pair when the profiler is enabled.  tag: a size label
@@ -161,6 +162,11 @@ hipError_t gather_kick_drift(const ParticlePtrs& P, long n_per_real, int n_real,
 hipError_t gather_force(const ParticlePtrs& P, long n_per_real, int n_real, const LatticeGeom& fgeom,
                         const float* fx, const float* fy, const float* fz, float* const acc[3],
                         hipStream_t st);
+
+// Exclusive scan of nkeys counts: start[k] = sum of count[0..k), start[nkeys] = total (the sum,
+// known to the caller), cursor = start.  block_sums holds ceil(nkeys / 1024) entries.
+hipError_t scan_counts(const uint32_t* count, uint32_t* start, uint32_t* cursor, uint32_t* block_sums, long nkeys,
+                       uint32_t total, hipStream_t st);
 
 // ------------------------------------------------------------------ tiled deposit (deposit_sorted.hip)
 struct TileGeom {

@@ -357,6 +357,17 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
 
 }  // namespace
 
+hipError_t scan_counts(const uint32_t* count, uint32_t* start, uint32_t* cursor, uint32_t* block_sums, long nkeys,
+                       uint32_t total, hipStream_t st) {
+    const int nblocks = (int)((nkeys + 1023) / 1024);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks, 1), dim3(256), 0, st, count, start, block_sums, nkeys, 0L,
+                       nblocks);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1, 1), dim3(1024), 0, st, block_sums, nblocks);
+    hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)((nkeys + 1 + 255) / 256), 1), dim3(256), 0, st, start, cursor,
+                       block_sums, nkeys, 0L, nblocks, total);
+    return hipGetLastError();
+}
+
 size_t sort_bytes(long n_particles_per_real, const TileGeom& tg, int n_real) {
     size_t nkp = (size_t)tg.nkeys + 1;
     size_t nblocks = (size_t)((tg.nkeys + 1023) / 1024);

@@ -72,6 +72,10 @@ def halo_positions(n, box, seed, n_halo, halo_frac=0.5, halo_radius=1.0, slope=-
     members of one clump are not neighbours in index."""
     rng = np.random.default_rng(seed)
     n_in = int(halo_frac * n)
+    if n_halo < 1 or n_in < min_members:
+        pos = rng.uniform(0.0, box, size=(3, n)).astype(np.float32)
+        pos[pos >= np.float32(box)] = 0.0
+        return pos
     # power-law weights by inverse transform on [1, 1000], then scaled to n_in members in total
     u = rng.uniform(size=n_halo)
     e = slope + 1.0
@@ -92,6 +96,6 @@ def halo_positions(n, box, seed, n_halo, halo_frac=0.5, halo_radius=1.0, slope=-
     pos = np.empty((3, n))
     pos[:, :n_in] = centres[:, owner] + v * r
     pos[:, n_in:] = rng.uniform(0.0, box, size=(3, n - n_in))
-    pos = np.mod(pos, box)[:, rng.permutation(n)].astype(np.float32)
+    pos = np.ascontiguousarray(np.mod(pos, box)[:, rng.permutation(n)], dtype=np.float32)
     pos[pos >= np.float32(box)] = 0.0
     return pos
