@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-seed ensemble measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
+    ap.add_argument("--no-haloes", action="store_true", help="skip the friends-of-friends halo measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
     ap.add_argument("--profile-step", action="store_true",
                     help="for hardware counters: autotune, ICs, one COLA step, one 1 GiB copy; no timing")
@@ -215,7 +216,42 @@ def ensemble_bench(cola, torch, reps):
     return out
 
 
-def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps):
+HALO_N_MIN = 101  # haloes of more than 100 particles (Sec. 2.5)
+
+
+def haloes(cola, torch, prob, st, cosmo, box, n_part):
+    """Friends-of-friends (b = 0.2) on the state's positions and the Warren mass histogram of the
+    haloes with more than 100 particles, in 0.2 dex bins from the 101-particle mass."""
+    import numpy as np
+    pos = cola.positions(prob, st)
+    link = cola.linking_length(box, n_part)
+    m_p = cola.particle_mass(cola.make_cosmology(**W.COSMOLOGY), box, n_part)
+    e0 = np.log10(m_p * HALO_N_MIN * (1.0 - HALO_N_MIN ** -0.6))
+    edges = e0 + 0.2 * np.arange(11)
+    fws = cola.fof_workspace(pos.shape[1], box, link)
+    cola.fof(pos, box, link, ws=fws)  # warm
+    stream = torch.cuda.current_stream()
+    e0v, e1v = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0v.record(stream)
+    g, s = cola.fof(pos, box, link, ws=fws)
+    e1v.record(stream)
+    counts = cola.fof_mass_histogram(s, HALO_N_MIN, m_p, edges).cpu().numpy()
+    ms = e0v.elapsed_time(e1v)
+    largest = int(s.max().item())
+    del pos, g, s, fws
+    return {"counts": counts, "log10_edges": edges, "fof_ms": ms, "largest": largest, "particle_mass": m_p}
+
+
+def abundance_error(counts, ref, min_count=20):
+    """Largest |N / N_ref - 1| over mass bins where the reference has at least min_count haloes,
+    and the ratio of the totals."""
+    import numpy as np
+    ok = ref >= min_count
+    per_bin = np.abs(counts[ok] / ref[ok] - 1.0)
+    return (float(per_bin.max()) if per_bin.size else float("nan"), float(counts.sum() / max(1, ref.sum())))
+
+
+def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps, halo3=None):
     """The learned-correction form: 256^3 particles on the 256^3 (PM_grid = 1) mesh with the trained
     network, against the plain 3x realization timed above (same seed, same outputs) and the plain
     1x run without the network."""
@@ -276,7 +312,18 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
         pk = outs[-1][1].cpu().numpy()[0]
         res[name] = {"ms_per_realization": round(ms, 2), "realizations_per_hour": round(3.6e6 / ms, 1),
                      "max_pk_error_k_lt_1": round(L.max_error(k, pk, pk_plain3), 4)}
+        if halo3 is not None:  # the state now holds this form's z = 0 particles
+            h = haloes(cola, torch, prob, st, cosmo, c["box"], c["n_part"])
+            worst, total = abundance_error(h["counts"], halo3["counts"])
+            res[name]["haloes_gt_100"] = int(h["counts"].sum())
+            res[name]["halo_counts"] = [int(v) for v in h["counts"]]
+            res[name]["max_halo_abundance_error"] = round(worst, 4)
+            res[name]["halo_total_ratio"] = round(total, 4)
     res["plain_3x"] = {"ms_per_realization": round(ms_plain3, 2), "realizations_per_hour": round(3.6e6 / ms_plain3, 1)}
+    if halo3 is not None:
+        res["plain_3x"]["haloes_gt_100"] = int(halo3["counts"].sum())
+        res["plain_3x"]["halo_counts"] = [int(v) for v in halo3["counts"]]
+        res["halo_bins_log10_mass"] = [round(float(v), 3) for v in halo3["log10_edges"]]
     res["speedup_vs_plain_3x"] = round(ms_plain3 / res["learned_1x"]["ms_per_realization"], 3)
     res["network"] = (f"C={net.channels}: two 3x3x3 conv layers + SiLU, 1x1x1 output; BF16 matrix cores, "
                       f"FP32 accumulation; trained on 128^3/384^3 pairs in 384 h^-1 Mpc (seeds 3001-3006), "
@@ -286,7 +333,9 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
                       f"{net.out_scale_slope:+.2f} in (1 - a); evaluation seed {c['seeds'][0]} held out")
     res["workload"] = (f"{lname}: {c['n_part']}^3 particles, {c['n_part']}^3 mesh (PM_grid 1), box {c['box']:g}, "
                        f"40 nodes from z=19, seed {c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = "
-                       f"max over 0<k<1 h/Mpc of |P/P_plain3x - 1| at z=0")
+                       f"max over 0<k<1 h/Mpc of |P/P_plain3x - 1| at z=0; haloes: FoF b=0.2 at z=0, "
+                       f"Warren masses, > 100 particles, 0.2 dex bins; halo error = max over bins with >= 20 "
+                       f"plain-3x haloes of |N/N_plain3x - 1|")
     return res
 
 
@@ -425,10 +474,21 @@ def main():
     }
     if roofline is not None:
         roofline["copy_ceiling_gbs"] = copy_ceiling(cola, torch)
+    halo3 = None
+    if not args.no_haloes:
+        # the state holds the last timed realization at z = 0
+        halo3 = haloes(cola, torch, prob, st, cosmo, box, n_part)
+        result["haloes"] = {"fof_ms": round(halo3["fof_ms"], 3),
+                            "fof_particles_per_s": round(particles / (halo3["fof_ms"] / 1e3), 1),
+                            "haloes_gt_100": int(halo3["counts"].sum()), "largest_halo": halo3["largest"],
+                            "particle_mass": halo3["particle_mass"],
+                            "what": "friends-of-friends (b = 0.2 of the mean separation) of the z = 0 particles, "
+                                    "Warren-mass histogram of haloes with more than 100 particles"}
+        print(f"[bench] haloes: {json.dumps(result['haloes'])}", file=sys.stderr, flush=True)
     if not args.no_learned:
         print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
         result["learned"] = learned_bench(cola, torch, args.workload, outs[-1][1].cpu().numpy()[0], a_outs, n_pk,
-                                          n_bins, ms_per_step, reps=2)
+                                          n_bins, ms_per_step, reps=2, halo3=halo3)
         print(f"[bench] learned: {json.dumps(result['learned'])}", file=sys.stderr, flush=True)
     if not args.no_ensemble:
         del st, ws, outs

@@ -277,7 +277,8 @@ int cola_positions(const cola_problem* prob, const cola_particles* in, float* po
  * graph.  The test is taken in float32, each operation rounded on its own:
  *   d = x_j - x_i, then d -= box if d > box/2, d += box if d < -box/2 (each axis);
  *   d2 = (dx*dx + dy*dy) + dz*dz;  friends iff d2 < float32(b) * float32(b).
- * Groups of at least n_min particles (100 in Sec. 2.5) are haloes with the Warren et al. mass
+ * Groups of at least n_min particles (more than 100 in Sec. 2.5: n_min = 101) are haloes with the
+ * Warren et al. mass
  * M = m_p N (1 - N^-0.6) (Sec. 2.5). */
 
 /* Workspace for cola_fof and cola_fof_catalogue with n particles in a box of side box at linking

@@ -4,7 +4,7 @@ Test infrastructure only (see the package docstring).
 
 Sec. 2.1 identifies haloes with the friends-of-friends algorithm of Davis et al. (1985) at a
 linking length of 0.2 (read here, as is usual, in units of the mean inter-particle separation
-L / N_p).  Sec. 2.5 keeps haloes of at least 100 particles and gives them the Warren et al. mass
+L / N_p).  Sec. 2.5 keeps haloes of more than 100 particles and gives them the Warren et al. mass
 M = m_p N (1 - N^-0.6).
 
 Definition followed here.  Two particles are friends when their periodic distance is below the
