@@ -325,10 +325,13 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
         res["plain_3x"]["halo_counts"] = [int(v) for v in halo3["counts"]]
         res["halo_bins_log10_mass"] = [round(float(v), 3) for v in halo3["log10_edges"]]
     res["speedup_vs_plain_3x"] = round(ms_plain3 / res["learned_1x"]["ms_per_realization"], 3)
-    res["network"] = (f"C={net.channels}: two 3x3x3 conv layers + SiLU, 1x1x1 output; BF16 matrix cores, "
-                      f"FP32 accumulation; trained on 128^3/384^3 pairs in 384 h^-1 Mpc (seeds 3001-3006), "
+    rec = doc.get("recipe", {})
+    seeds = rec.get("calib_seeds", (3001, 3002))
+    inputs = "density and force" if rec.get("force_input", True) else "density only"
+    res["network"] = (f"C={net.channels}: two 3x3x3 conv layers + SiLU, 1x1x1 output, input {inputs}; BF16 matrix "
+                      f"cores, FP32 accumulation; trained on 128^3/384^3 pairs in 384 h^-1 Mpc (seeds 3001-3006), "
                       f"validation loss {doc['val_loss_initial']:.3f} -> {doc['val_loss_trained']:.3f}; output "
-                      f"scale calibrated on training seeds 3001-3002: factor "
+                      f"scale calibrated on training seeds {seeds[0]}-{seeds[-1]}: factor "
                       f"{net.out_scale / doc.get('out_scale_fitted', net.out_scale):.2f}, slope "
                       f"{net.out_scale_slope:+.2f} in (1 - a); evaluation seed {c['seeds'][0]} held out")
     res["workload"] = (f"{lname}: {c['n_part']}^3 particles, {c['n_part']}^3 mesh (PM_grid 1), box {c['box']:g}, "

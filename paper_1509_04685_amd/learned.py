@@ -37,18 +37,24 @@ class Sample:
         self.acc = f["acc"]
 
 
-def make_samples(cosmo, box, n_part, pm_fine, n_steps, z_init, seeds, nodes=None):
-    """Plain fine-mesh runs for each seed; a Sample (coarse mesh = N_p cells) at each node in
-    `nodes` (default: all)."""
-    prob = make_problem(box, n_part, pm_fine, z_init, n_steps)
+def make_samples(cosmo, box, n_part, pm_fine, n_steps, z_init, seeds, nodes=None, net=None):
+    """A Sample (coarse mesh = N_p cells) at each node in `nodes` (default: all) of one run per
+    seed.  The runs are plain fine-mesh runs, or with `net` the corrected coarse runs (PM_grid 1
+    with the network): the positions are then the ones the corrected form visits, and the targets
+    stay the fine-mesh accelerations at those positions."""
+    prob = make_problem(box, n_part, 1 if net is not None else pm_fine, z_init, n_steps)
     st = ParticleState(prob)
     ws = Workspace(prob)
+    lws = lc_workspace(n_part, net.channels, 1) if net is not None else None
     out = []
     for seed in seeds:
         ic_2lpt(prob, cosmo, [int(seed)], st, ws)
         for j in range(n_steps):
             if j > st.node:
-                step(prob, cosmo, st, j, ws)
+                if net is None:
+                    step(prob, cosmo, st, j, ws)
+                else:
+                    step_lc(prob, cosmo, st, j, net, lws, ws)
             if nodes is None or j in nodes:
                 pos = positions(prob, st)
                 acc_fine = pm_fields(pos, n_part * pm_fine, box, delta=False, g=False)["acc"]
@@ -107,9 +113,15 @@ class Trainer:
         return float(np.mean(vals))
 
 
-def new_net(sample, channels=16, seed=0):
+def new_net(sample, channels=16, seed=0, force_input=True):
+    """A network with initial weights and scales from `sample`.  force_input=False zeroes the input
+    scales of the three force channels: the network then sees only the density, so its response to
+    a long-wavelength mode is a local stencil of the density (of order k^2 g at small k) and
+    cannot rescale the large-scale force itself."""
     from . import lc_init_params
     ins, outs = scales_from(sample)
+    if not force_input:
+        ins = (ins[0], 0.0, 0.0, 0.0)
     return LcNet(channels, params=lc_init_params(channels, seed), in_scale=ins, out_scale=outs)
 
 

@@ -4,9 +4,15 @@
 
 Training pairs: plain PM_grid = 3 runs of 128^3 particles in a 384 h^-1 Mpc box (the resolution,
 3 h^-1 Mpc per coarse cell, of the 256^3 / 768 h^-1 Mpc learned workload), 40 nodes from z = 19,
-seeds 3001-3006 for training and 3007 for validation, every other node.  After the force-level
-fit, the output scale is calibrated at trajectory level on training seeds 3001-3002 (the factor
-that minimises the worst max |P / P_3x - 1| for k < 1 at z = 0).  The weights file holds the flat
+seeds 3001-3006 for training and 3007 for validation, every other node.  The network sees the
+density only (the force channels' input scales are zero): its response to a long-wavelength mode
+is then a local stencil of the density, of order k^2 g, so it cannot rescale the large-scale force
+and bias the growth of large scales (with the force as input it did, by 1-2 % in P(k) at
+k ~ 0.2-0.3 h/Mpc).  After the force-level fit, the output scale is calibrated at trajectory level
+on training seeds 3001-3004 (the factor and slope that minimise the worst max |P / P_3x - 1| for
+k < 1 at z = 0).  Optional on-policy rounds (--onpolicy-rounds): the calibrated network runs the
+coarse form on the training seeds, the positions it visits get fine-mesh targets, the network is
+fine-tuned on the old and new samples together and calibrated again.  The weights file holds the flat
 FP32 parameters in the library's order, the input and output scales (fitted and calibrated), the
 validation loss before and after training, the calibration table and the recipe.
 """
@@ -23,9 +29,12 @@ sys.path.insert(0, os.path.dirname(HERE))
 RECIPE = dict(box=384.0, n_part=128, pm_fine=3, n_steps=40, z_init=19.0,
               train_seeds=(3001, 3002, 3003, 3004, 3005, 3006), val_seeds=(3007,),
               train_nodes=tuple(range(4, 40, 2)), val_nodes=tuple(range(5, 40, 6)),
-              iters=1500, batch=2, lr=3e-3, lr_decay=0.3, chunks=5, init_seed=1,
-              calib_seeds=(3001, 3002), calib_factors=tuple(round(1.2 + 0.05 * i, 2) for i in range(11)),
-              calib_slopes=tuple(round(-0.6 + 0.2 * i, 1) for i in range(7)))
+              iters=3000, batch=2, lr=3e-3, lr_decay=0.3, chunks=5, init_seed=1, force_input=False,
+              calib_seeds=(3001, 3002, 3003, 3004), calib_factors=tuple(round(0.8 + 0.05 * i, 2) for i in range(19)),
+              calib_slopes=tuple(round(0.2 * i, 1) for i in range(9)),
+              onpolicy_rounds=0, onpolicy_iters=1500, onpolicy_lr=1e-3,
+              onpolicy_factors=tuple(round(0.9 + 0.05 * i, 2) for i in range(13)),
+              onpolicy_slopes=tuple(round(-0.2 + 0.2 * i, 1) for i in range(6)))
 
 
 def train(channels, recipe=RECIPE, log=print):
@@ -39,7 +48,7 @@ def train(channels, recipe=RECIPE, log=print):
     val = L.make_samples(cosmo, r["box"], r["n_part"], r["pm_fine"], r["n_steps"], r["z_init"],
                          r["val_seeds"], nodes=set(r["val_nodes"]))
     log(f"[train_lc] {len(samples)} training and {len(val)} validation samples ({time.time() - t0:.1f} s)")
-    net = L.new_net(samples[-1], channels=channels, seed=r["init_seed"])
+    net = L.new_net(samples[-1], channels=channels, seed=r["init_seed"], force_input=r["force_input"])
     tr = L.Trainer(net, r["n_part"], r["box"])
     v0 = tr.evaluate(val)
     per = r["iters"] // r["chunks"]
@@ -47,13 +56,30 @@ def train(channels, recipe=RECIPE, log=print):
         h = tr.train(samples, per, r["lr"] * r["lr_decay"] ** c, batch=r["batch"], seed=c)
         log(f"[train_lc] chunk {c}: mean training loss {h.mean():.4f}, validation {tr.evaluate(val):.4f} "
             f"({time.time() - t0:.1f} s)")
-    v1 = tr.evaluate(val)
-    del samples, val
     fitted = net.out_scale
+    v1 = tr.evaluate(val)
     best, slope, table = L.calibrate_out_scale(net, cosmo, r["box"], r["n_part"], r["z_init"], r["n_steps"],
                                                r["calib_seeds"], r["calib_factors"], r["calib_slopes"], log=log)
     log(f"[train_lc] output scale {fitted:.5g} -> {best:.5g} (factor {best / fitted:.3f}), slope {slope:+.2f}; "
         f"worst training-seed error {min(t[2] for t in table):.4f}")
+    for rd in range(r["onpolicy_rounds"]):
+        onp = L.make_samples(cosmo, r["box"], r["n_part"], r["pm_fine"], r["n_steps"], r["z_init"],
+                             r["train_seeds"], nodes=set(r["train_nodes"]), net=net)
+        net.set_scales(net.in_scale, fitted, 0.0)  # fine-tune at the fitted scale, calibrate again after
+        data = samples + onp
+        per = r["onpolicy_iters"] // 3
+        for c in range(3):
+            h = tr.train(data, per, r["onpolicy_lr"] * 0.3 ** c, batch=r["batch"], seed=1000 * (rd + 1) + c)
+            log(f"[train_lc] on-policy round {rd} chunk {c}: mean training loss {h.mean():.4f}, validation "
+                f"{tr.evaluate(val):.4f} ({time.time() - t0:.1f} s)")
+        v1 = tr.evaluate(val)
+        del onp, data
+        best, slope, table = L.calibrate_out_scale(net, cosmo, r["box"], r["n_part"], r["z_init"], r["n_steps"],
+                                                   r["calib_seeds"], r["onpolicy_factors"], r["onpolicy_slopes"],
+                                                   log=log)
+        log(f"[train_lc] on-policy round {rd}: factor {best / fitted:.3f}, slope {slope:+.2f}; worst training-seed "
+            f"error {min(t[2] for t in table):.4f}")
+    del samples, val
     return net, v0, v1, fitted, table
 
 
@@ -62,9 +88,12 @@ def main():
     ap.add_argument("--channels", type=int, default=16)
     ap.add_argument("--out", default=None)
     ap.add_argument("--iters", type=int, default=RECIPE["iters"])
+    ap.add_argument("--onpolicy-rounds", type=int, default=RECIPE["onpolicy_rounds"])
+    ap.add_argument("--force-input", action="store_true", help="the network also sees the three force components")
     args = ap.parse_args()
     out = args.out or os.path.join(HERE, f"lc_weights_c{args.channels}.json")
-    recipe = dict(RECIPE, iters=args.iters)
+    recipe = dict(RECIPE, iters=args.iters, onpolicy_rounds=args.onpolicy_rounds,
+                  force_input=args.force_input)
     net, v0, v1, fitted, table = train(args.channels, recipe=recipe, log=lambda m: print(m, flush=True))
     doc = dict(channels=net.channels, in_scale=list(net.in_scale), out_scale=net.out_scale,
                out_scale_slope=net.out_scale_slope, out_scale_fitted=fitted, calibration=table,
