@@ -69,15 +69,22 @@ typedef struct {
     double  a_final;    /* last node, normally 1                                              */
     int32_t n_steps;    /* number of time nodes n of Eq. 3, both ends included (n >= 2);
                            one force evaluation per node, n - 1 drifts                        */
-    int32_t sampling;   /* time sampling f(a) of Eq. 3: 0 = linear in a (only value accepted) */
+    int32_t sampling;   /* time sampling f(a) of Eq. 3, nodes equally spaced in f (Sec. 4.3):
+                           0 = linear, f = a (the paper's choice); 1 = logarithmic, f = ln a;
+                           2 = power, f = a^sampling_power                                    */
     int32_t n_real;     /* realizations in the batch, >= 1                                    */
+    int32_t frame;      /* 0 = COLA: integrate the residual from the 2LPT path (Eq. 1-2);
+                           1 = PM only: the plain kick-drift-kick leapfrog with the LPT frame
+                           switched off (the comparison of Appendix B)                        */
+    double  sampling_power;  /* p of f = a^p for sampling = 2 (finite, > 0); ignored otherwise */
 } cola_problem;
 
 /* Particle state of a batch.  Each pointer: n_real * N_p^3 floats on the device.
  *   x     displacement from the Lagrangian position q (not the absolute position), where
  *         q = idx_d * L / N_p + H / 2 per axis, H = L / N_g: the lattice sits at force-mesh
  *         cell centres (on a node the CIC weights have a kink).
- *   p     residual momentum p_res = p - a^2 (dD1/dt Psi1 + dD2/dt Psi2) (Eq. 1-2 frame).
+ *   p     residual momentum p_res = p - a^2 (dD1/dt Psi1 + dD2/dt Psi2) (Eq. 1-2 frame);
+ *         with frame = 1 (PM only) the full momentum p = a^2 dx/dt.
  *   psi1  first-order Lagrangian displacement at D1 = 1; psi2 second order (D2 < 0 convention).
  * node        index of the time node the state sits at (0 after cola_ic_2lpt).
  * force_node  node whose force mesh the workspace `force_ws` holds, or -1.  Set by the
@@ -103,7 +110,8 @@ size_t cola_workspace_bytes(const cola_problem* prob, int32_t n_pk);
  * sqrt(P(k) N_p^3 / L^3), k = 0 removed; Psi1 = IFFT[i k delta / k^2]; Psi2 =
  * IFFT[-i k S_k / k^2] with S = sum_{i>j}(phi_ii phi_jj - phi_ij^2), phi_ij = IFFT[k_i k_j delta/k^2];
  * a factor odd in k_d is zeroed on the Nyquist plane of axis d.  On return x = D1(a_0) Psi1 +
- * D2(a_0) Psi2, p = 0, node = 0, force_node = -1.
+ * D2(a_0) Psi2, p = 0 (frame 0) or the 2LPT momentum a^2 (dD1/dt Psi1 + dD2/dt Psi2) at a_0
+ * (frame 1), node = 0, force_node = -1.
  * seeds: host array of n_real seeds.  ws: cola_workspace_bytes(prob, 0) bytes at least. */
 int cola_ic_2lpt(const cola_problem* prob, const cola_cosmology* cosmo, const uint64_t* seeds,
                  cola_particles* out, void* ws, size_t ws_bytes, void* stream);

@@ -43,9 +43,17 @@ def make_cosmology(omega_m=0.25, omega_b=0.044, h=0.7, n_s=0.95, sigma_8=0.8):
     return Cosmology(omega_m, omega_b, h, n_s, sigma_8)
 
 
-def make_problem(box, n_part, pm_factor, z_init, n_steps, a_final=1.0, n_real=1):
+SAMPLINGS = {"linear": 0, "log": 1, "power": 2}
+FRAMES = {"cola": 0, "pm": 1}
+
+
+def make_problem(box, n_part, pm_factor, z_init, n_steps, a_final=1.0, n_real=1, sampling="linear",
+                 sampling_power=1.0, frame="cola"):
+    """Run parameters (Table 1).  sampling: "linear" (f = a), "log" (f = ln a) or "power"
+    (f = a^sampling_power) node spacing of Eq. 3; frame: "cola" (2LPT frame, Eq. 1-2) or "pm"
+    (plain leapfrog, the LPT frame switched off)."""
     return Problem(float(box), int(n_part), int(pm_factor), float(z_init), float(a_final),
-                   int(n_steps), 0, int(n_real))
+                   int(n_steps), SAMPLINGS[sampling], int(n_real), FRAMES[frame], float(sampling_power))
 
 
 def workspace_bytes(prob, n_pk=0):

@@ -48,7 +48,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double), ("n_part", ctypes.c_int32), ("pm_factor", ctypes.c_int32),
                 ("z_init", ctypes.c_double), ("a_final", ctypes.c_double),
                 ("n_steps", ctypes.c_int32), ("sampling", ctypes.c_int32),
-                ("n_real", ctypes.c_int32)]
+                ("n_real", ctypes.c_int32), ("frame", ctypes.c_int32), ("sampling_power", ctypes.c_double)]
 
 
 _F3 = ctypes.c_void_p * 3

@@ -81,7 +81,10 @@ int check_problem(const cola_problem* p) {
     if (!p) return COLA_ERR_INVALID_ARG;
     if (!(p->box > 0.0) || !std::isfinite(p->box)) return COLA_ERR_INVALID_ARG;
     if (p->n_part < 2 || p->pm_factor < 1 || p->n_real < 1) return COLA_ERR_INVALID_ARG;
-    if (p->n_steps < 2 || p->sampling != 0) return COLA_ERR_INVALID_ARG;
+    if (p->n_steps < 2 || p->sampling < 0 || p->sampling > 2) return COLA_ERR_INVALID_ARG;
+    if (p->sampling == 2 && (!std::isfinite(p->sampling_power) || !(p->sampling_power > 0.0)))
+        return COLA_ERR_INVALID_ARG;
+    if (p->frame != 0 && p->frame != 1) return COLA_ERR_INVALID_ARG;
     if (!(p->z_init > -1.0) || !std::isfinite(p->z_init)) return COLA_ERR_INVALID_ARG;
     double a0 = 1.0 / (1.0 + p->z_init);
     if (!(p->a_final > a0) || !std::isfinite(p->a_final)) return COLA_ERR_INVALID_ARG;
@@ -199,6 +202,18 @@ ForceMeshes force_meshes(const Ws& w) {
             reinterpret_cast<const float*>(w.S)};
 }
 
+// With the LPT frame switched off (PM only) the kick uses g alone and the drift p alone: the
+// 2LPT terms of the bracket and of the drift are zero.
+KickDrift frame_terms(KickDrift kd, const cola_problem& p) {
+    if (p.frame == 1) {
+        kd.d1 = 0.0f;
+        kd.d2m = 0.0f;
+        kd.dd1 = 0.0f;
+        kd.dd2 = 0.0f;
+    }
+    return kd;
+}
+
 int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
               cola_particles* io, void* ws, size_t ws_bytes, void* stream, const LcHook* lc) {
     int s;
@@ -232,7 +247,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
         kd.drift = (float)sc.drift[j];
         kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
         kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
-        COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
+        COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, frame_terms(kd, p), st));
         COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j + 1]));
         pending = sc.k_in[j];
     }
@@ -240,7 +255,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     kd.kick = (float)(c32 * pending);
     kd.d1 = (float)sc.d1[j_end];
     kd.d2m = (float)(sc.d2[j_end] - sc.d1[j_end] * sc.d1[j_end]);
-    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, kd, st));
+    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, frame_terms(kd, p), st));
     io->node = j_end;
     io->force_node = j_end;
     io->force_ws = ws;
@@ -347,8 +362,12 @@ int cola_ic_2lpt(const cola_problem* prob, const cola_cosmology* cosmo, const ui
         COLA_TRY(fft3d_c2r_mult(w.S, L.cstride, w.A, L.cstride, out->psi1[d], np, npr, gp, w.twp, p.n_real,
                                 MUL_IK, d, d, kf, inv_n3, st));
     }
-    Growth g0 = growth(1.0 / (1.0 + p.z_init), cosmo->omega_m);
-    COLA_TRY(ic_set_state(P, ntot, (float)g0.d1, (float)g0.d2, st));
+    const double a0 = 1.0 / (1.0 + p.z_init);
+    Growth g0 = growth(a0, cosmo->omega_m);
+    // PM only: the full 2LPT momentum a^2 dD/dt = a^3 E(a) dD/da; COLA: zero residual
+    const double mom = p.frame == 1 ? a0 * a0 * a0 * hubble_e(a0, cosmo->omega_m) : 0.0;
+    COLA_TRY(ic_set_state(P, ntot, (float)g0.d1, (float)g0.d2, (float)(mom * g0.dd1_da), (float)(mom * g0.dd2_da),
+                          st));
     out->node = 0;
     out->force_node = -1;
     out->force_ws = nullptr;
@@ -443,6 +462,7 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
         kd.drift = (float)drift_integral(aj, a_out, sc.omega_m);
         kd.dd1 = (float)(go.d1 - sc.d1[j]);
         kd.dd2 = (float)(go.d2 - sc.d2[j]);
+        kd = frame_terms(kd, p);
     }
     const Mesh3& gk = L.gk;
     LatticeGeom dg;

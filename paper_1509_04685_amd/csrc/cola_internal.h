@@ -206,7 +206,8 @@ hipError_t ic_scale_spectrum(float2* spec, long bstride, const Mesh3& g, int n_r
 // S = phi_xx phi_yy + phi_xx phi_zz + phi_yy phi_zz  (first call, mode 0) or S -= phi^2 (mode 1)
 hipError_t lpt2_source(float* s, const float* a, const float* b, const float* c, long n, int mode,
                        hipStream_t st);
-hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, hipStream_t st);
+// x = d1 psi1 + d2 psi2, p = c1 psi1 + c2 psi2.
+hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, float c1, float c2, hipStream_t st);
 
 // ------------------------------------------------------------------ launchers (pk_kernels.hip)
 hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, int n_bins,

@@ -129,12 +129,25 @@ double drift_integral(double a0, double a1, double om) {
     return gauss_legendre([om](double a) { return 1.0 / (a * a * a * hubble_e(a, om)); }, a0, a1, 16);
 }
 
+// Eq. 3: nodes equally spaced in f(a) between a_0 and a_final, f = a, ln a or a^p.
 std::vector<double> time_nodes(const cola_problem& p) {
-    double a0 = 1.0 / (1.0 + p.z_init);
-    std::vector<double> a(p.n_steps);
-    double da = (p.a_final - a0) / (p.n_steps - 1);
-    for (int j = 0; j < p.n_steps; ++j) a[j] = a0 + j * da;
-    a[p.n_steps - 1] = p.a_final;
+    const double a0 = 1.0 / (1.0 + p.z_init);
+    const int n = p.n_steps;
+    std::vector<double> a(n);
+    if (p.sampling == 1) {
+        const double df = (std::log(p.a_final) - std::log(a0)) / (n - 1);
+        for (int j = 0; j < n; ++j) a[j] = std::exp(std::log(a0) + j * df);
+    } else if (p.sampling == 2) {
+        const double q = p.sampling_power;
+        const double f0 = std::pow(a0, q);
+        const double df = (std::pow(p.a_final, q) - f0) / (n - 1);
+        for (int j = 0; j < n; ++j) a[j] = std::pow(f0 + j * df, 1.0 / q);
+    } else {
+        const double da = (p.a_final - a0) / (n - 1);
+        for (int j = 0; j < n; ++j) a[j] = a0 + j * da;
+    }
+    a[0] = a0;
+    a[n - 1] = p.a_final;
     return a;
 }
 

@@ -117,20 +117,22 @@ hipError_t lpt2_source(float* s, const float* a, const float* b, const float* c,
     return hipGetLastError();
 }
 
-// x = D1 psi1 + D2 psi2 (displacement from q), p = 0: the particle starts on the 2LPT path.
-__global__ void k_ic_state(ParticlePtrs P, long n, float d1, float d2) {
+// x = D1 psi1 + D2 psi2 (displacement from q), p = c1 psi1 + c2 psi2: the particle starts on the
+// 2LPT path (c = 0 for the residual momentum of the COLA frame, c = a^2 dD/dt for the full one).
+__global__ void k_ic_state(ParticlePtrs P, long n, float d1, float d2, float c1, float c2) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        P.x[d][i] = d1 * P.psi1[d][i] + d2 * P.psi2[d][i];
-        P.p[d][i] = 0.0f;
+        const float s1 = P.psi1[d][i], s2 = P.psi2[d][i];
+        P.x[d][i] = d1 * s1 + d2 * s2;
+        P.p[d][i] = c1 * s1 + c2 * s2;
     }
 }
 
-hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, hipStream_t st) {
+hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, float c1, float c2, hipStream_t st) {
     ProfScope ps(PROF_IC, st);
-    hipLaunchKernelGGL(k_ic_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, n, d1, d2);
+    hipLaunchKernelGGL(k_ic_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, n, d1, d2, c1, c2);
     return hipGetLastError();
 }
 

@@ -119,3 +119,25 @@ def test_host_linear_power_matches_oracle():
     amp = ocosmo.linear_amplitude(c)
     for k in (1e-3, 0.01, 0.1, 0.5, 1.0, 3.0):
         assert cola.linear_power(COSMO, k) == pytest.approx(float(ocosmo.linear_power(k, c, amp)), rel=1e-8)
+
+
+def test_host_schedule_samplings_match_oracle():
+    """Eq. 3 with f = ln a and f = a^p (Sec. 4.3: 0.5 and 0.8), 40 nodes from z_i = 39."""
+    for sampling, power in (("log", None), ("power", 0.5), ("power", 0.8)):
+        p = cola.make_problem(256.0, 32, 3, 39.0, 40, sampling=sampling, sampling_power=power or 1.0)
+        tab = cola.schedule_table(p, COSMO)
+        op = ocola.Problem(256.0, 32, 3, 39.0, 40, sampling=sampling, sampling_power=power)
+        sch = ocola.Schedule(op, ocosmo.Cosmology())
+        assert np.allclose(tab[:, 0], sch.a, rtol=1e-13)
+        assert np.allclose(tab[:, 1], sch.d1, rtol=1e-10)
+        assert np.allclose(tab[:-1, 3], sch.k_out, rtol=1e-11)
+        assert np.allclose(tab[:-1, 5], sch.drift, rtol=1e-11)
+
+
+def test_problem_rejects_bad_sampling_and_frame():
+    for kw in (dict(sampling=3), dict(sampling=2, sampling_power=0.0), dict(sampling=2, sampling_power=float("nan")),
+               dict(frame=2)):
+        p = cola.make_problem(256.0, 32, 3, 19.0, 10)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        assert LIB.cola_workspace_bytes(ctypes.byref(p), 0) == 0
