@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-seed ensemble measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
     ap.add_argument("--no-haloes", action="store_true", help="skip the friends-of-friends halo measurement")
+    ap.add_argument("--no-stepping", action="store_true",
+                    help="skip the PM-only / time-sampling comparison (needs the halo measurement)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
     ap.add_argument("--profile-step", action="store_true",
                     help="for hardware counters: autotune, ICs, one COLA step, one 1 GiB copy; no timing")
@@ -249,6 +251,40 @@ def abundance_error(counts, ref, min_count=20):
     ok = ref >= min_count
     per_bin = np.abs(counts[ok] / ref[ok] - 1.0)
     return (float(per_bin.max()) if per_bin.size else float("nan"), float(counts.sum() / max(1, ref.sum())))
+
+
+def stepping_bench(cola, torch, cfg, pk_ref, halo_ref):
+    """What the 2LPT frame and the time sampling buy (Sec. 4.1, 4.3, Appendix B) on the headline
+    workload and seed: COLA and PM-only runs with 10, 20 and 40 nodes, and 40 logarithmic /
+    a^0.8 nodes, each against the timed 40-node linear COLA run (P(k) at z = 0 and haloes)."""
+    import numpy as np
+    from paper_1509_04685_amd import learned as L
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    n_pk = cfg["n_part"] * cfg["pm_factor"]
+    runs = [("cola", "linear", 10), ("cola", "linear", 20), ("pm", "linear", 10), ("pm", "linear", 20),
+            ("pm", "linear", 40), ("cola", "log", 40), ("cola", "power", 40)]
+    out = {}
+    for frame, sampling, n_steps in runs:
+        prob = cola.make_problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], cfg["z_init"], n_steps,
+                                 sampling=sampling, sampling_power=0.8, frame=frame)
+        st = cola.ParticleState(prob)
+        ws = cola.Workspace(prob, n_pk=n_pk)
+        cola.ic_2lpt(prob, cosmo, [cfg["seeds"][0]], st, ws)
+        cola.step(prob, cosmo, st, n_steps - 1, ws)
+        km, pk, _ = cola.power_spectrum(prob, cosmo, st, 1.0, n_pk, n_pk // 2, ws)
+        k, pk = km.cpu().numpy()[0], pk.cpu().numpy()[0]
+        h = haloes(cola, torch, prob, st, cosmo, cfg["box"], cfg["n_part"])
+        worst, total = abundance_error(h["counts"], halo_ref["counts"])
+        sel = (k > 0) & (k < 1.0)
+        at = {f"{kk:g}": round(float(np.interp(kk, k[sel], pk[sel] / pk_ref[sel])) - 1.0, 4) for kk in (0.1, 0.3, 1.0)}
+        name = f"{frame}_{sampling if sampling != 'power' else 'a0.8'}_{n_steps}"
+        out[name] = {"max_pk_error_k_lt_1": round(L.max_error(k, pk, pk_ref), 4), "pk_ratio_minus_1": at,
+                     "haloes_gt_100": int(h["counts"].sum()), "halo_total_ratio": round(total, 4),
+                     "max_halo_abundance_error": round(worst, 4)}
+        del st, ws
+        torch.cuda.empty_cache()
+    out["reference"] = "COLA, 40 nodes linear in a from z = 19, the timed headline run (same seed, same mesh)"
+    return out
 
 
 def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps, halo3=None):
@@ -488,6 +524,11 @@ def main():
                             "what": "friends-of-friends (b = 0.2 of the mean separation) of the z = 0 particles, "
                                     "Warren-mass histogram of haloes with more than 100 particles"}
         print(f"[bench] haloes: {json.dumps(result['haloes'])}", file=sys.stderr, flush=True)
+    if halo3 is not None and not args.no_stepping:
+        print("[bench] time stepping: COLA vs PM only, 10/20/40 nodes, log and a^0.8 samplings", file=sys.stderr,
+              flush=True)
+        result["stepping"] = stepping_bench(cola, torch, cfg, outs[-1][1].cpu().numpy()[0], halo3)
+        print(f"[bench] stepping: {json.dumps(result['stepping'])}", file=sys.stderr, flush=True)
     if not args.no_learned:
         print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
         result["learned"] = learned_bench(cola, torch, args.workload, outs[-1][1].cpu().numpy()[0], a_outs, n_pk,
