@@ -194,6 +194,23 @@ def step_pm_only(state, problem, sched, j_end):
     return state
 
 
+def redshift_space_positions(state, problem, cosmo, a, los=2, frame="cola"):
+    """Eq. 5, plane-parallel along axis los: s = x + v_los / (a H(a)), v = a dx/dt.
+
+    With p = a^2 dx/dt and H0 = 1 the shift is p_los / (a^2 E(a)).  The state must be synced at
+    a node of scale factor a.  In the COLA frame the full momentum is p_res plus the 2LPT
+    momentum a^2 (dD1/dt Psi1 + dD2/dt Psi2); with the frame switched off p_res is p itself.
+    """
+    p = state.p_res
+    if frame == "cola":
+        c1, c2 = lpt_momentum_coefficients(a, cosmo.omega_m)
+        p = p + c1 * state.psi1 + c2 * state.psi2
+    e = float(cosmology.hubble_e(a, cosmo.omega_m))
+    disp = state.disp.copy()
+    disp[los] = disp[los] + p[los] / (a * a * e)
+    return positions(State(disp, None, None, None, q=state.q), problem)
+
+
 def displacement_at(state, problem, sched, a_out):
     """Displacement at a_out in [a_j, a_{j+1}) without touching the state.
 

@@ -8,6 +8,10 @@ k-bin, and the CIC window is deconvolved by a division in Fourier space.  The pa
 names an aliasing correction (Jing 2005) without giving it, and subtracts shot noise only
 for haloes; the oracle applies neither to matter.
 
+Redshift-space multipoles (Sec. 6, Eq. 6): the same shells, each mode weighted by
+(2 ell + 1) L_ell(mu), mu = m_los / |m| the cosine to the line of sight (plane-parallel along one
+axis), L_2 = (3 mu^2 - 1) / 2, L_4 = (35 mu^4 - 30 mu^2 + 3) / 8.
+
 Estimator for an n^3 analysis mesh in a box L:
   delta_k = FFT[rho / rho_bar - 1],
   W(m) = prod_d sinc^2(pi m_d / n)                         (CIC window),
@@ -79,3 +83,50 @@ def field_power(delta, box, n_bins):
     n = delta.shape[0]
     dk = sfft.rfftn(delta)
     return bin_power(dk, n, box, n_bins, deconvolve=False)
+
+
+def legendre(ell, mu):
+    """Legendre polynomials L_0, L_2, L_4."""
+    mu = np.asarray(mu, dtype=np.float64)
+    if ell == 0:
+        return np.ones_like(mu)
+    if ell == 2:
+        return 0.5 * (3.0 * mu ** 2 - 1.0)
+    if ell == 4:
+        return 0.125 * (35.0 * mu ** 4 - 30.0 * mu ** 2 + 3.0)
+    raise ValueError(ell)
+
+
+def bin_multipoles(delta_k, n, box, n_bins, los=2, deconvolve=True):
+    """(k_mean, P_0, P_2, P_4, n_modes) of a half spectrum about axis los, shells of bin_power."""
+    mx, my, mz = lpt.mode_integers(n)
+    m2 = mx ** 2 + my ** 2 + mz ** 2
+    b = np.floor(np.sqrt(m2.astype(np.float64))).astype(np.int64)
+    b = np.where(b * b > m2, b - 1, b)
+    b = np.where((b + 1) * (b + 1) <= m2, b + 1, b)
+    p = np.abs(delta_k) ** 2
+    if deconvolve:
+        p = p / cic_window(n) ** 2
+    ml = (mx, my, mz)[los]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mu = np.where(m2 > 0, ml / np.sqrt(m2.astype(np.float64)), 0.0)
+    w = np.broadcast_to(mode_weights(n), m2.shape)
+    kmag = 2.0 * np.pi / box * np.sqrt(m2.astype(np.float64))
+    keep = (m2 > 0) & (b < n_bins)
+    bb, ww = b[keep], w[keep]
+    cnt = np.bincount(bb, weights=ww, minlength=n_bins)
+    ksum = np.bincount(bb, weights=ww * kmag[keep], minlength=n_bins)
+    out = []
+    for ell in (0, 2, 4):
+        s = np.bincount(bb, weights=ww * p[keep] * legendre(ell, mu[keep]), minlength=n_bins)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out.append(np.where(cnt > 0, (2 * ell + 1) * s / cnt * box ** 3 / float(n) ** 6, 0.0))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        km = np.where(cnt > 0, ksum / cnt, 0.0)
+    return km, out[0], out[1], out[2], cnt
+
+
+def multipoles(pos, n_mesh, box, n_bins, los=2, deconvolve=True):
+    """Multipoles of particles at positions (3, N) on an n_mesh^3 CIC grid."""
+    delta = pm.density_contrast(pos, n_mesh, box)
+    return bin_multipoles(sfft.rfftn(delta), n_mesh, box, n_bins, los, deconvolve)
