@@ -148,6 +148,22 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo,
                         double* k_mean, double* pk, double* n_modes,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Redshift-space multipoles (Sec. 6: Eq. 5 mapping, Eq. 6 multipoles).  Plane-parallel: the line
+ * of sight is axis `los` (0, 1, 2).  With redshift_space != 0 each particle is moved along the line
+ * of sight by v_los / (a H(a)) (Eq. 5), v = a dx/dt its peculiar velocity at the state's node (the
+ * momentum is synced only at nodes, so a_out must equal the scale factor of in->node; otherwise
+ * COLA_ERR_STATE); with redshift_space = 0 the real-space positions are used.  The density on the
+ * n_pk^3 mesh, its transform, the CIC window and the shells are those of cola_power_spectrum, and
+ * each mode is weighted by the Legendre polynomial of mu = k_los / |k|:
+ *   P_ell(k_b) = (2 ell + 1) sum_modes w |delta_k|^2 / W^2 L_ell(mu) / sum_modes w,  ell = 0, 2, 4
+ * (P_0 is cola_power_spectrum's P(k)).  Outputs: device [n_real][n_bins] float64 each, overwritten.
+ * No Jing (2005) aliasing correction and no shot-noise subtraction (the paper states neither
+ * method for matter).  ws: cola_workspace_bytes(prob, n_pk).  The state is not changed. */
+int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,
+                          double a_out, int32_t los, int32_t redshift_space, int32_t n_pk, int32_t n_bins,
+                          double* k_mean, double* p0, double* p2, double* p4, double* n_modes, void* ws,
+                          size_t ws_bytes, void* stream);
+
 /* ---- ensembles ------------------------------------------------------------------------- */
 
 /* One shape class of an ensemble: n_real = prob.n_real realizations of one problem. */

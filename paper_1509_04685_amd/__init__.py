@@ -131,6 +131,18 @@ def step(prob, cosmo, state, j_end, ws):
                "cola_step")
 
 
+def power_multipoles(prob, cosmo, state, a_out, n_pk, n_bins, ws, los=2, redshift_space=True):
+    """Multipoles about axis `los` at the state's node: (k_mean, p0, p2, p4, n_modes), each
+    (n_real, n_bins) float64 device tensors; redshift_space maps positions with Eq. 5 first."""
+    torch = _torch()
+    out = tuple(torch.empty((prob.n_real, n_bins), dtype=torch.float64, device=state.x.device) for _ in range(5))
+    _lib.check(_lib.lib().cola_power_multipoles(ctypes.byref(prob), ctypes.byref(cosmo), ctypes.byref(state.c),
+                                                float(a_out), int(los), 1 if redshift_space else 0, int(n_pk),
+                                                int(n_bins), *[_ptr(t) for t in out], ws.ptr, ws.nbytes, _stream()),
+               "cola_power_multipoles")
+    return out
+
+
 def power_spectrum(prob, cosmo, state, a_out, n_pk, n_bins, ws, out=None):
     """Returns (k_mean, pk, n_modes), each (n_real, n_bins) float64 device tensors."""
     torch = _torch()

@@ -488,6 +488,68 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     return COLA_OK;
 }
 
+int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in, double a_out,
+                          int32_t los, int32_t redshift_space, int32_t n_pk, int32_t n_bins, double* k_mean,
+                          double* p0, double* p2, double* p4, double* n_modes, void* ws, size_t ws_bytes,
+                          void* stream) {
+    int s;
+    if ((s = check_problem(prob)) != COLA_OK) return s;
+    if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
+    if ((s = check_particles(in)) != COLA_OK) return s;
+    if (!k_mean || !p0 || !p2 || !p4 || !n_modes || !ws) return COLA_ERR_INVALID_ARG;
+    if (n_bins < 1 || n_bins > 4096 || los < 0 || los > 2) return COLA_ERR_INVALID_ARG;
+    if (!fft_size_ok(n_pk) || n_pk > kMaxMesh) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (in->node < 0 || in->node >= prob->n_steps) return COLA_ERR_STATE;
+    const cola_problem& p = *prob;
+    Layout L = layout_of(p, n_pk);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    Schedule sc = make_schedule(p, *cosmo);
+    const int j = in->node;
+    const double aj = sc.a[j];
+    // velocities are synced only at a node: the output must sit on the state's node
+    if (!(std::fabs(a_out - aj) <= 1e-12 * aj)) return COLA_ERR_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    ParticlePtrs P = ptrs_of(in);
+    const long npr = (long)p.n_part * p.n_part * p.n_part;
+    LatticeGeom fg = force_geom(p, L);
+    ForceMeshes f = force_meshes(w);
+    // Eq. 5, plane-parallel: s = x + v_los / (a H) along axis los, v = a dx/dt the peculiar
+    // velocity.  With p = a^2 dx/dt (H0 = 1) the shift is p_los / (a^2 E(a)); in the COLA frame
+    // p = p_res + a^3 E (dD1/da Psi1 + dD2/da Psi2), which adds a (dD1/da Psi1 + dD2/da Psi2).
+    KickDrift kd{};
+    kd.los = los;
+    if (redshift_space) {
+        const double e = hubble_e(aj, sc.omega_m);
+        Growth ga = growth(aj, sc.omega_m);
+        kd.drift = (float)(1.0 / (aj * aj * e));
+        kd.dd1 = p.frame == 1 ? 0.0f : (float)(aj * ga.dd1_da);
+        kd.dd2 = p.frame == 1 ? 0.0f : (float)(aj * ga.dd2_da);
+    }
+    (void)hipGetLastError();
+    COLA_TRY(launch_twiddles(w.twk, n_pk, st));
+    const Mesh3& gk = L.gk;
+    LatticeGeom dg;
+    dg.n_part = p.n_part;
+    dg.n_mesh = n_pk;
+    dg.inv_h = (float)(n_pk / p.box);
+    dg.qoff = (float)(0.5 * (double)n_pk / (double)L.g.n);
+    dg.row = 2L * gk.nzp;
+    dg.mesh_bstride = 2L * L.kstride;
+    double cells = (double)n_pk * n_pk * n_pk;
+    SortBufs sb = carve_sort(w.sort, npr, L.tk, p.n_real);
+    COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, redshift_space != 0, fg, f.fx, f.fy, f.fz, kd, L.tk, sb,
+                            reinterpret_cast<float*>(w.K), (float)(cells / (double)npr), -1.0f, st));
+    COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K, L.kstride, gk, w.twk,
+                       p.n_real, 1.0f, 0.0f, st));
+    const long nb = (long)n_bins * p.n_real;
+    for (double* o : {k_mean, p0, p2, p4, n_modes}) COLA_TRY(launch_fill_d(o, nb, 0.0, st));
+    COLA_TRY(pk_bin_multipoles(w.K, L.kstride, gk, p.n_real, n_bins, los, k_mean, p0, p2, p4, n_modes,
+                               2.0 * M_PI / p.box, st));
+    COLA_TRY(pk_finish_multipoles(k_mean, p0, p2, p4, n_modes, nb, p.box * p.box * p.box / (cells * cells), st));
+    return COLA_OK;
+}
+
 // ---------------------------------------------------------------- component entry points
 
 size_t cola_cic_workspace_bytes(int64_t n, int32_t n_mesh) {

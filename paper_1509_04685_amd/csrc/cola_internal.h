@@ -140,6 +140,7 @@ struct KickDrift {
     float d2m;      // D2 - D1^2 at that node
     float drift;    // Dr of the drift (0 with no drift)
     float dd1, dd2; // growth increments of the drift
+    int los = -1;   // drift along this axis only (the redshift-space mapping); -1: every axis
 };
 
 hipError_t launch_fill(float* p, long n, float v, hipStream_t st);
@@ -212,6 +213,13 @@ hipError_t ic_set_state(const ParticlePtrs& P, long n, float d1, float d2, float
 // ------------------------------------------------------------------ launchers (pk_kernels.hip)
 hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, int n_bins,
                   double* ksum, double* psum, double* cnt, double kf, hipStream_t st);
+// Multipoles ell = 0, 2, 4 about the axis los: sums of w |delta|^2 / W^2 L_ell(mu), mu = m_los / |m|.
+hipError_t pk_bin_multipoles(const float2* spec, long bstride, const Mesh3& g, int n_real, int n_bins, int los,
+                             double* ksum, double* p0, double* p2, double* p4, double* cnt, double kf,
+                             hipStream_t st);
+// P_ell = (2 ell + 1) sum_ell / cnt * pnorm, k_mean = ksum / cnt.
+hipError_t pk_finish_multipoles(double* kmean, double* p0, double* p2, double* p4, const double* cnt, long n,
+                                double pnorm, hipStream_t st);
 hipError_t pk_finish(double* kmean, double* pk, double* cnt, long n, double pnorm, hipStream_t st);
 
 }  // namespace cola

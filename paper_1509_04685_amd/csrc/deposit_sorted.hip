@@ -133,14 +133,17 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
 #pragma unroll
         for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];
         if (DRIFT) {
-            CellC c[3];
+            float g[3] = {0.0f, 0.0f, 0.0f};
+            if (kd.kick != 0.0f) {  // no force mesh is read for a pure drift (redshift-space mapping)
+                CellC c[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) c[d] = cell_c(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
-            float g[3];
-            const long mo = (long)r * fg.mesh_bstride;
-            gather3c(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c, g);
+                for (int d = 0; d < 3; ++d) c[d] = cell_c(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
+                const long mo = (long)r * fg.mesh_bstride;
+                gather3c(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c, g);
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
+                if (kd.los >= 0 && d != kd.los) continue;
                 float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
                 float ph = P.p[d][gid] + kd.kick * (g[d] - kd.d1 * s1 - kd.d2m * s2);
                 x[d] = x[d] + ph * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
