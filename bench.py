@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-seed ensemble measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
     ap.add_argument("--no-haloes", action="store_true", help="skip the friends-of-friends halo measurement")
+    ap.add_argument("--no-multipoles", action="store_true", help="skip the redshift-space multipole measurement")
     ap.add_argument("--no-stepping", action="store_true",
                     help="skip the PM-only / time-sampling comparison (needs the halo measurement)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
@@ -287,6 +288,47 @@ def stepping_bench(cola, torch, cfg, pk_ref, halo_ref):
     return out
 
 
+def multipoles_bench(cola, torch, prob, st, cfg, n_pk=1024):
+    """Redshift-space multipoles (Sec. 6: Eq. 5, 6) of the headline run's z = 0 particles on the
+    paper's 1024^3 analysis mesh, line of sight z: time per call and P_2 / P_0 at large scales
+    against the linear (Kaiser) value (4f/3 + 4f^2/7) / (1 + 2f/3 + f^2/5)."""
+    import numpy as np
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    tab = cola.schedule_table(prob, cosmo)
+    a = float(tab[-1, 0])
+    # f = dln D1 / dln a at the last node from a three-point one-sided difference on the nodes
+    a3, d3 = tab[-3:, 0], tab[-3:, 1]
+    h = a3[2] - a3[1]
+    dd = (3.0 * d3[2] - 4.0 * d3[1] + d3[0]) / (2.0 * h) if abs((a3[1] - a3[0]) - h) < 1e-9 * h else None
+    f = a * dd / d3[2] if dd is not None else float("nan")
+    ws = cola.Workspace(prob, n_pk=n_pk)
+    n_bins = n_pk // 2
+    cola.power_multipoles(prob, cosmo, st, a, n_pk, n_bins, ws)  # warm (plans, twiddles)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    km, p0, p2, p4, nm = cola.power_multipoles(prob, cosmo, st, a, n_pk, n_bins, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    km, p0, p2, p4, nm = (t.cpu().numpy()[0] for t in (km, p0, p2, p4, nm))
+    real = cola.power_multipoles(prob, cosmo, st, a, n_pk, n_bins, ws, redshift_space=False)
+    r0 = real[1].cpu().numpy()[0]
+    lo = (nm > 0) & (km < 0.05)
+    kaiser = (4 * f / 3 + 4 * f * f / 7) / (1 + 2 * f / 3 + f * f / 5)
+    pick = {f"{kk:g}": [round(float(np.interp(kk, km[nm > 0], v[nm > 0])), 1) for v in (p0, p2, p4)]
+            for kk in (0.05, 0.1, 0.2, 0.5)}
+    del ws
+    torch.cuda.empty_cache()
+    return {"ms_per_call": round(e0.elapsed_time(e1), 3), "analysis_mesh": n_pk, "los": "z",
+            "growth_rate_f": round(f, 4), "p2_over_p0_k_lt_0.05": round(float(p2[lo].sum() / p0[lo].sum()), 4),
+            "kaiser_p2_over_p0": round(kaiser, 4),
+            "p0_over_real_k_lt_0.05": round(float(p0[lo].sum() / r0[lo].sum()), 4),
+            "kaiser_p0_over_real": round(1 + 2 * f / 3 + f * f / 5, 4),
+            "p0_p2_p4_at_k": pick,
+            "what": "plane-parallel redshift space (Eq. 5) at z = 0, multipoles in the P(k) shells (Eq. 6); "
+                    "mode-weighted sums over k < 0.05 h/Mpc against linear theory"}
+
+
 def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps, halo3=None):
     """The learned-correction form: 256^3 particles on the 256^3 (PM_grid = 1) mesh with the trained
     network, against the plain 3x realization timed above (same seed, same outputs) and the plain
@@ -513,6 +555,10 @@ def main():
     }
     if roofline is not None:
         roofline["copy_ceiling_gbs"] = copy_ceiling(cola, torch)
+    if not args.no_multipoles:
+        print("[bench] redshift-space multipoles on the 1024^3 analysis mesh", file=sys.stderr, flush=True)
+        result["multipoles"] = multipoles_bench(cola, torch, prob, st, cfg)
+        print(f"[bench] multipoles: {json.dumps(result['multipoles'])}", file=sys.stderr, flush=True)
     halo3 = None
     if not args.no_haloes:
         # the state holds the last timed realization at z = 0
