@@ -11,6 +11,10 @@ convolutional network that maps the coarse (PM_grid = 1) mesh fields to a force 
   Z1 = conv3(W1, X0) + b1,  A1 = silu(Z1)               (3x3x3 taps, C channels)
   Z2 = conv3(W2, A1) + b2,  A2 = silu(Z2)               (3x3x3 taps, C channels)
   Y  = conv1(W3, A2) + b3,  dF = Y * out_scale          (1x1x1, 3 channels)
+  optional band weight beta:  dF <- dF + beta (K dF - K K dF),
+  K the periodic [1, 2, 1] / 4 smoothing along each mesh axis: K - K^2 multiplies a mode by
+  c (1 - c) with c = prod_d cos^2(pi m_d / n), a band-pass that vanishes at k = 0 (as k^2) and at
+  the Nyquist corner and peaks where c = 1/2.
 
 conv3 is a periodic cross-correlation, Z[o][x] = sum_i sum_d W[o][i][d] X[i][x + d] with
 d in {-1, 0, 1}^3 and tap index (dx+1)*9 + (dy+1)*3 + (dz+1); silu(z) = z / (1 + e^-z).  The
@@ -66,10 +70,23 @@ def conv1(w, b, x):
     return np.tensordot(w, x, axes=([1], [0])) + b[:, None, None, None]
 
 
+def binomial_smooth(x):
+    """K: the periodic [1, 2, 1] / 4 smoothing along each of the last three axes."""
+    for ax in (-3, -2, -1):
+        x = 0.25 * np.roll(x, 1, axis=ax) + 0.5 * x + 0.25 * np.roll(x, -1, axis=ax)
+    return x
+
+
+def band_pass(x):
+    """K x - K K x (symmetric, so it is its own adjoint)."""
+    kx = binomial_smooth(x)
+    return kx - binomial_smooth(kx)
+
+
 class Net:
     """Parameters of the correction network (float64)."""
 
-    def __init__(self, channels=16, seed=0, in_scale=(1.0, 1.0, 1.0, 1.0), out_scale=1.0):
+    def __init__(self, channels=16, seed=0, in_scale=(1.0, 1.0, 1.0, 1.0), out_scale=1.0, band=0.0):
         rng = np.random.default_rng(seed)
         c = channels
         self.c = c
@@ -81,6 +98,7 @@ class Net:
         self.b3 = np.zeros(3)
         self.in_scale = np.asarray(in_scale, dtype=np.float64)
         self.out_scale = float(out_scale)
+        self.band = float(band)
 
     def params(self):
         return [self.w1, self.b1, self.w2, self.b2, self.w3, self.b3]
@@ -94,12 +112,17 @@ def forward(net, delta, g):
     z2 = conv3(net.w2, net.b2, a1)
     a2 = silu(z2)
     y = conv1(net.w3, net.b3, a2)
-    return y * net.out_scale, (x0, z1, a1, z2, a2)
+    df = y * net.out_scale
+    if net.band != 0.0:
+        df = df + net.band * band_pass(df)
+    return df, (x0, z1, a1, z2, a2)
 
 
 def backward(net, cache, d_df):
     """Parameter gradients for upstream d_df (3, n, n, n) = dL/d(dF)."""
     x0, z1, a1, z2, a2 = cache
+    if net.band != 0.0:
+        d_df = d_df + net.band * band_pass(d_df)
     dy = d_df * net.out_scale
     dw3 = np.tensordot(dy, a2, axes=([1, 2, 3], [1, 2, 3]))
     db3 = dy.sum(axis=(1, 2, 3))

@@ -61,8 +61,10 @@ def _loss(net, delta, g, box, pos, g1, g3):
     return L.particle_loss(df, pos, box, g1, g3)[0]
 
 
-def test_gradients_match_finite_differences():
+@pytest.mark.parametrize("band", [0.0, 0.8])
+def test_gradients_match_finite_differences(band):
     net, delta, g, box, pos, g1, g3 = _setup()
+    net.band = band
     df, cache = L.forward(net, delta, g)
     _, d_df = L.particle_loss(df, pos, box, g1, g3)
     grads = L.backward(net, cache, d_df)
@@ -79,6 +81,22 @@ def test_gradients_match_finite_differences():
             p[idx] = old
             fd = (lp - lm) / (2 * h)
             assert fd == pytest.approx(gr[idx], rel=1e-6, abs=1e-9), (p.shape, idx)
+
+
+def test_band_pass_on_plane_waves_and_constants():
+    n = 12
+    idx = np.indices((n, n, n))
+    for m in ((0, 0, 1), (1, 2, 3), (6, 0, 0), (3, 3, 3), (5, 1, 4)):
+        phase = 2 * np.pi * (m[0] * idx[0] + m[1] * idx[1] + m[2] * idx[2]) / n
+        x = np.cos(phase + 0.3)
+        c = np.prod([np.cos(np.pi * md / n) ** 2 for md in m])
+        assert np.allclose(L.binomial_smooth(x), c * x, atol=1e-12)
+        assert np.allclose(L.band_pass(x), c * (1 - c) * x, atol=1e-12)
+    assert np.allclose(L.band_pass(np.full((2, n, n, n), 3.7)), 0.0, atol=1e-12)
+    # self-adjoint: <B x, y> = <x, B y>
+    rng = np.random.default_rng(4)
+    a, b = rng.normal(size=(n, n, n)), rng.normal(size=(n, n, n))
+    assert abs(np.sum(L.band_pass(a) * b) - np.sum(a * L.band_pass(b))) < 1e-10
 
 
 def test_loss_is_one_without_correction():
