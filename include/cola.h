@@ -223,6 +223,10 @@ typedef struct {
     float out_scale;     /* output scale (at a = 1)                                            */
     float out_scale_slope; /* in the step the scale at a node is out_scale (1 + slope (1 - a)); the
                             other entry points use out_scale                                   */
+    float out_band;      /* band-pass weight beta: the output becomes dF + beta (K dF - K K dF),
+                            K the periodic [1, 2, 1] / 4 smoothing along each mesh axis (a mode
+                            is multiplied by 1 + beta c (1 - c), c = prod_d cos^2(pi m_d / n));
+                            0 = off.  Applied in every entry point, backward included          */
     float* params;       /* device, cola_lc_param_count(C) floats, flat in the order
                             w1 (C,4,27) b1 (C) w2 (C,C,27) b2 (C) w3 (3,C) b3 (3), C order       */
     float* grads;        /* device, same size: cola_lc_backward adds into it, cola_lc_adam

@@ -360,16 +360,22 @@ class LcNet:
         self.set_params(lc_init_params(channels) if params is None else params)
         self.step_count = 0
 
-    def set_scales(self, in_scale, out_scale, out_scale_slope=None):
+    def set_scales(self, in_scale, out_scale, out_scale_slope=None, out_band=None):
         for i in range(4):
             self.c.in_scale[i] = float(in_scale[i])
         self.c.out_scale = float(out_scale)
         if out_scale_slope is not None:
             self.c.out_scale_slope = float(out_scale_slope)
+        if out_band is not None:
+            self.c.out_band = float(out_band)
 
     @property
     def out_scale_slope(self):
         return float(self.c.out_scale_slope)
+
+    @property
+    def out_band(self):
+        return float(self.c.out_band)
 
     @property
     def in_scale(self):

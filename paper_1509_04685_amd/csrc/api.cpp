@@ -158,6 +158,7 @@ struct LcHook {
     float in_scale[4];
     float out_scale;
     float out_scale_slope;
+    float out_band;
     float scale_at(double a) const { return (float)(out_scale * (1.0 + out_scale_slope * (1.0 - a))); }
 };
 
@@ -188,7 +189,7 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
         float* f[3] = {reinterpret_cast<float*>(w.B) + r * bs, reinterpret_cast<float*>(w.A) + r * bs,
                        reinterpret_cast<float*>(w.S) + r * bs};
         if ((e = lc_forward_fields(lc->P, lc->A.a1, lc->A.x0 + r * lc->x0_stride, f, row, L.g.n, lc->in_scale,
-                                   lc->scale_at(a_node), st)) != hipSuccess)
+                                   lc->scale_at(a_node), lc->out_band, lc->A.t, st)) != hipSuccess)
             return e;
     }
     return hipSuccess;
@@ -417,6 +418,7 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
     for (int i = 0; i < 4; ++i) h.in_scale[i] = net->in_scale[i];
     h.out_scale = net->out_scale;
     h.out_scale_slope = net->out_scale_slope;
+    h.out_band = net->out_band;
     return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, &h);
 }
 

@@ -23,6 +23,7 @@ LcWsLayout lc_ws_layout(int n, int C, int n_real, bool training) {
     L.x0 = off; off += lc_align(V * 16 * (size_t)n_real);
     L.a1 = off; off += act;
     L.a2 = off; off += act;
+    L.t = off; off += lc_align(V * 12);
     if (training) {
         L.z1 = off; off += act;
         L.z2 = off; off += act;
@@ -39,6 +40,7 @@ LcActs lc_carve(void* ws, const LcWsLayout& L) {
     A.x0 = reinterpret_cast<uint16_t*>(b + L.x0);
     A.a1 = reinterpret_cast<uint16_t*>(b + L.a1);
     A.a2 = reinterpret_cast<uint16_t*>(b + L.a2);
+    A.t = reinterpret_cast<float*>(b + L.t);
     const bool tr = L.z1 != 0;
     A.z1 = tr ? reinterpret_cast<uint16_t*>(b + L.z1) : nullptr;
     A.z2 = tr ? reinterpret_cast<uint16_t*>(b + L.z2) : nullptr;
@@ -52,7 +54,8 @@ int lc_check_net(const cola_lc_net* net, bool training) {
     if (net->channels != 16 && net->channels != 32) return COLA_ERR_INVALID_ARG;
     for (int i = 0; i < 4; ++i)
         if (!std::isfinite(net->in_scale[i])) return COLA_ERR_INVALID_ARG;
-    if (!std::isfinite(net->out_scale) || !std::isfinite(net->out_scale_slope)) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(net->out_scale) || !std::isfinite(net->out_scale_slope) || !std::isfinite(net->out_band))
+        return COLA_ERR_INVALID_ARG;
     if (training && (!net->grads || !net->adam_m || !net->adam_v)) return COLA_ERR_INVALID_ARG;
     return COLA_OK;
 }
@@ -139,7 +142,8 @@ int cola_lc_forward(const cola_lc_net* net, int32_t n_mesh, const float* delta, 
     const LcParams P = lc_params_of(net);
     (void)hipGetLastError();
     LC_TRY(lc_pack(delta, g, n_mesh, n_mesh, net->in_scale, A.x0, st));
-    LC_TRY(lc_forward(P, A, n_mesh, net->out_scale, df, n_mesh, accumulate ? 1 : 0, training != 0, st));
+    LC_TRY(lc_forward(P, A, n_mesh, net->out_scale, net->out_band, df, n_mesh, accumulate ? 1 : 0, training != 0,
+                      st));
     return COLA_OK;
 }
 
@@ -159,7 +163,7 @@ int cola_lc_backward(const cola_lc_net* net, int32_t n_mesh, const float* d_df, 
     LcGrads G{net->grads + o.w1, net->grads + o.b1, net->grads + o.w2,
               net->grads + o.b2, net->grads + o.w3, net->grads + o.b3};
     (void)hipGetLastError();
-    LC_TRY(lc_backward(P, A, G, n_mesh, net->out_scale, d_df, st));
+    LC_TRY(lc_backward(P, A, G, n_mesh, net->out_scale, net->out_band, d_df, st));
     return COLA_OK;
 }
 

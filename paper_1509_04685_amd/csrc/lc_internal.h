@@ -52,6 +52,7 @@ struct LcGrads {
 // BF16 activations, channel-last: x0 [V][8]; the others [V][C].  z1, z2, dz1, dz2 only when training.
 struct LcActs {
     uint16_t *x0, *z1, *a1, *z2, *a2, *dz1, *dz2;
+    float* t;  // [3][V] FP32 scratch of the band-pass output weight
 };
 
 hipError_t lc_mfma_selftest(const uint16_t* A, const uint16_t* B, float* D, hipStream_t st);
@@ -64,15 +65,20 @@ hipError_t lc_pack(const float* delta, const float* const g[3], long row, int n,
 // overwrites the density; later the network reads d0 and the force meshes directly and adds dF
 // to the force meshes (a1: [n^3][C] BF16 scratch).
 hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* d0, hipStream_t st);
+// band != 0: dF goes through t ([3][n^3] scratch) and the band-pass weight (lc_band).
 hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row, int n,
-                             const float in_scale[4], float out_scale, hipStream_t st);
-// dF (times out_scale) written to, or added into, three meshes with `row` floats per row.  keep_z
-// stores z1, z2 for the backward pass.
-hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
-                      int accumulate, bool keep_z, hipStream_t st);
+                             const float in_scale[4], float out_scale, float band, float* t, hipStream_t st);
+// dF (times out_scale, then through the band-pass weight) written to, or added into, three meshes
+// with `row` floats per row.  keep_z stores z1, z2 for the backward pass.
+hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float band, float* const out[3],
+                      long row, int accumulate, bool keep_z, hipStream_t st);
 // Accumulates the parameter gradients for upstream d_df (dense [3][n^3]).
-hipError_t lc_backward(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, const float* ddf,
-                       hipStream_t st);
+hipError_t lc_backward(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, float band,
+                       const float* ddf, hipStream_t st);
+// out[c] (+)= T[c] + beta (K T[c] - K K T[c]), K the periodic [1, 2, 1] / 4 smoothing per axis;
+// T dense [3][n^3] (n a multiple of 16), out with `row` floats per row; T and out must not overlap.
+hipError_t lc_band(const float* T, int n, float beta, float* const out[3], long row, int accumulate,
+                   hipStream_t st);
 // Particle loss (stats[0] = L, stats[1] = denominator; zeroed here) and d_df = dL/d(dF) (overwritten).
 hipError_t lc_loss(const float* const pos[3], long np, int n, double box, const float* const df[3],
                    const float* const g1[3], const float* const g3[3], double* stats, float* ddf,
@@ -91,7 +97,7 @@ hipError_t mesh_unpad(const float* src, long row, int n, float* dst, hipStream_t
 // Workspace of the network (lc_api.cpp): x0 for n_real realizations, a1 and a2 shared, and when
 // training z1, z2, dz1, dz2.
 struct LcWsLayout {
-    size_t x0 = 0, a1 = 0, a2 = 0, z1 = 0, z2 = 0, dz1 = 0, dz2 = 0, total = 0;
+    size_t x0 = 0, a1 = 0, a2 = 0, t = 0, z1 = 0, z2 = 0, dz1 = 0, dz2 = 0, total = 0;
     long x0_stride = 0;  // uint16 per realization (x0 holds n_real compact deltas in the step)
 };
 LcWsLayout lc_ws_layout(int n, int C, int n_real, bool training);

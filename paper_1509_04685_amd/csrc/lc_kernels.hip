@@ -109,6 +109,7 @@ struct OutDst {
     const float* w3;
     const float* b3;
     float scale;
+    int overwrite;  // 1: store dF; 0: add it
 };
 
 // out[v][co] = sum_tap sum_ci W[co][tap][ci] in[v + d_tap][ci] + bias[co], then
@@ -220,9 +221,15 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
             }
             const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
             const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + z0 + lz;
-            od.f[0][o] += y0 * od.scale;
-            od.f[1][o] += y1 * od.scale;
-            od.f[2][o] += y2 * od.scale;
+            if (od.overwrite) {
+                od.f[0][o] = y0 * od.scale;
+                od.f[1][o] = y1 * od.scale;
+                od.f[2][o] = y2 * od.scale;
+            } else {
+                od.f[0][o] += y0 * od.scale;
+                od.f[1][o] += y1 * od.scale;
+                od.f[2][o] += y2 * od.scale;
+            }
             continue;
         }
 #pragma unroll
@@ -263,6 +270,110 @@ static hipError_t run_conv(const uint16_t* in, const uint16_t* w, const float* b
     ProfScope ps(PROF_LC_CONV, st);
     hipLaunchKernelGGL(kern, dim3((unsigned)std::min<long>(tiles, 4096)), dim3(256), lds, st, in, w, bias, out, out2,
                        prev, n, (int)tiles, fs, od);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ band-pass output weight
+
+// out[c] (+)= T[c] + beta (K T[c] - K K T[c]), K the periodic [1, 2, 1] / 4 smoothing along each
+// axis; T dense [3][n^3], out with `row` floats per (x, y) row.  One block per 8 x 8 x 16 tile:
+// T with a halo of two cells goes to LDS, K is applied as three axis passes (giving K T on the
+// tile plus one cell), then three more (K K T on the tile); the passes ping-pong between two
+// LDS buffers.
+constexpr int BX = 8, BY = 8, BZ = 16;
+constexpr int BH = (BX + 4) * (BY + 4) * (BZ + 4);
+
+__device__ __forceinline__ float k121(float a, float b, float c) { return 0.25f * a + 0.5f * b + 0.25f * c; }
+
+__global__ void __launch_bounds__(256) k_lc_band(const float* __restrict__ T, int n, float beta, float* o0, float* o1,
+                                                 float* o2, long row, int accumulate) {
+    __shared__ float bufa[BH], bufb[BH];
+    const int tid = threadIdx.x;
+    const int ntz = n / BZ, nty = n / BY;
+    const int tile = blockIdx.x;
+    const int z0 = (tile % ntz) * BZ, y0 = ((tile / ntz) % nty) * BY, x0 = (tile / (ntz * nty)) * BX;
+    const long V = (long)n * n * n;
+    float* outs[3] = {o0, o1, o2};
+    for (int c = 0; c < 3; ++c) {
+        const float* src = T + c * V;
+        // H: (BX+4) x (BY+4) x (BZ+4), origin at (x0-2, y0-2, z0-2)
+        constexpr int HX = BX + 4, HY = BY + 4, HZ = BZ + 4;
+        for (int i = tid; i < BH; i += 256) {
+            const int hz = i % HZ, hy = (i / HZ) % HY, hx = i / (HZ * HY);
+            const int gx = (x0 + hx - 2 + n) % n, gy = (y0 + hy - 2 + n) % n, gz = (z0 + hz - 2 + n) % n;
+            bufa[i] = src[((long)gx * n + gy) * n + gz];
+        }
+        __syncthreads();
+        float tc[4], kt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = tid + 256 * j, lz = v % BZ, ly = (v / BZ) % BY, lx = v / (BZ * BY);
+            tc[j] = bufa[((lx + 2) * HY + ly + 2) * HZ + lz + 2];
+        }
+        // z pass: HX x HY x (BZ+2)
+        constexpr int Z1 = BZ + 2;
+        for (int i = tid; i < HX * HY * Z1; i += 256) {
+            const int z = i % Z1, xy = i / Z1;
+            const float* h = bufa + xy * HZ + z;
+            bufb[i] = k121(h[0], h[1], h[2]);
+        }
+        __syncthreads();
+        // y pass: HX x (BY+2) x Z1
+        constexpr int Y1 = BY + 2;
+        for (int i = tid; i < HX * Y1 * Z1; i += 256) {
+            const int z = i % Z1, y = (i / Z1) % Y1, x = i / (Z1 * Y1);
+            const float* h = bufb + (x * HY + y) * Z1 + z;
+            bufa[i] = k121(h[0], h[Z1], h[2 * Z1]);
+        }
+        __syncthreads();
+        // x pass: (BX+2) x Y1 x Z1 = K T on the tile plus one cell
+        constexpr int X1 = BX + 2;
+        for (int i = tid; i < X1 * Y1 * Z1; i += 256) {
+            const int yz = i % (Y1 * Z1), x = i / (Y1 * Z1);
+            const float* h = bufa + x * Y1 * Z1 + yz;
+            bufb[i] = k121(h[0], h[Y1 * Z1], h[2 * Y1 * Z1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = tid + 256 * j, lz = v % BZ, ly = (v / BZ) % BY, lx = v / (BZ * BY);
+            kt[j] = bufb[((lx + 1) * Y1 + ly + 1) * Z1 + lz + 1];
+        }
+        // second smoothing: z pass X1 x Y1 x BZ
+        for (int i = tid; i < X1 * Y1 * BZ; i += 256) {
+            const int z = i % BZ, xy = i / BZ;
+            const float* h = bufb + xy * Z1 + z;
+            bufa[i] = k121(h[0], h[1], h[2]);
+        }
+        __syncthreads();
+        // y pass: X1 x BY x BZ
+        for (int i = tid; i < X1 * BY * BZ; i += 256) {
+            const int z = i % BZ, y = (i / BZ) % BY, x = i / (BZ * BY);
+            const float* h = bufa + (x * Y1 + y) * BZ + z;
+            bufb[i] = k121(h[0], h[BZ], h[2 * BZ]);
+        }
+        __syncthreads();
+        float* dst = outs[c];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = tid + 256 * j, lz = v % BZ, ly = (v / BZ) % BY, lx = v / (BZ * BY);
+            const float* h = bufb + (lx * BY + ly) * BZ + lz;
+            const float kkt = k121(h[0], h[BY * BZ], h[2 * BY * BZ]);
+            const float val = tc[j] + beta * (kt[j] - kkt);
+            const long o = ((long)(x0 + lx) * n + (y0 + ly)) * row + z0 + lz;
+            if (accumulate) dst[o] += val;
+            else dst[o] = val;
+        }
+        __syncthreads();  // the buffers are reused by the next component
+    }
+}
+
+hipError_t lc_band(const float* T, int n, float beta, float* const out[3], long row, int accumulate,
+                   hipStream_t st) {
+    ProfScope ps(PROF_LC_MISC, st);
+    const long tiles = (long)(n / BX) * (n / BY) * (n / BZ);
+    hipLaunchKernelGGL(k_lc_band, dim3((unsigned)tiles), dim3(256), 0, st, T, n, beta, out[0], out[1], out[2], row,
+                       accumulate);
     return hipGetLastError();
 }
 
@@ -708,8 +819,8 @@ hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t
 }
 
 template <int C>
-static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
-                            int accumulate, bool keep_z, hipStream_t st) {
+static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out_scale, float band,
+                            float* const out[3], long row, int accumulate, bool keep_z, hipStream_t st) {
     constexpr int NB = C / 16;
     hipError_t e = keep_z ? run_conv<8, NB, EPI_ZA>(A.x0, P.wb1, P.b1, A.z1, A.a1, nullptr, n, st)
                           : run_conv<8, NB, EPI_A>(A.x0, P.wb1, P.b1, A.a1, nullptr, nullptr, n, st);
@@ -717,6 +828,16 @@ static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out
     e = keep_z ? run_conv<C, NB, EPI_ZA>(A.a1, P.wb2, P.b2, A.z2, A.a2, nullptr, n, st)
                : run_conv<C, NB, EPI_A>(A.a1, P.wb2, P.b2, A.a2, nullptr, nullptr, n, st);
     if (e != hipSuccess) return e;
+    if (band != 0.0f) {  // dF into T (dense), then the band-pass weight into `out`
+        const long V = (long)n * n * n;
+        {
+            ProfScope ps(PROF_LC_MISC, st);
+            hipLaunchKernelGGL(k_lc_out<C>, dim3(blocks_for(V, 256)), dim3(256), 0, st, A.a2, P.w3, P.b3, out_scale,
+                               n, (long)n, A.t, A.t + V, A.t + 2 * V, 0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        return lc_band(A.t, n, band, out, row, accumulate, st);
+    }
     ProfScope ps(PROF_LC_MISC, st);
     hipLaunchKernelGGL(k_lc_out<C>, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, A.a2, P.w3, P.b3,
                        out_scale, n, row, out[0], out[1], out[2], accumulate);
@@ -725,34 +846,47 @@ static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out
 
 template <int C>
 static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row,
-                                   int n, const float in_scale[4], float out_scale, hipStream_t st) {
+                                   int n, const float in_scale[4], float out_scale, float band, float* t,
+                                   hipStream_t st) {
     constexpr int NB = C / 16;
     FieldSrc fs{d0, {g[0], g[1], g[2]}, row, {in_scale[1], in_scale[2], in_scale[3]}};
     hipError_t e = run_conv<8, NB, EPI_A, true>(nullptr, P.wb1, P.b1, a1, nullptr, nullptr, n, st, fs);
     if (e != hipSuccess) return e;
-    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale};
+    if (band != 0.0f) {  // dF stored in t, then added to the force meshes through the band-pass weight
+        const long V = (long)n * n * n;
+        OutDst od{{t, t + V, t + 2 * V}, (long)n, P.w3, P.b3, out_scale, 1};
+        e = run_conv<C, NB, EPI_OUT>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
+        if (e != hipSuccess) return e;
+        return lc_band(t, n, band, g, row, 1, st);
+    }
+    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale, 0};
     return run_conv<C, NB, EPI_OUT>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
 }
 
 hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row, int n,
-                             const float in_scale[4], float out_scale, hipStream_t st) {
-    if (P.C == 16) return forward_fields_c<16>(P, a1, d0, g, row, n, in_scale, out_scale, st);
-    if (P.C == 32) return forward_fields_c<32>(P, a1, d0, g, row, n, in_scale, out_scale, st);
+                             const float in_scale[4], float out_scale, float band, float* t, hipStream_t st) {
+    if (P.C == 16) return forward_fields_c<16>(P, a1, d0, g, row, n, in_scale, out_scale, band, t, st);
+    if (P.C == 32) return forward_fields_c<32>(P, a1, d0, g, row, n, in_scale, out_scale, band, t, st);
     return hipErrorInvalidValue;
 }
 
-hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float* const out[3], long row,
-                      int accumulate, bool keep_z, hipStream_t st) {
-    if (P.C == 16) return forward_c<16>(P, A, n, out_scale, out, row, accumulate, keep_z, st);
-    if (P.C == 32) return forward_c<32>(P, A, n, out_scale, out, row, accumulate, keep_z, st);
+hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale, float band, float* const out[3],
+                      long row, int accumulate, bool keep_z, hipStream_t st) {
+    if (P.C == 16) return forward_c<16>(P, A, n, out_scale, band, out, row, accumulate, keep_z, st);
+    if (P.C == 32) return forward_c<32>(P, A, n, out_scale, band, out, row, accumulate, keep_z, st);
     return hipErrorInvalidValue;
 }
 
 template <int C>
-static hipError_t backward_c(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, const float* ddf,
-                             hipStream_t st) {
+static hipError_t backward_c(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, float band,
+                             const float* ddf, hipStream_t st) {
     constexpr int NB = C / 16;
     const long V = (long)n * n * n;
+    if (band != 0.0f) {  // the band-pass weight is self-adjoint: upstream d_df + band B d_df
+        float* t3[3] = {A.t, A.t + V, A.t + 2 * V};
+        if (hipError_t e = lc_band(ddf, n, band, t3, (long)n, 0, st); e != hipSuccess) return e;
+        ddf = A.t;
+    }
     {
         ProfScope ps(PROF_LC_MISC, st);
         hipLaunchKernelGGL(k_lc_out_back<C>, dim3((unsigned)std::min<long>(blocks_for(V, 256), 1024)), dim3(256), 0,
@@ -765,10 +899,10 @@ static hipError_t backward_c(const LcParams& P, const LcActs& A, LcGrads& G, int
     return run_wgrad<8, NB>(A.dz1, A.x0, G.w1, G.b1, n, 4, st);
 }
 
-hipError_t lc_backward(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, const float* ddf,
-                       hipStream_t st) {
-    if (P.C == 16) return backward_c<16>(P, A, G, n, out_scale, ddf, st);
-    if (P.C == 32) return backward_c<32>(P, A, G, n, out_scale, ddf, st);
+hipError_t lc_backward(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, float band,
+                       const float* ddf, hipStream_t st) {
+    if (P.C == 16) return backward_c<16>(P, A, G, n, out_scale, band, ddf, st);
+    if (P.C == 32) return backward_c<32>(P, A, G, n, out_scale, band, ddf, st);
     return hipErrorInvalidValue;
 }
 

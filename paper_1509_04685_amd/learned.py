@@ -158,7 +158,7 @@ def load_net(path, training=False):
         doc = json.load(fh)
     net = LcNet(int(doc["channels"]), params=np.asarray(doc["params"], dtype=np.float32),
                 in_scale=doc["in_scale"], out_scale=doc["out_scale"], training=training)
-    net.set_scales(net.in_scale, net.out_scale, doc.get("out_scale_slope", 0.0))
+    net.set_scales(net.in_scale, net.out_scale, doc.get("out_scale_slope", 0.0), doc.get("out_band", 0.0))
     return net, doc
 
 

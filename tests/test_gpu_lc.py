@@ -117,6 +117,42 @@ def test_forward_matches_oracle(cola, n, c):
     assert np.allclose(acc.cpu().numpy() - base, got, rtol=0, atol=1e-5 * np.abs(got).max())
 
 
+@pytest.mark.parametrize("n,c", [(32, 16), (48, 32)])
+def test_band_weight_forward_and_backward_match_oracle(cola, n, c):
+    say(f"lc band weight n={n} C={c}")
+    band = 0.9
+    onet, flat = make_pair(c, seed=70 + c)
+    onet.band = band
+    delta, g = fields(n, seed=80 + n)
+    ref, cache = olc.forward(onet, delta, g)
+    net = cola.LcNet(c, params=flat, in_scale=onet.in_scale, out_scale=onet.out_scale)
+    net.set_scales(net.in_scale, net.out_scale, 0.0, band)
+    ws = cola.lc_workspace(n, c, 1, training=True)
+    got = cola.lc_forward(net, to_dev(delta), to_dev(g), ws, training=True).cpu().numpy()
+    assert rel_rms(got, ref) < 1.5e-2
+    assert cosine(got, ref) > 0.9995
+    d_df = f32(np.random.default_rng(90 + n).normal(size=(3, n, n, n)))
+    refg = olc.backward(onet, cache, d_df)
+    cola.lc_backward(net, to_dev(d_df), ws)
+    gg = net.grads.cpu().numpy().astype(np.float64)
+    rr = np.concatenate([r.ravel() for r in refg])
+    for lo, hi in ((0, refg[0].size), (refg[0].size + refg[1].size, refg[0].size + refg[1].size + refg[2].size)):
+        assert np.linalg.norm(gg[lo:hi] - rr[lo:hi]) / np.linalg.norm(rr[lo:hi]) < 2e-2
+    # accumulate mode through the band weight adds onto what is there
+    base = np.random.default_rng(6).normal(size=got.shape).astype(np.float32)
+    acc = to_dev(base)
+    cola.lc_forward(net, to_dev(delta), to_dev(g), ws, df=acc, accumulate=True)
+    assert np.allclose(acc.cpu().numpy() - base, got, rtol=0, atol=1e-5 * np.abs(got).max())
+    # a bias-only network gives a constant dF, which the band-pass leaves unchanged
+    zero = flat.copy()
+    zero[:-3] = 0.0
+    net0 = cola.LcNet(c, params=zero, in_scale=onet.in_scale, out_scale=onet.out_scale)
+    net0.set_scales(net0.in_scale, net0.out_scale, 0.0, band)
+    const = cola.lc_forward(net0, to_dev(delta), to_dev(g), ws).cpu().numpy()
+    for d in range(3):
+        assert np.allclose(const[d], zero[-3 + d] * onet.out_scale, rtol=1e-6, atol=1e-7)
+
+
 @pytest.mark.parametrize("n,c", [(16, 16), (32, 16), (16, 32), (32, 32)])
 def test_backward_matches_oracle(cola, n, c):
     say(f"lc backward n={n} C={c}")
@@ -251,13 +287,15 @@ def test_zero_network_step_equals_plain_step(cola):
     assert rel_rms(b.x.cpu().numpy(), a.x.cpu().numpy()) < 1e-6
 
 
-@pytest.mark.parametrize("n_real", [1, 2])
-def test_corrected_run_matches_oracle(cola, n_real):
-    say(f"corrected run vs oracle, n_real={n_real}")
+@pytest.mark.parametrize("n_real,band", [(1, 0.0), (2, 0.0), (2, 0.9)])
+def test_corrected_run_matches_oracle(cola, n_real, band):
+    say(f"corrected run vs oracle, n_real={n_real} band={band}")
     cosmo = cola.make_cosmology(**W.COSMOLOGY)
     prob = _small_problem(cola, n_real)
     onet, flat = make_pair(16, seed=7, in_scale=(0.25, 1.0, 1.0, 1.0), out_scale=0.5)
+    onet.band = band
     net = cola.LcNet(16, params=flat, in_scale=onet.in_scale, out_scale=onet.out_scale, training=False)
+    net.set_scales(net.in_scale, net.out_scale, 0.0, band)
     st = cola.ParticleState(prob)
     ws = cola.Workspace(prob)
     lws = cola.lc_workspace(16, 16, n_real)
