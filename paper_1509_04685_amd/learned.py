@@ -169,14 +169,16 @@ def max_error(k, pk, pk_ref, k_max=1.0):
 
 
 def calibrate_out_scale(net, cosmo, box, n_part, z_init, n_steps, seeds, factors, slopes=(0.0,), n_pk=None,
-                        k_max=1.0, log=None):
+                        k_max=1.0, log=None, bands=None):
     """Trajectory-level calibration of the output scale on training realizations.  For each factor
-    f and slope s the step uses out_scale * f * (1 + s (1 - a)) at a node of scale factor a; every
-    seed's corrected PM_grid = 1 realization is compared at the last node with the plain
-    PM_grid = 3 run of the same seed, by max over 0 < k < k_max of |P / P_3x - 1|, and the pair
-    with the smallest worst case wins.  A network fitted to noisy force residuals underestimates
-    the correction (regression dilution); this picks the scale on the training seeds only.  Sets
-    the best scale on the network and returns (out_scale, slope, table of (f, s, error))."""
+    f, slope s (and band weight b, when `bands` is given) the step uses out_scale * f * (1 + s (1 - a))
+    at a node of scale factor a (and the band-pass weight b); every seed's corrected PM_grid = 1
+    realization is compared at the last node with the plain PM_grid = 3 run of the same seed, by
+    max over 0 < k < k_max of |P / P_3x - 1|, and the combination with the smallest worst case
+    wins.  A network fitted to noisy force residuals underestimates the correction (regression
+    dilution); this picks the scale on the training seeds only.  Sets the best values on the
+    network and returns (out_scale, slope, table of (f, s, error)), or of (f, s, b, error) with
+    bands."""
     n_pk = n_pk or n_part * 3
     n_bins = n_pk // 2
     base = net.out_scale
@@ -184,16 +186,18 @@ def calibrate_out_scale(net, cosmo, box, n_part, z_init, n_steps, seeds, factors
     prob3 = make_problem(box, n_part, 3, z_init, n_steps)
     refs = [run_spectra(prob3, cosmo, s, (1.0,), n_pk, n_bins)[0] for s in seeds]
     table = []
-    for f in factors:
-        for sl in slopes:
-            net.set_scales(net.in_scale, base * f, sl)
-            worst = 0.0
-            for s, (k, p3) in zip(seeds, refs):
-                _, plc = run_spectra(prob1, cosmo, s, (1.0,), n_pk, n_bins, net=net)[0]
-                worst = max(worst, max_error(k, plc, p3, k_max))
-            table.append((float(f), float(sl), worst))
-            if log:
-                log(f"[calibrate] factor {f:.3f} slope {sl:+.2f}: worst max |P/P_3x - 1| {worst:.4f}")
-    best = min(table, key=lambda x: x[2])
-    net.set_scales(net.in_scale, base * best[0], best[1])
+    for b in (bands if bands is not None else (None,)):
+        for f in factors:
+            for sl in slopes:
+                net.set_scales(net.in_scale, base * f, sl, b)
+                worst = 0.0
+                for s, (k, p3) in zip(seeds, refs):
+                    _, plc = run_spectra(prob1, cosmo, s, (1.0,), n_pk, n_bins, net=net)[0]
+                    worst = max(worst, max_error(k, plc, p3, k_max))
+                table.append((float(f), float(sl), worst) if b is None else (float(f), float(sl), float(b), worst))
+                if log:
+                    tag = "" if b is None else f" band {b:.2f}"
+                    log(f"[calibrate] factor {f:.3f} slope {sl:+.2f}{tag}: worst max |P/P_3x - 1| {worst:.4f}")
+    best = min(table, key=lambda x: x[-1])
+    net.set_scales(net.in_scale, base * best[0], best[1], None if bands is None else best[2])
     return net.out_scale, net.out_scale_slope, table
