@@ -158,3 +158,65 @@ def test_fullsize_learned_sampled_voxels(cola):
     err = rel_rms(got, ref)
     say(f"  sampled relative RMS {err:.3e}")
     assert err < 2e-2
+
+
+def test_fullsize_multipoles_properties(cola):
+    """Multipoles on the 1024^3 analysis mesh after one step of the headline workload: the
+    real-space monopole is cola_power_spectrum's P(k); the real-space quadrupoles about the three
+    axes sum to zero mode by mode (L_2(mu_x) + L_2(mu_y) + L_2(mu_z) = 0); the redshift-space
+    monopole exceeds the real-space one at the largest scales (Kaiser)."""
+    cfg = W.CONFIGS["plain_256_768"]
+    say("full size: multipoles on 1024^3 after one step")
+    prob = cola.make_problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], cfg["z_init"], cfg["n_steps"])
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    st = cola.ParticleState(prob)
+    ws = cola.Workspace(prob, n_pk=1024)
+    cola.ic_2lpt(prob, cosmo, [cfg["seeds"][0]], st, ws)
+    cola.step(prob, cosmo, st, 1, ws)
+    a = float(cola.schedule_table(prob, cosmo)[1, 0])
+    n_bins = 400
+    p2s = []
+    for los in (0, 1, 2):
+        km, p0, p2, p4, nm = cola.power_multipoles(prob, cosmo, st, a, 1024, n_bins, ws, los=los,
+                                                   redshift_space=False)
+        p2s.append(p2.cpu().numpy()[0])
+    p0 = p0.cpu().numpy()[0]
+    km2, pk, nm2 = cola.power_spectrum(prob, cosmo, st, a, 1024, n_bins, ws)
+    pk = pk.cpu().numpy()[0]
+    sel = pk > 0
+    assert np.allclose(p0[sel], pk[sel], rtol=1e-10, atol=0)
+    total = np.abs(p2s[0] + p2s[1] + p2s[2])[sel]
+    assert np.all(total < 1e-9 * p0[sel])
+    red = cola.power_multipoles(prob, cosmo, st, a, 1024, n_bins, ws, los=2)
+    r0 = red[1].cpu().numpy()[0]
+    low = sel & (km2.cpu().numpy()[0] < 0.05)
+    ratio = r0[low].sum() / p0[low].sum()
+    say(f"  redshift/real monopole at k < 0.05: {ratio:.3f} (linear theory at f = 1: 1.867)")
+    assert 1.5 < ratio < 2.2
+
+
+def test_fullsize_pm_only_one_step(cola):
+    from scipy import fft as sfft
+    cfg = W.CONFIGS["plain_256_768"]
+    say("full size: PM-only ICs + one step (256^3 / 768^3)")
+    prob = cola.make_problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], cfg["z_init"], cfg["n_steps"], frame="pm")
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    st = cola.ParticleState(prob)
+    ws = cola.Workspace(prob)
+    cola.ic_2lpt(prob, cosmo, [cfg["seeds"][0]], st, ws)
+    cola.step(prob, cosmo, st, 1, ws)
+    x = st.x.cpu().numpy()
+    p = st.p.cpu().numpy()
+    say("full size: oracle PM-only step")
+    with sfft.set_workers(workers()):
+        op = ocola.Problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], cfg["z_init"], cfg["n_steps"])
+        oc = ocosmo.Cosmology(**W.COSMOLOGY)
+        sched = ocola.Schedule(op, oc)
+        ost = ocola.initial_state(op, oc, cfg["seeds"][0])
+        c1, c2 = ocola.lpt_momentum_coefficients(sched.a[0], oc.omega_m)
+        ost.p_res = c1 * ost.psi1 + c2 * ost.psi2
+        ocola.step_pm_only(ost, op, sched, 1)
+    err = rel_rms(x, ost.disp)
+    say(f"  relative RMS displacement {err:.2e}, momentum {rel_rms(p, ost.p_res):.2e}")
+    assert err < 1e-5
+    assert rel_rms(p, ost.p_res) < 1e-4
