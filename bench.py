@@ -82,6 +82,35 @@ def algorithmic_bytes(kind, tag, n_g, n_part):
     return table.get(kind)
 
 
+def floor_bytes(n_g, n_part):
+    """Algorithmic bytes of one PM step in the floor model (every FFT one read and one write of
+    the array, Green/gradient fused) and in the three-pass model (each 3D FFT three passes)."""
+    G = n_g ** 3
+    C = n_g * n_g * (n_g // 2 + 1)
+    N = n_part ** 3
+    dep, gkd = 12 * N + 4 * G, 12 * G + 72 * N
+    fft = (4 * G + 8 * C) + 3 * (8 * C + 4 * G)
+    return dep + fft + gkd, dep + 3 * fft + gkd
+
+
+def step_loop_bench(cola, torch, prob, cosmo, st, ws, seed, n_steps, reps=5):
+    """The step loop alone (ICs and P(k) outputs excluded): median over reps of the time from the
+    first force to the last node, timed with events."""
+    times = []
+    stream = torch.cuda.current_stream()
+    for _ in range(reps):
+        cola.ic_2lpt(prob, cosmo, [seed], st, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cola.step(prob, cosmo, st, n_steps - 1, ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
 def node_index(table, a_out):
     a = table[:, 0]
     j = int((a <= a_out * (1 + 1e-12)).sum()) - 1
@@ -555,6 +584,20 @@ def main():
     }
     if roofline is not None:
         roofline["copy_ceiling_gbs"] = copy_ceiling(cola, torch)
+    ms_loop = step_loop_bench(cola, torch, prob, cosmo, st, ws, seed, n_steps)
+    fb, fb3 = floor_bytes(n_g, n_part)
+    ms_node = ms_loop / n_steps
+    result["step_loop"] = {
+        "particle_steps_per_s": round(particles * n_steps / (ms_loop / 1e3), 1),
+        "ms_per_realization": round(ms_loop, 2), "ms_per_node": round(ms_node, 3),
+        "floor_bytes_per_step": fb, "three_pass_bytes_per_step": fb3,
+        "floor_ms_at_peak": round(fb / HBM_PEAK_GBS / 1e6, 3), "three_pass_ms_at_peak": round(fb3 / HBM_PEAK_GBS / 1e6, 3),
+        "floor_fraction": round(fb / HBM_PEAK_GBS / 1e6 / ms_node, 4),
+        "three_pass_fraction": round(fb3 / HBM_PEAK_GBS / 1e6 / ms_node, 4),
+        "what": "ICs and P(k) outputs excluded: the first force to the last node (40 forces, 39 drifts), "
+                "median of 5; fractions = step time at 8 TB/s of the floor / three-pass byte models over "
+                "the measured time per node"}
+    print(f"[bench] step loop: {json.dumps(result['step_loop'])}", file=sys.stderr, flush=True)
     if not args.no_multipoles:
         print("[bench] redshift-space multipoles on the 1024^3 analysis mesh", file=sys.stderr, flush=True)
         result["multipoles"] = multipoles_bench(cola, torch, prob, st, cfg)
