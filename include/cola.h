@@ -318,7 +318,9 @@ size_t cola_fof_workspace_bytes(int64_t n, double box, double link);
  * are taken modulo the box), 1 <= n < 2^31, 0 < link < box / 2.  group: device n int32, out:
  * group[i] = the smallest particle index in i's group (so group[i] <= i, and group[i] == i marks
  * a group's label).  group_size: device n int32, out: at a label r the number of members of its
- * group, 0 at every other index.  The result is deterministic.  Errors: COLA_ERR_INVALID_ARG,
+ * group, 0 at every other index.  The result is deterministic.  The time grows with the square
+ * of the particles per cell (cells of side >= link, about one particle per cell on average), so
+ * inputs that pile most particles into one small region are slow.  Errors: COLA_ERR_INVALID_ARG,
  * COLA_ERR_WORKSPACE_TOO_SMALL, COLA_ERR_HIP. */
 int cola_fof(const float* pos[3], int64_t n, double box, double link, int32_t* group, int32_t* group_size,
              void* ws, size_t ws_bytes, void* stream);

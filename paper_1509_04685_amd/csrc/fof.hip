@@ -22,6 +22,12 @@
 // non-root entry holds a smaller index than its own.  Walks therefore end, no cycle can form,
 // and the root of each tree is the smallest index in it.  Each failed compare-and-swap means
 // another thread completed a hook, and at most n - 1 hooks exist, so every thread exits.
+//
+// Cost: the link pass tests every pair in each cell and between forward neighbours, so its time
+// grows with the square of the particles per cell.  At the mean density there is about one
+// particle per cell; the densest cells of the z = 0 runs hold a few hundred.  Positions that
+// pile a large fraction of all particles into one cell (a degenerate input) make the pass
+// quadratic in n.
 
 #include <algorithm>
 #include <cmath>
