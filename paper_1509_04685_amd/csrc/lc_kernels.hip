@@ -152,8 +152,11 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
                     static_assert(C8 == 1, "field input has 4 channels (padded to 8)");
                     const long v = ((long)gx * n + gy) * n + gz;
                     const long o = ((long)gx * n + gy) * fs.row + gz;
-                    sh[hv] = make_uint4(fs.d0[v] | (f2bf(fs.g[0][o] * fs.s[0]) << 16),
-                                        f2bf(fs.g[1][o] * fs.s[1]) | (f2bf(fs.g[2][o] * fs.s[2]) << 16), 0u, 0u);
+                    // a channel with a zero input scale is not read (a density-only network)
+                    const float g0 = fs.s[0] != 0.0f ? fs.g[0][o] * fs.s[0] : 0.0f;
+                    const float g1 = fs.s[1] != 0.0f ? fs.g[1][o] * fs.s[1] : 0.0f;
+                    const float g2 = fs.s[2] != 0.0f ? fs.g[2][o] * fs.s[2] : 0.0f;
+                    sh[hv] = make_uint4(fs.d0[v] | (f2bf(g0) << 16), f2bf(g1) | (f2bf(g2) << 16), 0u, 0u);
                 } else {
                     const uint4* src = ing + (((long)gx * n + gy) * n + gz) * C8;
 #pragma unroll
