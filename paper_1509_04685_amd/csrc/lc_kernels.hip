@@ -91,7 +91,7 @@ constexpr int TV = TX * TY * TZ;
 
 __device__ __forceinline__ int wrap_halo(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-enum { EPI_ZA = 0, EPI_A = 1, EPI_DSILU = 2, EPI_OUT = 3 };
+enum { EPI_ZA = 0, EPI_A = 1, EPI_DSILU = 2, EPI_OUT = 3, EPI_OUT_STORE = 4 };
 
 // Inputs of the first layer taken straight from the step's fields (instead of a packed X0):
 // delta as BF16 (already scaled) and the three force meshes with `row` floats per row.
@@ -109,14 +109,14 @@ struct OutDst {
     const float* w3;
     const float* b3;
     float scale;
-    int overwrite;  // 1: store dF; 0: add it
 };
 
 // out[v][co] = sum_tap sum_ci W[co][tap][ci] in[v + d_tap][ci] + bias[co], then
 //   EPI_ZA: out = Z, out2 = silu(Z);  EPI_A: out = silu(Z);  EPI_DSILU: out = Z * silu'(prev[v][co]).
 // in: [V][CINP] BF16; W: [16 NB][27][CINP] BF16; out: [V][16 NB].  Block = 4 waves on a 4x4x16
 // tile, wave w computing the rows x0 + w, y0 + 0..3 (16 voxels along z each) for all outputs.
-//   EPI_OUT: the output layer, dF = (W3 silu(Z) + b3) * scale, added to the meshes of `od`.
+//   EPI_OUT: the output layer, dF = (W3 silu(Z) + b3) * scale, added to the meshes of `od`;
+//   EPI_OUT_STORE: the same, stored instead of added.
 // FIELDS (first layer only, CINP = 8): the halo is built from `fs` instead of `in`.
 template <int CINP, int NB, int EPI, bool FIELDS = false>
 __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
                     acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r].v, bf[b].v, acc[r][b], 0, 0, 0);
         }
         // lane holds voxels z0 + 4 kb + q of the row, output channel co = 16 b + m
-        if constexpr (EPI == EPI_OUT) {
+        if constexpr (EPI == EPI_OUT || EPI == EPI_OUT_STORE) {
             // A2 (rounded to BF16 as in the stored-activation path) goes to LDS as [voxel][COP + 1]
             // floats in the halo's space; then one thread per voxel forms the three outputs
             constexpr int SP = COP + 1;
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(256) k_conv3_mfma(const uint16_t* __restrict__
             }
             const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
             const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + z0 + lz;
-            if (od.overwrite) {
+            if constexpr (EPI == EPI_OUT_STORE) {
                 od.f[0][o] = y0 * od.scale;
                 od.f[1][o] = y1 * od.scale;
                 od.f[2][o] = y2 * od.scale;
@@ -857,12 +857,12 @@ static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16
     if (e != hipSuccess) return e;
     if (band != 0.0f) {  // dF stored in t, then added to the force meshes through the band-pass weight
         const long V = (long)n * n * n;
-        OutDst od{{t, t + V, t + 2 * V}, (long)n, P.w3, P.b3, out_scale, 1};
-        e = run_conv<C, NB, EPI_OUT>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
+        OutDst od{{t, t + V, t + 2 * V}, (long)n, P.w3, P.b3, out_scale};
+        e = run_conv<C, NB, EPI_OUT_STORE>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
         if (e != hipSuccess) return e;
         return lc_band(t, n, band, g, row, 1, st);
     }
-    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale, 0};
+    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale};
     return run_conv<C, NB, EPI_OUT>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
 }
 
