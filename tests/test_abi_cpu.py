@@ -141,3 +141,46 @@ def test_problem_rejects_bad_sampling_and_frame():
         for k, v in kw.items():
             setattr(p, k, v)
         assert LIB.cola_workspace_bytes(ctypes.byref(p), 0) == 0
+
+
+def test_fof_and_multipole_entry_points_validate_before_launch():
+    fake = ctypes.c_void_p(0x1000)
+    P3 = ctypes.c_void_p * 3
+    pos = P3(0x1000, 0x2000, 0x3000)
+    assert LIB.cola_fof_workspace_bytes(0, 100.0, 1.0) == 0
+    assert LIB.cola_fof_workspace_bytes(1000, -1.0, 1.0) == 0
+    nb = LIB.cola_fof_workspace_bytes(1000, 100.0, 1.0)
+    assert nb > 1000 * 20
+    # linking length of half the box or more, NULL outputs, small workspace
+    assert LIB.cola_fof(pos, 1000, 100.0, 50.0, fake, fake, fake, nb, None) == -1
+    assert LIB.cola_fof(pos, 1000, 100.0, 1.0, None, fake, fake, nb, None) == -1
+    assert LIB.cola_fof(pos, 1000, 100.0, 1.0, fake, fake, fake, 16, None) == -3
+    # catalogue: room for fewer haloes than n / n_min
+    com = P3(0x1000, 0x1000, 0x1000)
+    assert LIB.cola_fof_catalogue(pos, 1000, 100.0, fake, fake, 100, 1.0, 9, fake, fake, fake, com, fake, fake,
+                                  nb, None) == -1
+    # mass histogram: edges not increasing, too many bins, non-positive particle mass
+    edges = (ctypes.c_double * 3)(14.0, 13.0, 15.0)
+    assert LIB.cola_fof_mass_histogram(fake, 1000, 101, 1e12, edges, 2, fake, None) == -1
+    edges = (ctypes.c_double * 66)(*[12.0 + 0.1 * i for i in range(66)])
+    assert LIB.cola_fof_mass_histogram(fake, 1000, 101, 1e12, edges, 65, fake, None) == -1
+    assert LIB.cola_fof_mass_histogram(fake, 1000, 101, 0.0, edges, 3, fake, None) == -1
+    # multipoles: line of sight out of range, output off the state's node
+    p = prob()
+    st = cola.Particles()
+    for d in range(3):
+        st.x[d] = st.p[d] = st.psi1[d] = st.psi2[d] = 0x1000
+    st.node = 2
+    a2 = float(cola.schedule_table(p, COSMO)[2, 0])
+    args = (96, 48, fake, fake, fake, fake, fake, fake, 1 << 40, None)
+    assert LIB.cola_power_multipoles(ctypes.byref(p), ctypes.byref(COSMO), ctypes.byref(st), a2, 3, 1, *args) == -1
+    assert LIB.cola_power_multipoles(ctypes.byref(p), ctypes.byref(COSMO), ctypes.byref(st), a2 + 0.01, 2, 1,
+                                     *args) == -5
+
+
+def test_particle_mass_matches_oracle():
+    for box, n in ((768.0, 256), (1536.0, 512), (300.0, 96)):
+        got = cola.particle_mass(COSMO, box, n)
+        ref = ocosmo.particle_mass(ocosmo.Cosmology(), box, n)
+        assert got == pytest.approx(ref, rel=1e-14)
+    assert cola.particle_mass(COSMO, -1.0, 8) == 0.0
