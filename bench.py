@@ -415,10 +415,11 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
             label = f"{kname}@{tag}" if tag else kname
             print(f"[bench]   {name:10s} {label:22s} {kms:8.2f} ms/realization  {cnt:5d} launches  "
                   f"{kms / cnt:7.3f} ms/launch", file=sys.stderr, flush=True)
-        k = outs[-1][0].cpu().numpy()[0]
-        pk = outs[-1][1].cpu().numpy()[0]
+        by_a = {}
+        for (a, _), o, ref in zip(plan, outs, pk_plain3):
+            by_a[f"{a:.3f}"] = round(L.max_error(o[0].cpu().numpy()[0], o[1].cpu().numpy()[0], ref), 4)
         res[name] = {"ms_per_realization": round(ms, 2), "realizations_per_hour": round(3.6e6 / ms, 1),
-                     "max_pk_error_k_lt_1": round(L.max_error(k, pk, pk_plain3), 4)}
+                     "max_pk_error_k_lt_1": max(by_a.values()), "max_pk_error_k_lt_1_by_a": by_a}
         if halo3 is not None:  # the state now holds this form's z = 0 particles
             h = haloes(cola, torch, prob, st, cosmo, c["box"], c["n_part"])
             worst, total = abundance_error(h["counts"], halo3["counts"])
@@ -438,12 +439,15 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
     res["network"] = (f"C={net.channels}: two 3x3x3 conv layers + SiLU, 1x1x1 output, input {inputs}; BF16 matrix "
                       f"cores, FP32 accumulation; trained on 128^3/384^3 pairs in 384 h^-1 Mpc (seeds 3001-3006), "
                       f"validation loss {doc['val_loss_initial']:.3f} -> {doc['val_loss_trained']:.3f}; output "
-                      f"scale calibrated on training seeds {seeds[0]}-{seeds[-1]}: factor "
+                      f"scale calibrated on training seeds {seeds[0]}-{seeds[-1]} at every output: factor "
                       f"{net.out_scale / doc.get('out_scale_fitted', net.out_scale):.2f}, slope "
-                      f"{net.out_scale_slope:+.2f} in (1 - a); evaluation seed {c['seeds'][0]} held out")
+                      f"{net.out_scale_slope:+.2f} in (1 - a)"
+                      + (f", schedule {[round(v, 3) for v in net.schedule[1]]} at a = {[round(v, 3) for v in net.schedule[0]]}"
+                         if net.schedule else "")
+                      + f"; evaluation seed {c['seeds'][0]} held out")
     res["workload"] = (f"{lname}: {c['n_part']}^3 particles, {c['n_part']}^3 mesh (PM_grid 1), box {c['box']:g}, "
                        f"40 nodes from z=19, seed {c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = "
-                       f"max over 0<k<1 h/Mpc of |P/P_plain3x - 1| at z=0; haloes: FoF b=0.2 at z=0, "
+                       f"max over 0<k<1 h/Mpc and over the outputs of |P/P_plain3x - 1| (by_a: per output); haloes: FoF b=0.2 at z=0, "
                        f"Warren masses, > 100 particles, 0.2 dex bins; halo error = max over bins with >= 20 "
                        f"plain-3x haloes of |N/N_plain3x - 1|")
     return res
@@ -620,7 +624,7 @@ def main():
         print(f"[bench] stepping: {json.dumps(result['stepping'])}", file=sys.stderr, flush=True)
     if not args.no_learned:
         print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
-        result["learned"] = learned_bench(cola, torch, args.workload, outs[-1][1].cpu().numpy()[0], a_outs, n_pk,
+        result["learned"] = learned_bench(cola, torch, args.workload, [o[1].cpu().numpy()[0] for o in outs], a_outs, n_pk,
                                           n_bins, ms_per_step, reps=2, halo3=halo3)
         print(f"[bench] learned: {json.dumps(result['learned'])}", file=sys.stderr, flush=True)
     if not args.no_ensemble:

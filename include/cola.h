@@ -227,6 +227,12 @@ typedef struct {
                             K the periodic [1, 2, 1] / 4 smoothing along each mesh axis (a mode
                             is multiplied by 1 + beta c (1 - c), c = prod_d cos^2(pi m_d / n));
                             0 = off.  Applied in every entry point, backward included          */
+    int32_t n_knots;     /* 0, or 2..8: in the step the scale is further multiplied by the
+                            piecewise-linear interpolation of (knot_a[i], knot_v[i]) at the
+                            node's a (knot_a increasing; constant beyond the end knots).  Lets
+                            a calibration set the correction's strength per epoch              */
+    float knot_a[8];
+    float knot_v[8];
     float* params;       /* device, cola_lc_param_count(C) floats, flat in the order
                             w1 (C,4,27) b1 (C) w2 (C,C,27) b2 (C) w3 (3,C) b3 (3), C order       */
     float* grads;        /* device, same size: cola_lc_backward adds into it, cola_lc_adam

@@ -377,6 +377,23 @@ class LcNet:
     def out_band(self):
         return float(self.c.out_band)
 
+    def set_schedule(self, knot_a=None, knot_v=None):
+        """Piecewise-linear multiplier of the step's output scale over a (None: none)."""
+        if knot_a is None:
+            self.c.n_knots = 0
+            return
+        if len(knot_a) != len(knot_v) or not 2 <= len(knot_a) <= 8:
+            raise ValueError("2 to 8 knots with one value each")
+        self.c.n_knots = len(knot_a)
+        for i, (a, v) in enumerate(zip(knot_a, knot_v)):
+            self.c.knot_a[i] = float(a)
+            self.c.knot_v[i] = float(v)
+
+    @property
+    def schedule(self):
+        n = int(self.c.n_knots)
+        return ([float(self.c.knot_a[i]) for i in range(n)], [float(self.c.knot_v[i]) for i in range(n)]) if n else None
+
     @property
     def in_scale(self):
         return tuple(float(self.c.in_scale[i]) for i in range(4))

@@ -159,7 +159,25 @@ struct LcHook {
     float out_scale;
     float out_scale_slope;
     float out_band;
-    float scale_at(double a) const { return (float)(out_scale * (1.0 + out_scale_slope * (1.0 - a))); }
+    int n_knots;
+    float knot_a[8], knot_v[8];
+    // out_scale (1 + slope (1 - a)), times the knot schedule at a when there is one
+    float scale_at(double a) const {
+        double s = out_scale * (1.0 + out_scale_slope * (1.0 - a));
+        if (n_knots >= 2) {
+            double v = knot_v[0];
+            if (a >= knot_a[n_knots - 1]) {
+                v = knot_v[n_knots - 1];
+            } else if (a > knot_a[0]) {
+                int i = 0;
+                while (i + 2 < n_knots && a >= knot_a[i + 1]) ++i;
+                const double t = (a - knot_a[i]) / ((double)knot_a[i + 1] - knot_a[i]);
+                v = knot_v[i] + t * ((double)knot_v[i + 1] - knot_v[i]);
+            }
+            s *= v;
+        }
+        return (float)s;
+    }
 };
 
 // Density, forward transform and force meshes for the current positions.  Force meshes end up
@@ -419,6 +437,11 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
     h.out_scale = net->out_scale;
     h.out_scale_slope = net->out_scale_slope;
     h.out_band = net->out_band;
+    h.n_knots = net->n_knots;
+    for (int i = 0; i < 8; ++i) {
+        h.knot_a[i] = net->knot_a[i];
+        h.knot_v[i] = net->knot_v[i];
+    }
     return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, &h);
 }
 

@@ -56,6 +56,11 @@ int lc_check_net(const cola_lc_net* net, bool training) {
         if (!std::isfinite(net->in_scale[i])) return COLA_ERR_INVALID_ARG;
     if (!std::isfinite(net->out_scale) || !std::isfinite(net->out_scale_slope) || !std::isfinite(net->out_band))
         return COLA_ERR_INVALID_ARG;
+    if (net->n_knots != 0 && (net->n_knots < 2 || net->n_knots > 8)) return COLA_ERR_INVALID_ARG;
+    for (int i = 0; i < net->n_knots; ++i) {
+        if (!std::isfinite(net->knot_a[i]) || !std::isfinite(net->knot_v[i])) return COLA_ERR_INVALID_ARG;
+        if (i > 0 && !(net->knot_a[i] > net->knot_a[i - 1])) return COLA_ERR_INVALID_ARG;
+    }
     if (training && (!net->grads || !net->adam_m || !net->adam_v)) return COLA_ERR_INVALID_ARG;
     return COLA_OK;
 }

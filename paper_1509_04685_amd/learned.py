@@ -159,6 +159,8 @@ def load_net(path, training=False):
     net = LcNet(int(doc["channels"]), params=np.asarray(doc["params"], dtype=np.float32),
                 in_scale=doc["in_scale"], out_scale=doc["out_scale"], training=training)
     net.set_scales(net.in_scale, net.out_scale, doc.get("out_scale_slope", 0.0), doc.get("out_band", 0.0))
+    sched = doc.get("schedule")
+    net.set_schedule(*(sched if sched else (None, None)))
     return net, doc
 
 
@@ -169,31 +171,32 @@ def max_error(k, pk, pk_ref, k_max=1.0):
 
 
 def calibrate_out_scale(net, cosmo, box, n_part, z_init, n_steps, seeds, factors, slopes=(0.0,), n_pk=None,
-                        k_max=1.0, log=None, bands=None):
+                        k_max=1.0, log=None, bands=None, a_outs=(1.0,)):
     """Trajectory-level calibration of the output scale on training realizations.  For each factor
     f, slope s (and band weight b, when `bands` is given) the step uses out_scale * f * (1 + s (1 - a))
     at a node of scale factor a (and the band-pass weight b); every seed's corrected PM_grid = 1
-    realization is compared at the last node with the plain PM_grid = 3 run of the same seed, by
-    max over 0 < k < k_max of |P / P_3x - 1|, and the combination with the smallest worst case
-    wins.  A network fitted to noisy force residuals underestimates the correction (regression
-    dilution); this picks the scale on the training seeds only.  Sets the best values on the
-    network and returns (out_scale, slope, table of (f, s, error)), or of (f, s, b, error) with
-    bands."""
+    realization is compared with the plain PM_grid = 3 run of the same seed at every output scale
+    factor in a_outs, by max over 0 < k < k_max of |P / P_3x - 1|, and the combination with the
+    smallest worst case over seeds and outputs wins.  A network fitted to noisy force residuals
+    underestimates the correction (regression dilution); this picks the scale on the training
+    seeds only.  Sets the best values on the network and returns (out_scale, slope, table of
+    (f, s, error)), or of (f, s, b, error) with bands."""
     n_pk = n_pk or n_part * 3
     n_bins = n_pk // 2
     base = net.out_scale
     prob1 = make_problem(box, n_part, 1, z_init, n_steps)
     prob3 = make_problem(box, n_part, 3, z_init, n_steps)
-    refs = [run_spectra(prob3, cosmo, s, (1.0,), n_pk, n_bins)[0] for s in seeds]
+    refs = [run_spectra(prob3, cosmo, s, a_outs, n_pk, n_bins) for s in seeds]
     table = []
     for b in (bands if bands is not None else (None,)):
         for f in factors:
             for sl in slopes:
                 net.set_scales(net.in_scale, base * f, sl, b)
                 worst = 0.0
-                for s, (k, p3) in zip(seeds, refs):
-                    _, plc = run_spectra(prob1, cosmo, s, (1.0,), n_pk, n_bins, net=net)[0]
-                    worst = max(worst, max_error(k, plc, p3, k_max))
+                for s, ref in zip(seeds, refs):
+                    got = run_spectra(prob1, cosmo, s, a_outs, n_pk, n_bins, net=net)
+                    for (k, p3), (_, plc) in zip(ref, got):
+                        worst = max(worst, max_error(k, plc, p3, k_max))
                 table.append((float(f), float(sl), worst) if b is None else (float(f), float(sl), float(b), worst))
                 if log:
                     tag = "" if b is None else f" band {b:.2f}"
@@ -201,3 +204,49 @@ def calibrate_out_scale(net, cosmo, box, n_part, z_init, n_steps, seeds, factors
     best = min(table, key=lambda x: x[-1])
     net.set_scales(net.in_scale, base * best[0], best[1], None if bands is None else best[2])
     return net.out_scale, net.out_scale_slope, table
+
+
+def calibrate_schedule(net, cosmo, box, n_part, z_init, n_steps, seeds, knot_a, a_outs=(1.0,), n_pk=None,
+                       k_max=1.0, rounds=5, log=None):
+    """Refines the step's output scale into a piecewise-linear schedule over a: starting from the
+    network's out_scale (1 + slope (1 - a)) sampled at the knots, each knot value in turn is
+    multiplied by a few factors and the change is kept when the worst max |P / P_3x - 1| over the
+    training seeds and outputs a_outs drops (coordinate descent; coarse factors first, then fine).
+    Sets the schedule on the network (with the slope folded in) and returns (knot values, worst
+    error, log of accepted moves)."""
+    n_pk = n_pk or n_part * 3
+    n_bins = n_pk // 2
+    prob1 = make_problem(box, n_part, 1, z_init, n_steps)
+    prob3 = make_problem(box, n_part, 3, z_init, n_steps)
+    refs = [run_spectra(prob3, cosmo, s, a_outs, n_pk, n_bins) for s in seeds]
+    knot_a = [float(a) for a in knot_a]
+    vals = [1.0 + net.out_scale_slope * (1.0 - a) for a in knot_a]
+    net.set_scales(net.in_scale, net.out_scale, 0.0)
+
+    def worst(v):
+        net.set_schedule(knot_a, v)
+        w = 0.0
+        for s, ref in zip(seeds, refs):
+            got = run_spectra(prob1, cosmo, s, a_outs, n_pk, n_bins, net=net)
+            for (k, p3), (_, plc) in zip(ref, got):
+                w = max(w, max_error(k, plc, p3, k_max))
+        return w
+
+    best = worst(vals)
+    moves = []
+    for rnd in range(rounds):
+        improved = False
+        for i in range(len(knot_a)):
+            for m in ((0.8, 0.9, 1.1, 1.25) if rnd < 2 else (0.93, 0.97, 1.03, 1.07)):
+                trial = list(vals)
+                trial[i] *= m
+                w = worst(trial)
+                if w < best - 1e-5:
+                    best, vals, improved = w, trial, True
+                    moves.append((rnd, i, m, w))
+                    if log:
+                        log(f"[schedule] round {rnd} knot a={knot_a[i]:.2f} x{m}: worst {w:.4f}")
+        if not improved and rnd >= 2:
+            break
+    net.set_schedule(knot_a, vals)
+    return vals, best, moves

@@ -9,8 +9,10 @@ density only (the force channels' input scales are zero): its response to a long
 is then a local stencil of the density, of order k^2 g, so it cannot rescale the large-scale force
 and bias the growth of large scales (with the force as input it did, by 1-2 % in P(k) at
 k ~ 0.2-0.3 h/Mpc).  After the force-level fit, the output scale is calibrated at trajectory level
-on training seeds 3001-3004 (the factor and slope that minimise the worst max |P / P_3x - 1| for
-k < 1 at z = 0).  Optional on-policy rounds (--onpolicy-rounds): the calibrated network runs the
+on training seeds 3001-3004 against the plain 3x runs at every output (a = 0.5, 2/3, 1): first a
+factor and slope on a grid, then a piecewise-linear schedule over a (seven knots, coordinate
+descent), each minimising the worst max |P / P_3x - 1| for k < 1 over seeds and outputs.
+Optional on-policy rounds (--onpolicy-rounds): the calibrated network runs the
 coarse form on the training seeds, the positions it visits get fine-mesh targets, the network is
 fine-tuned on the old and new samples together and calibrated again.  The weights file holds the flat
 FP32 parameters in the library's order, the input and output scales (fitted and calibrated), the
@@ -30,8 +32,9 @@ RECIPE = dict(box=384.0, n_part=128, pm_fine=3, n_steps=40, z_init=19.0,
               train_seeds=(3001, 3002, 3003, 3004, 3005, 3006), val_seeds=(3007,),
               train_nodes=tuple(range(4, 40, 2)), val_nodes=tuple(range(5, 40, 6)),
               iters=3000, batch=2, lr=3e-3, lr_decay=0.3, chunks=5, init_seed=1, force_input=False,
-              calib_seeds=(3001, 3002, 3003, 3004), calib_factors=tuple(round(0.8 + 0.05 * i, 2) for i in range(19)),
-              calib_slopes=tuple(round(0.2 * i, 1) for i in range(9)),
+              calib_seeds=(3001, 3002, 3003, 3004), calib_factors=tuple(round(0.3 + 0.1 * i, 2) for i in range(14)),
+              calib_slopes=tuple(round(-0.8 + 0.2 * i, 1) for i in range(9)),
+              calib_a=(0.5, 2.0 / 3.0, 1.0), knot_a=(0.05, 0.2, 0.35, 0.5, 0.65, 0.8, 1.0), knot_rounds=5,
               onpolicy_rounds=0, onpolicy_iters=1500, onpolicy_lr=1e-3,
               onpolicy_factors=tuple(round(0.9 + 0.05 * i, 2) for i in range(13)),
               onpolicy_slopes=tuple(round(-0.2 + 0.2 * i, 1) for i in range(6)))
@@ -59,7 +62,8 @@ def train(channels, recipe=RECIPE, log=print):
     fitted = net.out_scale
     v1 = tr.evaluate(val)
     best, slope, table = L.calibrate_out_scale(net, cosmo, r["box"], r["n_part"], r["z_init"], r["n_steps"],
-                                               r["calib_seeds"], r["calib_factors"], r["calib_slopes"], log=log)
+                                               r["calib_seeds"], r["calib_factors"], r["calib_slopes"], log=log,
+                                               a_outs=r["calib_a"])
     log(f"[train_lc] output scale {fitted:.5g} -> {best:.5g} (factor {best / fitted:.3f}), slope {slope:+.2f}; "
         f"worst training-seed error {min(t[2] for t in table):.4f}")
     for rd in range(r["onpolicy_rounds"]):
@@ -76,10 +80,16 @@ def train(channels, recipe=RECIPE, log=print):
         del onp, data
         best, slope, table = L.calibrate_out_scale(net, cosmo, r["box"], r["n_part"], r["z_init"], r["n_steps"],
                                                    r["calib_seeds"], r["onpolicy_factors"], r["onpolicy_slopes"],
-                                                   log=log)
+                                                   log=log, a_outs=r["calib_a"])
         log(f"[train_lc] on-policy round {rd}: factor {best / fitted:.3f}, slope {slope:+.2f}; worst training-seed "
             f"error {min(t[2] for t in table):.4f}")
     del samples, val
+    if r["knot_rounds"] > 0:
+        vals, worst, _ = L.calibrate_schedule(net, cosmo, r["box"], r["n_part"], r["z_init"], r["n_steps"],
+                                              r["calib_seeds"], r["knot_a"], a_outs=r["calib_a"],
+                                              rounds=r["knot_rounds"], log=log)
+        log(f"[train_lc] schedule {[round(v, 3) for v in vals]} at a = {list(r['knot_a'])}: worst training-seed "
+            f"error {worst:.4f}")
     return net, v0, v1, fitted, table
 
 
@@ -97,6 +107,7 @@ def main():
     net, v0, v1, fitted, table = train(args.channels, recipe=recipe, log=lambda m: print(m, flush=True))
     doc = dict(channels=net.channels, in_scale=list(net.in_scale), out_scale=net.out_scale,
                out_scale_slope=net.out_scale_slope, out_scale_fitted=fitted, calibration=table,
+               schedule=net.schedule,
                val_loss_initial=v0, val_loss_trained=v1, recipe=recipe,
                params=[float(x) for x in net.get_params()])
     with open(out, "w") as fh:

@@ -316,3 +316,38 @@ def test_corrected_run_matches_oracle(cola, n_real, band):
         say(f"  seed {seed}: err {err:.2e}, effect of the correction {effect:.2e}")
         assert err < 2e-3
         assert effect > 10 * 2e-3
+
+
+def test_schedule_equals_node_by_node_scales(cola):
+    """A knot schedule in one call equals stepping one node at a time with the interpolated scale
+    set by hand (knots constant below the first force nodes so both runs start alike)."""
+    say("output-scale schedule")
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    prob = cola.make_problem(64.0, 16, 1, 19.0, 6)
+    a = cola.schedule_table(prob, cosmo)[:, 0]
+    onet, flat = make_pair(16, seed=9, in_scale=(0.25, 1.0, 1.0, 1.0), out_scale=0.5)
+    knot_a, knot_v = [0.3, 0.6, 0.9], [1.5, 0.7, 1.2]
+    assert a[1] < knot_a[0]
+    lws = cola.lc_workspace(16, 16, 1)
+    xs = []
+    for mode in ("schedule", "by hand"):
+        net = cola.LcNet(16, params=flat, in_scale=onet.in_scale, out_scale=onet.out_scale, training=False)
+        st = cola.ParticleState(prob)
+        ws = cola.Workspace(prob)
+        cola.ic_2lpt(prob, cosmo, [5], st, ws)
+        if mode == "schedule":
+            net.set_schedule(knot_a, knot_v)
+            cola.step_lc(prob, cosmo, st, 5, net, lws, ws)
+        else:
+            for j in range(1, 6):
+                net.set_scales(net.in_scale, onet.out_scale * float(np.interp(a[j], knot_a, knot_v)), 0.0)
+                cola.step_lc(prob, cosmo, st, j, net, lws, ws)
+        xs.append(st.x.cpu().numpy())
+    assert rel_rms(xs[0], xs[1]) < 1e-6
+    # the schedule changes the run
+    net = cola.LcNet(16, params=flat, in_scale=onet.in_scale, out_scale=onet.out_scale, training=False)
+    st = cola.ParticleState(prob)
+    ws = cola.Workspace(prob)
+    cola.ic_2lpt(prob, cosmo, [5], st, ws)
+    cola.step_lc(prob, cosmo, st, 5, net, lws, ws)
+    assert rel_rms(st.x.cpu().numpy(), xs[0]) > 1e-4
