@@ -12,7 +12,9 @@
 // inverse plan starts with the forward plan's last radix.
 //
 // Twiddles come from a table tw[m] = exp(-2 pi i m / (n * tw_stride)) built in float64 on the
-// device; the inverse uses conjugates.  Transforms are unnormalised.
+// device; the inverse uses conjugates.  Transforms are unnormalised.  Kernels built on a static
+// plan read the table from a copy in LDS (kTwN entries): read from global memory, the twiddles
+// cost a quarter of a pass's time on the 768-point lines.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -251,6 +253,8 @@ template <int R>
 struct DynLine {
     static constexpr int kR = R;
     static constexpr bool kStatic = false;
+    static constexpr int kN = 0;
+    static constexpr int kTwN = 0;  // reads the table in global memory
     FftPlan p;
     int les;
     __device__ int T() const { return p.T; }
@@ -295,6 +299,18 @@ constexpr int radices_ns(const Radices& s, int st) {
     return ns;
 }
 
+// Entries of a twiddle table with stride tws that a plan reads: its largest index + 1.
+constexpr int radices_tw_entries(const Radices& s, int n, int tws) {
+    int mx = 0, ns = 1;
+    for (int i = 0; i < s.nst; ++i) {
+        const int r = s.r[i];
+        const int m = (r - 1) * (n / (ns * r)) * tws * (ns - 1);
+        if (m > mx) mx = m;
+        ns *= r;
+    }
+    return mx + 1;
+}
+
 constexpr bool static_plan_ok(int n, int R) {
     if (R < 2 || n % R) return false;
     Radices s = static_radices(n, R, false);
@@ -313,8 +329,10 @@ struct StatLine {
     static_assert(static_plan_ok(N, R), "no static plan for this line length and R");
     static constexpr int kR = R;
     static constexpr bool kStatic = true;
+    static constexpr int kN = N;
     static constexpr int kT = N / R;
     static constexpr Radices kRad = static_radices(N, R, REV);
+    static constexpr int kTwN = radices_tw_entries(kRad, N, TWS);  // staged in LDS by the kernels
     static constexpr int kFirst = kRad.r[0];
     static constexpr int kLast = kRad.r[kRad.nst - 1];
     __device__ static constexpr int T() { return kT; }

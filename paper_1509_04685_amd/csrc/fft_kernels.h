@@ -52,6 +52,32 @@ __device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& b
 
 __device__ __forceinline__ int signed_mode(int e, int n) { return e < n / 2 ? e : e - n; }
 
+// ------------------------------------------------------------------ twiddles in LDS
+
+// Table entries a kernel stages at the front of its LDS (0: it reads the global table).  The z
+// passes' split steps also read entries 0..M-1.
+template <class LE>
+constexpr int z_tw_entries() {
+    return LE::kTwN > 0 ? (LE::kTwN > LE::kN ? LE::kTwN : LE::kN) : 0;
+}
+template <class LF, class LI>
+constexpr int pair_tw_entries() {
+    return LF::kTwN > LI::kTwN ? LF::kTwN : LI::kTwN;
+}
+constexpr size_t tw_lds_bytes(int entries) { return (size_t)entries * sizeof(float2); }
+
+// Copies the first CNT table entries to lds[0..CNT) and returns the table to read (the caller
+// places a barrier before the first read); CNT = 0 returns the global table.
+template <int CNT>
+__device__ __forceinline__ const float2* stage_twiddles(const float2* tw, float2* lds) {
+    if constexpr (CNT == 0) {
+        return tw;
+    } else {
+        for (int i = threadIdx.x; i < CNT; i += blockDim.x) lds[i] = tw[i];
+        return lds;
+    }
+}
+
 // ------------------------------------------------------------------ z pass: real -> half complex
 
 // Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
@@ -62,6 +88,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
                                                    long nrows, LE eng, const float2* tw,
                                                    float pa, float pb) {
     constexpr int R = LE::kR;
+    constexpr int TW = z_tw_entries<LE>();
     extern __shared__ float2 lds[];
     const int T = eng.T(), M = eng.n();
     const int line = threadIdx.x / T, t = threadIdx.x % T;
@@ -69,7 +96,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
     const bool active = row < nrows;
     in += (long)blockIdx.y * in_bstride;
     out += (long)blockIdx.y * out_bstride;
-    float2* L = lds + line * (M + 1);
+    float2* L = lds + TW + line * (M + 1);
     float2 v[R];
     if (active) {
         const float2* src = reinterpret_cast<const float2*>(in + row * in_row);
@@ -78,7 +105,9 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
             v[q] = make_float2(fmaf(z.x, pa, pb), fmaf(z.y, pa, pb));
         });
     }
-    eng.template run<false>(v, L, t, tw, active);
+    const float2* twl = stage_twiddles<TW>(tw, lds);
+    if constexpr (TW > 0) __syncthreads();
+    eng.template run<false>(v, L, t, twl, active);
     if (active) eng.last(t, [&](int q, int e) { L[e] = v[q]; });
     __syncthreads();
     if (!active) return;
@@ -91,7 +120,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
         float2 e = cscale(cadd(zk, zc), 0.5f);
         float2 d = csub(zk, zc);
         float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
-        dst[k] = cadd(e, cmul(tw[k], o));
+        dst[k] = cadd(e, cmul(twl[k], o));
     }
     if (t == 0) {
         float2 z0 = L[0];
@@ -109,6 +138,7 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row
                                                    long nrows, LE eng, const float2* tw,
                                                    float kf, float scale) {
     constexpr int R = LE::kR;
+    constexpr int TW = z_tw_entries<LE>();
     extern __shared__ float2 lds[];
     const int T = eng.T(), M = eng.n();
     const int line = threadIdx.x / T, t = threadIdx.x % T;
@@ -116,7 +146,8 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row
     const bool active = row < nrows;
     in += (long)blockIdx.y * in_bstride;
     out += (long)blockIdx.y * out_bstride;
-    float2* L = lds + line * (M + 1);
+    float2* L = lds + TW + line * (M + 1);
+    const float2* twl = stage_twiddles<TW>(tw, lds);  // visible after the barrier below
     if (active) {
         // issue all R loads of this thread before the first LDS store
         const float2* src = in + row * in_row;
@@ -142,12 +173,12 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row
         eng.first(t, [&](int q, int k) {
             float2 xk = L[k];
             float2 xc = cconj(L[M - k]);
-            float2 d = cmul(cconj(tw[k]), csub(xk, xc));
+            float2 d = cmul(cconj(twl[k]), csub(xk, xc));
             v[q] = make_float2(xk.x + xc.x - d.y, xk.y + xc.y + d.x);  // (xk + xc) + i d
         });
     }
     __syncthreads();
-    eng.template run<true>(v, L, t, tw, active);
+    eng.template run<true>(v, L, t, twl, active);
     if (!active) return;
     float2* dst = reinterpret_cast<float2*>(out + row * out_row);
     eng.last(t, [&](int q, int e) { dst[e] = v[q]; });
@@ -159,6 +190,7 @@ template <class LE, int TK, bool INV>
 __global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, ColGeom cg, LE eng,
                                                   const float2* tw) {
     constexpr int R = LE::kR;
+    constexpr int TW = LE::kTwN;
     extern __shared__ float2 lds[];
     int t, c;
     uint32_t base;
@@ -167,7 +199,9 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, Co
     const uint32_t es = (uint32_t)cg.es;
     float2 v[R];
     if (active) eng.first(t, [&](int q, int e) { v[q] = data[base + (uint32_t)e * es]; });
-    eng.template run<INV>(v, lds + threadIdx.x % (TK > 0 ? TK : cg.tk), t, tw, active);
+    const float2* twl = stage_twiddles<TW>(tw, lds);
+    if constexpr (TW > 0) __syncthreads();
+    eng.template run<INV>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
     if (!active) return;
     eng.last(t, [&](int q, int e) { data[base + (uint32_t)e * es] = v[q]; });
 }
@@ -181,6 +215,7 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
                                                      ColGeom cg, LF ef, LI ei, const float2* tw, float kf,
                                                      float gscale) {
     constexpr int R = LF::kR;
+    constexpr int TW = pair_tw_entries<LF, LI>();
     extern __shared__ float2 lds[];
     int t, c;
     uint32_t base;
@@ -193,23 +228,25 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
     const int n = ef.n();
     const int yrow = c / cg.nzp;
     const int my = signed_mode(yrow, n), mz = c - yrow * cg.nzp;
-    float2* L = lds + threadIdx.x % (TK > 0 ? TK : cg.tk);
+    float2* L = lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk);
     float2 v[R], h[R];
     if (active) ef.first(t, [&](int q, int e) { v[q] = S[base + (uint32_t)e * es]; });
-    ef.template run<false>(v, L, t, tw, active);
+    const float2* twl = stage_twiddles<TW>(tw, lds);
+    if constexpr (TW > 0) __syncthreads();
+    ef.template run<false>(v, L, t, twl, active);
     const float kyz2 = (float)(my * my + mz * mz);
     const float g0 = gscale / (kf * kf);
     ef.last(t, [&](int q, int e) {
         int mx = signed_mode(e, n);
         float m2 = (float)(mx * mx) + kyz2;
-        float gk = (m2 > 0.0f) ? g0 * __frcp_rn(m2) : 0.0f;
+        float gk = (m2 > 0.0f) ? g0 * __builtin_amdgcn_rcpf(m2) : 0.0f;  // hardware reciprocal, 1 ulp
         v[q] = cscale(v[q], gk);
         float kx = (2 * mx == -n) ? 0.0f : kf * (float)mx;
         h[q] = make_float2(-kx * v[q].y, kx * v[q].x);  // i k_x V
     });
-    ei.template run<true>(v, L, t, tw, active);
+    ei.template run<true>(v, L, t, twl, active);
     if (active) ei.last(t, [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
-    ei.template run<true>(h, L, t, tw, active);
+    ei.template run<true>(h, L, t, twl, active);
     if (!active) return;
     ei.last(t, [&](int q, int e) { B[base + (uint32_t)e * es] = h[q]; });
 }
@@ -220,6 +257,7 @@ template <class LE, int TK>
 __global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long bstride, ColGeom cg, LE eng,
                                                      const float2* tw, float kf) {
     constexpr int R = LE::kR;
+    constexpr int TW = LE::kTwN;
     extern __shared__ float2 lds[];
     int t, c;
     uint32_t base;
@@ -229,7 +267,7 @@ __global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long 
     S += boff;
     const uint32_t es = (uint32_t)cg.es;
     const int n = eng.n();
-    float2* L = lds + threadIdx.x % (TK > 0 ? TK : cg.tk);
+    float2* L = lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk);
     float2 v[R], h[R];
     if (active) {
         eng.first(t, [&](int q, int e) {
@@ -240,9 +278,11 @@ __global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long 
             v[q] = make_float2(-ky * a.y, ky * a.x);
         });
     }
-    eng.template run<true>(v, L, t, tw, active);
+    const float2* twl = stage_twiddles<TW>(tw, lds);
+    if constexpr (TW > 0) __syncthreads();
+    eng.template run<true>(v, L, t, twl, active);
     if (active) eng.last(t, [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
-    eng.template run<true>(h, L, t, tw, active);
+    eng.template run<true>(h, L, t, twl, active);
     if (!active) return;
     eng.last(t, [&](int q, int e) { S[base + (uint32_t)e * es] = h[q]; });
 }
@@ -255,6 +295,7 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
                                                     long w_bstride, ColGeom cg, LE eng, const float2* tw,
                                                     int mtype, int ax_a, int ax_b, float kf, float scale) {
     constexpr int R = LE::kR;
+    constexpr int TW = LE::kTwN;
     extern __shared__ float2 lds[];
     int t, c;
     uint32_t base;
@@ -290,7 +331,9 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
             v[q] = x;
         });
     }
-    eng.template run<true>(v, lds + threadIdx.x % (TK > 0 ? TK : cg.tk), t, tw, active);
+    const float2* twl = stage_twiddles<TW>(tw, lds);
+    if constexpr (TW > 0) __syncthreads();
+    eng.template run<true>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
     if (!active) return;
     eng.last(t, [&](int q, int e) { W[base + (uint32_t)e * es] = v[q]; });
 }
@@ -338,8 +381,9 @@ inline hipError_t allow_lds_fft(K kernel, size_t bytes) {
 template <class LE>
 inline hipError_t go_z_r2c(const FftLaunch& L, LE e) {
     auto kern = k_fft_z_r2c<LE>;
-    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.rin, L.in_row, L.in_bstride, L.cout, L.out_row,
+    const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.rin, L.in_row, L.in_bstride, L.cout, L.out_row,
                        L.out_bstride, L.nrows, e, L.tw, L.pa, L.pb);
     return hipGetLastError();
 }
@@ -347,8 +391,9 @@ inline hipError_t go_z_r2c(const FftLaunch& L, LE e) {
 template <class LE, bool MUL>
 inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
     auto kern = k_fft_z_c2r<LE, MUL>;
-    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.cin, L.in_row, L.in_bstride, L.rout, L.out_row,
+    const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.in_row, L.in_bstride, L.rout, L.out_row,
                        L.out_bstride, L.nrows, e, L.tw, L.kf, L.scale);
     return hipGetLastError();
 }
@@ -356,32 +401,36 @@ inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
 template <class LE, int TK, bool INV>
 inline hipError_t go_cols(const FftLaunch& L, LE e) {
     auto kern = k_fft_cols<LE, TK, INV>;
-    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.d0, L.b0, L.cg, e, L.tw);
+    const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.d0, L.b0, L.cg, e, L.tw);
     return hipGetLastError();
 }
 
 template <class LF, class LI, int TK>
 inline hipError_t go_x_green(const FftLaunch& L, LF f, LI i) {
     auto kern = k_fft_x_green<LF, LI, TK>;
-    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.c0, L.d0, L.d1, L.b0, L.cg, f, i, L.tw, L.kf, L.scale);
+    const size_t lds = L.lds + tw_lds_bytes(pair_tw_entries<LF, LI>());
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.c0, L.d0, L.d1, L.b0, L.cg, f, i, L.tw, L.kf, L.scale);
     return hipGetLastError();
 }
 
 template <class LE, int TK>
 inline hipError_t go_y_split(const FftLaunch& L, LE e) {
     auto kern = k_fft_y_split<LE, TK>;
-    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.d0, L.d1, L.b0, L.cg, e, L.tw, L.kf);
+    const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.d0, L.d1, L.b0, L.cg, e, L.tw, L.kf);
     return hipGetLastError();
 }
 
 template <class LE, int TK>
 inline hipError_t go_x_mult(const FftLaunch& L, LE e) {
     auto kern = k_fft_x_mult<LE, TK>;
-    if (hipError_t ea = allow_lds_fft(kern, L.lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, L.st, L.c0, L.b0, L.d0, L.b1, L.cg, e, L.tw, L.mtype, L.ax_a,
+    const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.c0, L.b0, L.d0, L.b1, L.cg, e, L.tw, L.mtype, L.ax_a,
                        L.ax_b, L.kf, L.scale);
     return hipGetLastError();
 }
