@@ -1,9 +1,9 @@
 // Register/LDS Stockham FFT engine for gfx950 (64-wide wavefronts).
 //
 // A line of n complex values (n = 2^a 3^b) is transformed by T = n / R threads, each owning
-// R values in registers.  Radix-r stages (r in {2,3,4,8}, r | R) follow the Stockham
-// autosort recursion: with ns the product of the radices already applied, butterfly j
-// (0 <= j < n/r) reads elements j + i n/r (i < r), multiplies element i by W_{ns r}^{i (j mod ns)},
+// R values in registers.  Radix-r stages (r in {2,3,4,8}, and 6 and 12 in static plans; r | R)
+// follow the Stockham autosort recursion: with ns the product of the radices already applied,
+// butterfly j (0 <= j < n/r) reads elements j + i n/r (i < r), multiplies element i by W_{ns r}^{i (j mod ns)},
 // applies an r-point DFT and writes element i to (j / ns) ns r + (j mod ns) + i ns.  Thread t
 // owns butterflies j = t + s T, s < R/r.  Between stages the values go through LDS (write,
 // barrier, read, barrier).  The first stage's inputs and the last stage's outputs use the same
@@ -122,6 +122,41 @@ __device__ __forceinline__ void dft8(float2* a) {
     a[6] = csub(e2, w2);
     a[3] = cadd(e3, w3);
     a[7] = csub(e3, w3);
+}
+
+// k in [0, N1 N2) with k = k1 (mod N1) and k = k2 (mod N2) (N1, N2 coprime).
+constexpr int crt_index(int k1, int k2, int n1, int n2) {
+    for (int k = 0; k < n1 * n2; ++k)
+        if (k % n1 == k1 && k % n2 == k2) return k;
+    return 0;
+}
+
+// 6- and 12-point DFTs (N1 = 2 or 4 times N2 = 3) by the prime-factor (Good-Thomas) mapping:
+// input n = (n1 N2 + n2 N1) mod N, output k = CRT(k1, k2); the two factors need no twiddles
+// between them, so a radix-6 or -12 stage costs a radix-3 stage's butterflies without its own
+// pass through LDS.
+template <int N1, bool INV>
+__device__ __forceinline__ void dft_pfa3(float2* a) {
+    constexpr int N2 = 3, N = N1 * N2;
+    float2 y[N];  // y[k1 N2 + n2]
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+        float2 t[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) t[n1] = a[(n1 * N2 + n2 * N1) % N];
+        if constexpr (N1 == 2) dft2<INV>(t[0], t[1]);
+        if constexpr (N1 == 4) dft4<INV>(t[0], t[1], t[2], t[3]);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) y[k1 * N2 + n2] = t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        float2 u0 = y[k1 * N2], u1 = y[k1 * N2 + 1], u2 = y[k1 * N2 + 2];
+        dft3<INV>(u0, u1, u2);
+        a[crt_index(k1, 0, N1, N2)] = u0;
+        a[crt_index(k1, 1, N1, N2)] = u1;
+        a[crt_index(k1, 2, N1, N2)] = u2;
+    }
 }
 
 __device__ __forceinline__ int div_ns(int j, uint32_t nsm) { return (int)__umulhi((uint32_t)j, nsm); }
@@ -247,7 +282,8 @@ __device__ __forceinline__ void fft_line(float2 (&v)[R], const FftPlan& pl, floa
 // the host (any size), StatLine a plan fixed at compile time for one line length N, values per
 // thread R and LDS element stride LES.  With every stage's radix, product ns and LDS offset known
 // to the compiler, the static engine's index arithmetic folds into constants and LDS instruction
-// offsets; its radix order is the host plan's (3s first, then 8s, 4s, 2s; reversed for REV).
+// offsets; its radix order is 3s first (each merged with a 4 or a 2 into a radix-12 or -6
+// stage where R allows), then 8s, 4s, 2s; reversed for REV.
 
 template <int R>
 struct DynLine {
@@ -279,7 +315,18 @@ struct Radices {
 constexpr Radices static_radices(int n, int R, bool rev) {
     Radices s{0, {}};
     int m = n, k = 0;
-    while (m % 3 == 0) { s.r[k++] = 3; m /= 3; }
+    while (m % 3 == 0) {  // each factor 3 joins a factor 4 or 2 in one prime-factor stage when it can
+        if (R % 12 == 0 && (m / 3) % 4 == 0) {
+            s.r[k++] = 12;
+            m /= 12;
+        } else if (R % 6 == 0 && (m / 3) % 2 == 0) {
+            s.r[k++] = 6;
+            m /= 6;
+        } else {
+            s.r[k++] = 3;
+            m /= 3;
+        }
+    }
     while (R % 8 == 0 && m % 8 == 0) { s.r[k++] = 8; m /= 8; }
     while (R % 4 == 0 && m % 4 == 0) { s.r[k++] = 4; m /= 4; }
     while (m % 2 == 0) { s.r[k++] = 2; m /= 2; }
@@ -370,7 +417,9 @@ struct StatLine {
                     if constexpr (r == 2) dft2<INV>(a[0], a[1]);
                     if constexpr (r == 3) dft3<INV>(a[0], a[1], a[2]);
                     if constexpr (r == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
+                    if constexpr (r == 6) dft_pfa3<2, INV>(a);
                     if constexpr (r == 8) dft8<INV>(a);
+                    if constexpr (r == 12) dft_pfa3<4, INV>(a);
                 }
             }
             if constexpr (ST + 1 < kRad.nst) {
