@@ -48,10 +48,11 @@ struct CellC {
     float f;
 };
 
+// 32-bit index arithmetic: i * n_mesh < 1536^2 and a lattice index < 1536^3 < 2^32.
 __device__ __forceinline__ CellC cell_c(int i, float x, int n_part, int n_mesh, float inv_h, float qoff) {
-    long a = (long)i * n_mesh;
-    int q = (int)(a / n_part);
-    int rem = (int)(a - (long)q * n_part);
+    const uint32_t a = (uint32_t)i * (uint32_t)n_mesh;
+    const int q = (int)(a / (uint32_t)n_part);
+    const int rem = (int)(a - (uint32_t)q * (uint32_t)n_part);
     float w = (float)rem / (float)n_part + qoff + x * inv_h;
     float fl = floorf(w);
     CellC c;
@@ -62,12 +63,12 @@ __device__ __forceinline__ CellC cell_c(int i, float x, int n_part, int n_mesh, 
     return c;
 }
 
-__device__ __forceinline__ void lagr_idx(long p, int n_part, int& i, int& j, int& l) {
-    long np2 = (long)n_part * n_part;
-    i = (int)(p / np2);
-    long r = p - (long)i * np2;
-    j = (int)(r / n_part);
-    l = (int)(r - (long)j * n_part);
+__device__ __forceinline__ void lagr_idx(uint32_t p, int n_part, int& i, int& j, int& l) {
+    const uint32_t np = (uint32_t)n_part, np2 = np * np;
+    const uint32_t ii = p / np2, r = p - ii * np2, jj = r / np;
+    i = (int)ii;
+    j = (int)jj;
+    l = (int)(r - jj * np);
 }
 
 __device__ __forceinline__ int wrapn(int m, int n) { return m + 1 == n ? 0 : m + 1; }
@@ -128,7 +129,7 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
     float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
         int idx[3];
-        lagr_idx(p, dg.n_part, idx[0], idx[1], idx[2]);
+        lagr_idx((uint32_t)p, dg.n_part, idx[0], idx[1], idx[2]);
         float x[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];

@@ -18,10 +18,12 @@ struct Cell {
     float f;  // fraction towards m + 1
 };
 
+// 32-bit index arithmetic throughout: i * n_mesh < 1536^2 and a lattice index < 1536^3 < 2^32
+// (64-bit divisions are long instruction sequences on this hardware).
 __device__ __forceinline__ Cell cell_of(int i, float x, int n_part, int n_mesh, float inv_h, float qoff) {
-    long a = (long)i * n_mesh;
-    int q = (int)(a / n_part);
-    int rem = (int)(a - (long)q * n_part);
+    const uint32_t a = (uint32_t)i * (uint32_t)n_mesh;
+    const int q = (int)(a / (uint32_t)n_part);
+    const int rem = (int)(a - (uint32_t)q * (uint32_t)n_part);
     float w = (float)rem / (float)n_part + qoff + x * inv_h;
     float fl = floorf(w);
     Cell c;
@@ -34,12 +36,12 @@ __device__ __forceinline__ Cell cell_of(int i, float x, int n_part, int n_mesh, 
 
 __device__ __forceinline__ int wrap1(int m, int n) { return m + 1 == n ? 0 : m + 1; }
 
-__device__ __forceinline__ void lagr_index(long p, int n_part, int& i, int& j, int& l) {
-    long np2 = (long)n_part * n_part;
-    i = (int)(p / np2);
-    long r = p - (long)i * np2;
-    j = (int)(r / n_part);
-    l = (int)(r - (long)j * n_part);
+__device__ __forceinline__ void lagr_index(uint32_t p, int n_part, int& i, int& j, int& l) {
+    const uint32_t np = (uint32_t)n_part, np2 = np * np;
+    const uint32_t ii = p / np2, r = p - ii * np2, jj = r / np;
+    i = (int)ii;
+    j = (int)jj;
+    l = (int)(r - jj * np);
 }
 
 // CIC gather of three meshes at one particle.
@@ -134,7 +136,7 @@ __global__ void k_deposit_lagr(ParticlePtrs P, long npr, int n_real, LatticeGeom
     if (gid >= npr * n_real) return;
     long r = gid / npr, p = gid - r * npr;
     int i, j, l;
-    lagr_index(p, dg.n_part, i, j, l);
+    lagr_index((uint32_t)p, dg.n_part, i, j, l);
     Cell cx = cell_of(i, P.x[0][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
     Cell cy = cell_of(j, P.x[1][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
     Cell cz = cell_of(l, P.x[2][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
@@ -161,7 +163,7 @@ __global__ void k_deposit_drifted(ParticlePtrs P, long npr, int n_real, LatticeG
     if (gid >= npr * n_real) return;
     long r = gid / npr, p = gid - r * npr;
     int idx[3];
-    lagr_index(p, fg.n_part, idx[0], idx[1], idx[2]);
+    lagr_index((uint32_t)p, fg.n_part, idx[0], idx[1], idx[2]);
     float x[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];
@@ -242,39 +244,47 @@ hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float 
 // ------------------------------------------------------------------ gather + kick + drift
 
 // p += kick [g - D1 psi1 - (D2 - D1^2) psi2];  x += p Dr + dD1 psi1 + dD2 psi2.
-__global__ void k_gather_kick_drift(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* fx,
-                                    const float* fy, const float* fz, KickDrift kd) {
-    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= npr * n_real) return;
-    long r = gid / npr, p = gid - r * npr;
-    int idx[3];
-    lagr_index(p, fg.n_part, idx[0], idx[1], idx[2]);
-    float x[3];
-    Cell c[3];
+// Grid: (particle blocks, realizations).  Every particle array is read before the first store, so
+// the twelve streaming loads and the 24 mesh reads are in flight together (the arrays of one
+// particle set could alias as far as the compiler knows, which would otherwise order them).
+__global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint32_t npr, LatticeGeom fg,
+                                                           const float* fx, const float* fy, const float* fz,
+                                                           KickDrift kd) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npr) return;
+    const int r = blockIdx.y;
+    const long gid = (long)r * npr + p;
+    float x[3], pv[3], s1[3], s2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         x[d] = P.x[d][gid];
-        c[d] = cell_of(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
+        pv[d] = P.p[d][gid];
+        s1[d] = P.psi1[d][gid];
+        s2[d] = P.psi2[d][gid];
     }
+    int idx[3];
+    lagr_index((uint32_t)p, fg.n_part, idx[0], idx[1], idx[2]);
+    Cell c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
     float g[3];
-    long mo = r * fg.mesh_bstride;
+    const long mo = r * fg.mesh_bstride;
     gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
+    const bool move = kd.drift != 0.0f || kd.dd1 != 0.0f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
-        float pp = P.p[d][gid] + kd.kick * bracket(g[d], kd.d1, kd.d2m, s1, s2);
+        const float pp = pv[d] + kd.kick * bracket(g[d], kd.d1, kd.d2m, s1[d], s2[d]);
         P.p[d][gid] = pp;
-        if (kd.drift != 0.0f || kd.dd1 != 0.0f) P.x[d][gid] = x[d] + pp * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
+        if (move) P.x[d][gid] = x[d] + pp * kd.drift + kd.dd1 * s1[d] + kd.dd2 * s2[d];
     }
 }
 
 hipError_t gather_kick_drift(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg,
                              const float* fx, const float* fy, const float* fz, const KickDrift& kd,
                              hipStream_t st) {
-    long n = npr * n_real;
     ProfScope ps((kd.drift != 0.0f || kd.dd1 != 0.0f) ? PROF_GKD : PROF_KICK, st);
-    hipLaunchKernelGGL(k_gather_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr,
-                       n_real, fg, fx, fy, fz, kd);
+    hipLaunchKernelGGL(k_gather_kick_drift, dim3((unsigned)((npr + 255) / 256), n_real), dim3(256), 0, st, P,
+                       (uint32_t)npr, fg, fx, fy, fz, kd);
     return hipGetLastError();
 }
 
@@ -284,7 +294,7 @@ __global__ void k_gather_force(ParticlePtrs P, long npr, int n_real, LatticeGeom
     if (gid >= npr * n_real) return;
     long r = gid / npr, p = gid - r * npr;
     int idx[3];
-    lagr_index(p, fg.n_part, idx[0], idx[1], idx[2]);
+    lagr_index((uint32_t)p, fg.n_part, idx[0], idx[1], idx[2]);
     Cell c[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], P.x[d][gid], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
