@@ -78,6 +78,23 @@ __device__ __forceinline__ const float2* stage_twiddles(const float2* tw, float2
     }
 }
 
+// ------------------------------------------------------------------ streaming row access
+
+// Non-temporal loads and stores for the z passes: a block moves whole contiguous rows that no
+// other block touches, and the measured z c2r time falls by a tenth (0.66 -> 0.59 ms on 768^3)
+// with both.  The column passes keep cached access: a 64-byte tile row shares its 128-byte line
+// with the neighbouring tile, which finds it in L2.
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+    float2 v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    return v;
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // ------------------------------------------------------------------ z pass: real -> half complex
 
 // Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
@@ -101,7 +118,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
     if (active) {
         const float2* src = reinterpret_cast<const float2*>(in + row * in_row);
         eng.first(t, [&](int q, int e) {
-            float2 z = src[e];
+            float2 z = load_stream(src + e);
             v[q] = make_float2(fmaf(z.x, pa, pb), fmaf(z.y, pa, pb));
         });
     }
@@ -120,11 +137,11 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
         float2 e = cscale(cadd(zk, zc), 0.5f);
         float2 d = csub(zk, zc);
         float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
-        dst[k] = cadd(e, cmul(twl[k], o));
+        store_stream(dst + k, cadd(e, cmul(twl[k], o)));
     }
     if (t == 0) {
         float2 z0 = L[0];
-        dst[M] = make_float2(z0.x - z0.y, 0.0f);
+        store_stream(dst + M, make_float2(z0.x - z0.y, 0.0f));
     }
 }
 
@@ -153,8 +170,8 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row
         const float2* src = in + row * in_row;
         float2 x[R];
 #pragma unroll
-        for (int u = 0; u < R; ++u) x[u] = src[t + u * T];
-        float2 xm = (t == 0) ? src[M] : make_float2(0.0f, 0.0f);
+        for (int u = 0; u < R; ++u) x[u] = load_stream(src + t + u * T);
+        float2 xm = (t == 0) ? load_stream(src + M) : make_float2(0.0f, 0.0f);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             int e = t + u * T;
@@ -181,7 +198,7 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row
     eng.template run<true>(v, L, t, twl, active);
     if (!active) return;
     float2* dst = reinterpret_cast<float2*>(out + row * out_row);
-    eng.last(t, [&](int q, int e) { dst[e] = v[q]; });
+    eng.last(t, [&](int q, int e) { store_stream(dst + e, v[q]); });
 }
 
 // ------------------------------------------------------------------ strided column passes
