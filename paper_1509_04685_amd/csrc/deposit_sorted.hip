@@ -73,6 +73,23 @@ __device__ __forceinline__ void lagr_idx(uint32_t p, int n_part, int& i, int& j,
 
 __device__ __forceinline__ int wrapn(int m, int n) { return m + 1 == n ? 0 : m + 1; }
 
+// The per-particle key and record arrays are written once and read once, in particle order:
+// non-temporal, so that they do not evict mesh and count lines from L2.
+__device__ __forceinline__ void store_rec_stream(float4* p, float4 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z);
+    __builtin_nontemporal_store(v.w, &p->w);
+}
+__device__ __forceinline__ float4 load_rec_stream(const float4* p) {
+    float4 v;
+    v.x = __builtin_nontemporal_load(&p->x);
+    v.y = __builtin_nontemporal_load(&p->y);
+    v.z = __builtin_nontemporal_load(&p->z);
+    v.w = __builtin_nontemporal_load(&p->w);
+    return v;
+}
+
 // CIC gather of three meshes (force at the particle, for positions drifted between nodes).
 __device__ __forceinline__ void gather3c(const float* fx, const float* fy, const float* fz, long row, int n,
                                          const CellC* c, float g[3]) {
@@ -132,7 +149,7 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
         lagr_idx((uint32_t)p, dg.n_part, idx[0], idx[1], idx[2]);
         float x[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];
+        for (int d = 0; d < 3; ++d) x[d] = __builtin_nontemporal_load(P.x[d] + gid);
         if (DRIFT) {
             float g[3] = {0.0f, 0.0f, 0.0f};
             if (kd.kick != 0.0f) {  // no force mesh is read for a pure drift (redshift-space mapping)
@@ -159,8 +176,8 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
         key = (uint32_t)(tile * 8 + cat);
         const int local = (((lx << tg.ly) + ly) << tg.lz) + lz;
         rec = make_float4(__int_as_float(local), c[0].f, c[1].f, c[2].f);
-        sb.keys[gid] = key;
-        sb.recs[gid] = rec;
+        __builtin_nontemporal_store(key, sb.keys + gid);
+        store_rec_stream(sb.recs + gid, rec);
     }
     (void)wave_increment(sb.count + (long)r * sb.kstride, key, valid);
 }
@@ -246,8 +263,8 @@ __global__ void k_dep_scatter(long npr, SortBufs sb) {
     const int r = blockIdx.y;
     const bool valid = p < npr;
     const long gid = (long)r * npr + p;
-    uint32_t key = valid ? sb.keys[gid] : 0u;
-    float4 rec = valid ? sb.recs[gid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t key = valid ? __builtin_nontemporal_load(sb.keys + gid) : 0u;
+    float4 rec = valid ? load_rec_stream(sb.recs + gid) : make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t slot = wave_increment(sb.cursor + (long)r * sb.kstride, key, valid);
     if (valid) sb.sorted[(long)r * npr + slot] = rec;
 }

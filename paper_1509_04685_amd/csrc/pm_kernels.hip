@@ -246,7 +246,9 @@ hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float 
 // p += kick [g - D1 psi1 - (D2 - D1^2) psi2];  x += p Dr + dD1 psi1 + dD2 psi2.
 // Grid: (particle blocks, realizations).  Every particle array is read before the first store, so
 // the twelve streaming loads and the 24 mesh reads are in flight together (the arrays of one
-// particle set could alias as far as the compiler knows, which would otherwise order them).
+// particle set could alias as far as the compiler knows, which would otherwise order them).  The
+// particle streams are non-temporal, leaving L2 to the force-mesh lines that neighbouring
+// particles share.
 __global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint32_t npr, LatticeGeom fg,
                                                            const float* fx, const float* fy, const float* fz,
                                                            KickDrift kd) {
@@ -257,10 +259,10 @@ __global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint3
     float x[3], pv[3], s1[3], s2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        x[d] = P.x[d][gid];
-        pv[d] = P.p[d][gid];
-        s1[d] = P.psi1[d][gid];
-        s2[d] = P.psi2[d][gid];
+        x[d] = __builtin_nontemporal_load(P.x[d] + gid);
+        pv[d] = __builtin_nontemporal_load(P.p[d] + gid);
+        s1[d] = __builtin_nontemporal_load(P.psi1[d] + gid);
+        s2[d] = __builtin_nontemporal_load(P.psi2[d] + gid);
     }
     int idx[3];
     lagr_index((uint32_t)p, fg.n_part, idx[0], idx[1], idx[2]);
@@ -274,8 +276,8 @@ __global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint3
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const float pp = pv[d] + kd.kick * bracket(g[d], kd.d1, kd.d2m, s1[d], s2[d]);
-        P.p[d][gid] = pp;
-        if (move) P.x[d][gid] = x[d] + pp * kd.drift + kd.dd1 * s1[d] + kd.dd2 * s2[d];
+        __builtin_nontemporal_store(pp, P.p[d] + gid);
+        if (move) __builtin_nontemporal_store(x[d] + pp * kd.drift + kd.dd1 * s1[d] + kd.dd2 * s2[d], P.x[d] + gid);
     }
 }
 
