@@ -276,6 +276,14 @@ struct Pull {
 };
 __constant__ Pull kPulls[14] = {{0, 0, 8}, {4, 4, 8}, {2, 2, 4}, {2, 6, 8}, {1, 1, 2}, {1, 3, 4}, {1, 5, 6},
                                 {1, 7, 8}, {6, 6, 8}, {5, 5, 6}, {5, 7, 8}, {3, 3, 4}, {3, 7, 8}, {7, 7, 8}};
+// The offsets d of kPulls packed 3 bits each (entry q at bits 3q), for a register lookup.
+constexpr unsigned long long pack_pull_offsets() {
+    const int d[14] = {0, 4, 2, 2, 1, 1, 1, 1, 6, 5, 5, 3, 3, 7};
+    unsigned long long v = 0;
+    for (int q = 0; q < 14; ++q) v |= (unsigned long long)d[q] << (3 * q);
+    return v;
+}
+constexpr unsigned long long kPullOffsets = pack_pull_offsets();
 
 // One block per tile: pull the records whose corners reach into the tile, accumulate in LDS,
 // write every cell of the tile once as delta = rho * scale + offset.  The 14 record ranges are
@@ -291,12 +299,13 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
     const int r = blockIdx.y;
     const long tile = blockIdx.x;
     const int ncell = tg.tx * tg.ty * tg.tz;
-    for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = 0ull;
     const int tzi = (int)(tile % tg.ntz);
     const int tyi = (int)((tile / tg.ntz) % tg.nty);
     const int txi = (int)(tile / ((long)tg.ntz * tg.nty));
     const uint32_t* start = sb.start + (long)r * sb.kstride;
     const float4* recs = sb.sorted + (long)r * npr;
+    // The 14 range bounds are requested first, so that their latency overlaps the LDS clear.
+    uint32_t b = 0, e = 0;
     if (threadIdx.x < 14) {
         const Pull pl = kPulls[threadIdx.x];
         const int dx = (pl.d >> 2) & 1, dy = (pl.d >> 1) & 1, dz = pl.d & 1;
@@ -304,22 +313,29 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
         const int sy = tyi - dy < 0 ? tg.nty - 1 : tyi - dy;
         const int sz = tzi - dz < 0 ? tg.ntz - 1 : tzi - dz;
         const long src = ((long)sx * tg.nty + sy) * tg.ntz + sz;
-        const uint32_t b = start[src * 8 + pl.c_lo], e = start[src * 8 + pl.c_hi];
-        rb[threadIdx.x] = b;
-        rlen[threadIdx.x] = e - b;
+        b = start[src * 8 + pl.c_lo];
+        e = start[src * 8 + pl.c_hi];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {  // exclusive prefix of the range lengths, total in rlen[14]
-        uint32_t run = 0;
-        for (int q = 0; q < 14; ++q) {
-            uint32_t l = rlen[q];
-            rlen[q] = run;
-            run += l;
+    for (int i = threadIdx.x; i < ncell; i += blockDim.x) acc[i] = 0ull;
+    if (threadIdx.x < 64) {  // first wave: exclusive prefix of the range lengths by a lane scan
+        const uint32_t len = threadIdx.x < 14 ? e - b : 0u;
+        uint32_t inc = len;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off);
+            if ((int)threadIdx.x >= off) inc += y;
         }
-        rlen[14] = run;
+        if (threadIdx.x < 14) {
+            rb[threadIdx.x] = b;
+            rlen[threadIdx.x] = inc - len;
+        }
+        if (threadIdx.x == 13) rlen[14] = inc;
     }
     __syncthreads();
     const uint32_t total = rlen[14];
+    uint32_t rl[14];  // range starts in the concatenation (non-decreasing)
+#pragma unroll
+    for (int k = 0; k < 14; ++k) rl[k] = rlen[k];
     // Each thread sweeps a contiguous chunk of the concatenated records, so that the lanes of a
     // wave work on records far apart in the sorted order: records of one key range are in
     // Lagrangian order, and neighbouring particles hit the same cells -- consecutive records on
@@ -327,10 +343,11 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
     const uint32_t chunk = (total + blockDim.x - 1) / blockDim.x;
     const uint32_t i0 = threadIdx.x * chunk;
     const uint32_t i1 = min(total, i0 + chunk);
-    int q = 0;
     for (uint32_t i = i0; i < i1; ++i) {
-        while (q < 13 && i >= rlen[q + 1]) ++q;  // i only grows, so q only moves forward
-        const int d = kPulls[q].d;
+        int q = 0;  // the last range starting at or before i (empty ranges share their start)
+#pragma unroll
+        for (int k = 1; k < 14; ++k) q += i >= rl[k] ? 1 : 0;
+        const int d = (int)((kPullOffsets >> (3 * q)) & 7u);
         const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
         const float4 rec = recs[rb[q] + (i - rlen[q])];
         const int local = __float_as_int(rec.x);
