@@ -120,6 +120,26 @@ def test_pm_force_identical_positions(cola, n_part, pm, box, scale):
     assert np.abs(acc.astype(np.float64).sum(1)).max() < 1e-5 * np.abs(acc).sum(1).max()
 
 
+@pytest.mark.parametrize("n_part,box", [(96, 300.0), (128, 400.0)])
+def test_pm_force_static_plans(cola, n_part, box):
+    """288^3 and 384^3 force meshes after the autotuner, which picks the compile-time plans
+    (radix-6/12 prime-factor stages, twiddles read from LDS) for these sizes: every pass of the
+    force (z r2c, y, fused x Green/gradient, y split, y inverse, three z c2r) against the float64
+    oracle."""
+    say(f"pm force static plans n_part={n_part}")
+    prob = cola.make_problem(box, n_part, 3, 19.0, 10)
+    ws = cola.Workspace(prob)
+    report = cola.autotune(prob, ws)
+    print(report)
+    disp = W.random_displacements(n_part, 5.0, seed=5).astype(np.float32)
+    st = gpu_state_from_disp(cola, prob, disp)
+    acc = cola.pm_force(prob, st, ws).cpu().numpy()
+    op = ocola.Problem(box, n_part, 3, 19.0, 10)
+    ref = opm.pm_accel(ocola.positions(ocola.State(disp.astype(np.float64), None, None, None), op),
+                       op.n_mesh, box)
+    assert rel_rms(acc, ref) < 1e-5
+
+
 def test_pm_force_lattice_is_zero(cola):
     say("pm force lattice")
     prob = cola.make_problem(256.0, 32, 3, 19.0, 10)
