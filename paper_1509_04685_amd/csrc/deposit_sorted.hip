@@ -74,7 +74,8 @@ __device__ __forceinline__ void lagr_idx(uint32_t p, int n_part, int& i, int& j,
 __device__ __forceinline__ int wrapn(int m, int n) { return m + 1 == n ? 0 : m + 1; }
 
 // The per-particle key and record arrays are written once and read once, in particle order:
-// non-temporal, so that they do not evict mesh and count lines from L2.
+// non-temporal, so that they do not evict mesh and count lines from L2 (the tile pass also
+// stores the mesh this way).
 __device__ __forceinline__ void store_rec_stream(float4* p, float4 v) {
     __builtin_nontemporal_store(v.x, &p->x);
     __builtin_nontemporal_store(v.y, &p->y);
@@ -382,7 +383,7 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
             const int uz = i & (tg.tz - 1), uy = (i >> tg.lz) & (tg.ty - 1), ux = i >> (tg.lz + tg.ly);
             const long gx = (long)txi * tg.tx + ux, gy = (long)tyi * tg.ty + uy, gz = (long)tzi * tg.tz + uz;
             const float4 a = make_float4(cell(i), cell(i + 1), cell(i + 2), cell(i + 3));
-            *reinterpret_cast<float4*>(out + (gx * tg.n + gy) * row + gz) = a;
+            store_rec_stream(reinterpret_cast<float4*>(out + (gx * tg.n + gy) * row + gz), a);
         }
     } else {
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
