@@ -95,6 +95,18 @@ __device__ __forceinline__ void store_stream(float2* p, float2 v) {
     __builtin_nontemporal_store(v.y, &p->y);
 }
 
+// Column passes: streaming access only when a tile row fills whole 128-byte lines (16 columns).
+template <int TK>
+__device__ __forceinline__ float2 load_col(const float2* p) {
+    if constexpr (TK >= 16) return load_stream(p);
+    else return *p;
+}
+template <int TK>
+__device__ __forceinline__ void store_col(float2* p, float2 v) {
+    if constexpr (TK >= 16) store_stream(p, v);
+    else *p = v;
+}
+
 // ------------------------------------------------------------------ z pass: real -> half complex
 
 // Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
@@ -288,7 +300,7 @@ __global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long 
     float2 v[R], h[R];
     if (active) {
         eng.first(t, [&](int q, int e) {
-            float2 a = A[base + (uint32_t)e * es];
+            float2 a = load_col<TK>(A + base + (uint32_t)e * es);
             h[q] = a;
             int my = signed_mode(e, n);
             float ky = (2 * my == -n) ? 0.0f : kf * (float)my;
@@ -298,10 +310,10 @@ __global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long 
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
     eng.template run<true>(v, L, t, twl, active);
-    if (active) eng.last(t, [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
+    if (active) eng.last(t, [&](int q, int e) { store_col<TK>(A + base + (uint32_t)e * es, v[q]); });
     eng.template run<true>(h, L, t, twl, active);
     if (!active) return;
-    eng.last(t, [&](int q, int e) { S[base + (uint32_t)e * es] = h[q]; });
+    eng.last(t, [&](int q, int e) { store_col<TK>(S + base + (uint32_t)e * es, h[q]); });
 }
 
 // x inverse with a multiplier taken from the full spectrum: W = IFFT_x[M(k) spec].
