@@ -227,12 +227,12 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, Co
     data += (long)blockIdx.y * bstride;
     const uint32_t es = (uint32_t)cg.es;
     float2 v[R];
-    if (active) eng.first(t, [&](int q, int e) { v[q] = data[base + (uint32_t)e * es]; });
+    if (active) eng.first(t, [&](int q, int e) { v[q] = load_col<TK>(data + base + (uint32_t)e * es); });
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
     eng.template run<INV>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
     if (!active) return;
-    eng.last(t, [&](int q, int e) { data[base + (uint32_t)e * es] = v[q]; });
+    eng.last(t, [&](int q, int e) { store_col<TK>(data + base + (uint32_t)e * es, v[q]); });
 }
 
 // Fused x pass of the particle-mesh force.  Columns are (y, kz); the transform axis is x.
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
     const int my = signed_mode(yrow, n), mz = c - yrow * cg.nzp;
     float2* L = lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk);
     float2 v[R], h[R];
-    if (active) ef.first(t, [&](int q, int e) { v[q] = S[base + (uint32_t)e * es]; });
+    if (active) ef.first(t, [&](int q, int e) { v[q] = load_col<TK>(S + base + (uint32_t)e * es); });
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
     ef.template run<false>(v, L, t, twl, active);
@@ -274,10 +274,10 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
         h[q] = make_float2(-kx * v[q].y, kx * v[q].x);  // i k_x V
     });
     ei.template run<true>(v, L, t, twl, active);
-    if (active) ei.last(t, [&](int q, int e) { A[base + (uint32_t)e * es] = v[q]; });
+    if (active) ei.last(t, [&](int q, int e) { store_col<TK>(A + base + (uint32_t)e * es, v[q]); });
     ei.template run<true>(h, L, t, twl, active);
     if (!active) return;
-    ei.last(t, [&](int q, int e) { B[base + (uint32_t)e * es] = h[q]; });
+    ei.last(t, [&](int q, int e) { store_col<TK>(B + base + (uint32_t)e * es, h[q]); });
 }
 
 // y inverse of A giving two outputs: A <- IFFT_y[i k_y A] (Nyquist of k_y set to 0) and
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
     float2 v[R];
     if (active) {
         eng.first(t, [&](int q, int e) {
-            float2 x = spec[base + (uint32_t)e * es];
+            float2 x = load_col<TK>(spec + base + (uint32_t)e * es);
             const int mx = signed_mode(e, n);
             const int ma = ax_a == 0 ? mx : (ax_a == 1 ? my : mz);
             const int mb = ax_b == 0 ? mx : (ax_b == 1 ? my : mz);
@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
     if constexpr (TW > 0) __syncthreads();
     eng.template run<true>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
     if (!active) return;
-    eng.last(t, [&](int q, int e) { W[base + (uint32_t)e * es] = v[q]; });
+    eng.last(t, [&](int q, int e) { store_col<TK>(W + base + (uint32_t)e * es, v[q]); });
 }
 
 // ------------------------------------------------------------------ launches
