@@ -152,6 +152,15 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
 #pragma unroll
         for (int d = 0; d < 3; ++d) x[d] = __builtin_nontemporal_load(P.x[d] + gid);
         if (DRIFT) {
+            // the particle arrays are read before the force gather, so both are in flight together
+            float s1[3] = {0.0f, 0.0f, 0.0f}, s2[3] = {0.0f, 0.0f, 0.0f}, pv[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (kd.los >= 0 && d != kd.los) continue;
+                s1[d] = __builtin_nontemporal_load(P.psi1[d] + gid);
+                s2[d] = __builtin_nontemporal_load(P.psi2[d] + gid);
+                pv[d] = __builtin_nontemporal_load(P.p[d] + gid);
+            }
             float g[3] = {0.0f, 0.0f, 0.0f};
             if (kd.kick != 0.0f) {  // no force mesh is read for a pure drift (redshift-space mapping)
                 CellC c[3];
@@ -163,9 +172,8 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 if (kd.los >= 0 && d != kd.los) continue;
-                float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
-                float ph = P.p[d][gid] + kd.kick * (g[d] - kd.d1 * s1 - kd.d2m * s2);
-                x[d] = x[d] + ph * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
+                const float ph = pv[d] + kd.kick * (g[d] - kd.d1 * s1[d] - kd.d2m * s2[d]);
+                x[d] = x[d] + ph * kd.drift + kd.dd1 * s1[d] + kd.dd2 * s2[d];
             }
         }
         CellC c[3];
