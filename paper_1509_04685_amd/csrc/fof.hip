@@ -145,23 +145,25 @@ __global__ void k_fof_link(const float4* __restrict__ recs, long n, FofGrid g, c
     const int32_t i = __float_as_int(a.w);
     const float half = 0.5f * box;
     const int cx = cell1(a.x, g.inv_cell, g.nc), cy = cell1(a.y, g.inv_cell, g.nc), cz = cell1(a.z, g.inv_cell, g.nc);
-    // own cell: the records after this one
-    {
-        const long c = ((long)cx * g.nc + cy) * g.nc + cz;
-        const uint32_t e = start[c + 1];
-        for (uint32_t k = (uint32_t)t + 1; k < e; ++k) {
-            const float4 b = recs[k];
-            if (d2_of(a, b, box, half) < link2) fof_union(parent, i, __float_as_int(b.w));
+    // the record ranges of the own cell (the records after this one) and of the 13 forward
+    // neighbours, all requested before the first is used (one memory round trip, not fourteen)
+    uint32_t rb[14], re[14];
+    rb[0] = (uint32_t)t + 1;
+    re[0] = start[((long)cx * g.nc + cy) * g.nc + cz + 1];
+    const int ncells = g.nc < 3 ? 1 : 14;  // a single cell holds every particle
+    if (ncells == 14) {
+#pragma unroll
+        for (int o = 0; o < 13; ++o) {
+            const int ux = (cx + kForward[o][0] + g.nc) % g.nc;
+            const int uy = (cy + kForward[o][1] + g.nc) % g.nc;
+            const int uz = (cz + kForward[o][2] + g.nc) % g.nc;
+            const long c = ((long)ux * g.nc + uy) * g.nc + uz;
+            rb[o + 1] = start[c];
+            re[o + 1] = start[c + 1];
         }
     }
-    if (g.nc < 3) return;  // a single cell holds every particle
-    for (int o = 0; o < 13; ++o) {
-        const int ux = (cx + kForward[o][0] + g.nc) % g.nc;
-        const int uy = (cy + kForward[o][1] + g.nc) % g.nc;
-        const int uz = (cz + kForward[o][2] + g.nc) % g.nc;
-        const long c = ((long)ux * g.nc + uy) * g.nc + uz;
-        const uint32_t b0 = start[c], e = start[c + 1];
-        for (uint32_t k = b0; k < e; ++k) {
+    for (int q = 0; q < ncells; ++q) {
+        for (uint32_t k = rb[q]; k < re[q]; ++k) {
             const float4 b = recs[k];
             if (d2_of(a, b, box, half) < link2) fof_union(parent, i, __float_as_int(b.w));
         }
