@@ -118,7 +118,8 @@ struct OutDst {
 //   EPI_OUT: the output layer, dF = (W3 silu(Z) + b3) * scale, added to the meshes of `od`;
 //   EPI_OUT_STORE: the same, stored instead of added.
 // FIELDS (first layer only, CINP = 8): the halo is built from `fs` instead of `in`.
-// Three blocks per CU (at most 168 VGPRs): with two, the 16-channel layers left the matrix cores
+// At least three waves per SIMD, i.e. three blocks per CU (at most 168 VGPRs): with two, the
+// 16-channel layers left the matrix cores
 // and LDS idle through each tile's barriers (0.50 -> 0.41 ms per launch on 256^3); four would
 // spill the 16-channel output layer.
 template <int CINP, int NB, int EPI, bool FIELDS = false>
