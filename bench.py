@@ -456,7 +456,7 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(an ensemble shards one realization per GPU with no communication).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
