@@ -63,10 +63,10 @@ Layout layout_of(const cola_problem& p, int n_pk) {
         off += align256((size_t)L.kstride * sizeof(float2) * p.n_real);
     }
     const long npr = (long)p.n_part * p.n_part * p.n_part;
-    L.tg = make_tiles(L.g.n);
+    L.tg = make_tiles(L.g.n, npr);
     size_t sb = sort_bytes(npr, L.tg, p.n_real);
     if (n_pk > 0) {
-        L.tk = make_tiles(n_pk);
+        L.tk = make_tiles(n_pk, npr);
         sb = std::max(sb, sort_bytes(npr, L.tk, p.n_real));
     }
     L.off_sort = off; off += align256(sb);

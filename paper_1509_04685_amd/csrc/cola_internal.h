@@ -189,7 +189,7 @@ struct SortBufs {
     long kstride = 0;
     int nblocks = 0;
 };
-TileGeom make_tiles(int n);
+TileGeom make_tiles(int n, long n_particles);
 size_t sort_bytes(long n_particles_per_real, const TileGeom& tg, int n_real);
 SortBufs carve_sort(void* base, long npr, const TileGeom& tg, int n_real);
 // CIC deposit of every particle (drifted on the fly when `drift`, with the force gathered from
