@@ -34,6 +34,7 @@
 
 #include "cola_internal.h"
 #include "lc_internal.h"
+#include "wave_ops.h"
 
 namespace cola {
 
@@ -116,18 +117,22 @@ __device__ __forceinline__ float d2_of(float4 a, float4 b, float box, float half
 __global__ void k_fof_bin(const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
                           long n, FofGrid g, uint32_t* cell_of, uint32_t* count) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t c = cell3(px[i], py[i], pz[i], g);
-    cell_of[i] = c;
-    atomicAdd(count + c, 1u);
+    const bool valid = i < n;  // every lane takes part in the wave-level counting
+    uint32_t c = 0;
+    if (valid) {
+        c = cell3(px[i], py[i], pz[i], g);
+        cell_of[i] = c;
+    }
+    (void)wave_increment(count, c, valid);
 }
 
 __global__ void k_fof_scatter(const float* __restrict__ px, const float* __restrict__ py,
                               const float* __restrict__ pz, long n, const uint32_t* cell_of, uint32_t* cursor,
                               float4* recs, int32_t* parent) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t slot = atomicAdd(cursor + cell_of[i], 1u);
+    const bool valid = i < n;
+    const uint32_t slot = wave_increment(cursor, valid ? cell_of[i] : 0u, valid);
+    if (!valid) return;
     recs[slot] = make_float4(px[i], py[i], pz[i], __int_as_float((int)i));
     parent[i] = (int32_t)i;
 }
