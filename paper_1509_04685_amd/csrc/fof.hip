@@ -85,6 +85,12 @@ __device__ __forceinline__ int32_t fof_find(int32_t* parent, int32_t x) {
 }
 
 __device__ __forceinline__ void fof_union(int32_t* parent, int32_t a, int32_t b) {
+    // friends inside a halo mostly share a parent already (path halving points them at the root):
+    // then the sets are joined and both find walks are skipped
+    const int32_t pa = ld_parent(parent, a), pb = ld_parent(parent, b);
+    if (pa == pb) return;
+    a = pa;
+    b = pb;
     while (true) {
         int32_t ra = fof_find(parent, a), rb = fof_find(parent, b);
         if (ra == rb) return;
