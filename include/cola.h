@@ -88,8 +88,14 @@ typedef struct {
  *   psi1  first-order Lagrangian displacement at D1 = 1; psi2 second order (D2 < 0 convention).
  * node        index of the time node the state sits at (0 after cola_ic_2lpt).
  * force_node  node whose force mesh the workspace `force_ws` holds, or -1.  Set by the
- *             library; set it to -1 yourself after changing x or switching workspaces.
- * force_ws    workspace that holds that force mesh. */
+ *             library; set it to -1 yourself after changing x, or the parameters or scales of
+ *             the network of cola_step_lc.
+ * force_ws    workspace that holds that force mesh.
+ * The library also keeps, per workspace, which state (identified by its x[0] array), node and
+ * network (its params array, or none) the force meshes belong to; every call that writes a
+ * workspace drops that record.  A cached force is used only when both agree, so sharing a
+ * workspace between states, or between cola_step and cola_step_lc, costs a force evaluation,
+ * never a wrong force. */
 typedef struct {
     float* x[3];
     float* p[3];
@@ -142,7 +148,9 @@ int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
  * multiplicity of each half-spectrum mode; sums in float64.  No shot-noise or aliasing
  * correction.  Outputs (device, n_real * n_bins each, bin 0 empty): k_mean [h/Mpc], pk
  * [(h^-1 Mpc)^3], n_modes.  n_pk: even, factors 2 and 3 only.  ws: cola_workspace_bytes(prob,
- * n_pk) bytes at least.  May evaluate and cache the node's force if it is not cached. */
+ * n_pk) bytes at least.  Between nodes it uses the force of node j that the workspace holds for
+ * this state (from cola_step or cola_step_lc); with none cached it evaluates and caches the plain
+ * mesh force of node j. */
 int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo,
                         cola_particles* in, double a_out, int32_t n_pk, int32_t n_bins,
                         double* k_mean, double* pk, double* n_modes,
@@ -204,6 +212,13 @@ int cola_ensemble_release(void);
  * report (host, may be NULL): one line per pass with the chosen shape and its time. */
 int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_bytes, void* stream,
                   char* report, size_t report_len);
+
+/* Pins the kernel shape of one FFT pass kind at mesh side n for the rest of the process, as the
+ * autotuner would: kind one of "z_r2c", "z_c2r", "cols_y", "cols_x", "x_green", "y_split",
+ * "x_mult"; values_per_thread and width (lines per block for the z passes, columns per tile
+ * otherwise) must form an admissible shape; use_static selects the compile-time plan of that
+ * shape (COLA_ERR_INVALID_ARG if the library has none).  Host only: nothing is launched. */
+int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, int32_t width, int32_t use_static);
 
 /* ---- learned coarse-mesh force correction ---------------------------------------------- */
 
@@ -283,12 +298,21 @@ int cola_lc_adam(const cola_lc_net* net, int32_t t, float lr, float beta1, float
 /* cola_step with the network's correction: at each force evaluation the density contrast and the
  * mesh force of every realization feed the network and dF is added to the force mesh before the
  * kick.  lc_ws: cola_lc_workspace_bytes(N_g, C, n_real, 0) bytes.  N_g a multiple of 16.  The
- * cached force (force_node) is then the corrected one: reset force_node to -1 before mixing
- * cola_step and cola_step_lc on one state, and call cola_power_spectrum between nodes only on a
- * state whose corrected force is cached. */
+ * cached force is then the corrected one (recorded with net->params, so cola_step on the same
+ * state evaluates its own plain force).  j_end = j_begin evaluates and caches the corrected force
+ * of the current node without stepping.  cola_power_spectrum between nodes drifts with the cached
+ * force of the state's node whatever network made it; with none cached it evaluates the plain
+ * force, so a corrected run keeps its corrected force cached (as every cola_step_lc leaves it). */
 int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin,
                  int32_t j_end, cola_particles* io, const cola_lc_net* net, void* lc_ws,
                  size_t lc_ws_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* The corrected acceleration of cola_step_lc at the current positions, without stepping: the
+ * mesh force of cola_pm_force plus the network's dF (output scale evaluated as in the step at
+ * scale factor a, a > 0), interpolated to the particles.  acc[d]: device, n_real * N_p^3 floats.
+ * lc_ws, ws: as for cola_step_lc.  The state is not changed; ws's force cache is dropped. */
+int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const cola_lc_net* net, double a,
+                     void* lc_ws, size_t lc_ws_bytes, float* acc[3], void* ws, size_t ws_bytes, void* stream);
 
 /* Mesh fields of arbitrary particles: CIC of the absolute positions pos[3] (device, n floats
  * each, any real, wrapped into the box) onto n_mesh^3 cells, delta = rho / rho_bar - 1, the force
@@ -298,6 +322,14 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
 size_t cola_pm_fields_workspace_bytes(int32_t n_mesh);
 int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, float* delta, float* g[3],
                    float* acc[3], void* ws, size_t ws_bytes, void* stream);
+
+/* Force meshes of a density-contrast mesh (Sec. 2.2: one forward FFT, the k-space force, three
+ * inverse FFTs), the transform passes of the step without its deposit and gather:
+ * g_d = IFFT[i k_d delta_k / k^2] (k = 0 and component d's own Nyquist plane set to 0).
+ * delta: device, dense n_mesh^3 floats; g[d]: device, dense n_mesh^3 floats each, overwritten.
+ * n_mesh: even, factors 2 and 3 only, <= 1536.  ws: cola_pm_fields_workspace_bytes(n_mesh). */
+int cola_mesh_force(int32_t n_mesh, double box, const float* delta, float* g[3], void* ws, size_t ws_bytes,
+                    void* stream);
 
 /* Absolute positions q + x of a batch, wrapped into [0, box): pos[d] device arrays of
  * n_real * N_p^3 floats. */
@@ -357,9 +389,13 @@ double cola_particle_mass(const cola_cosmology* cosmo, double box, int32_t n_par
 
 /* ---- component entry points (the stages above, exposed for parity checks) ------------- */
 
-/* CIC density contrast of arbitrary positions: pos[d] device arrays of n floats (absolute
- * positions in [0, box) or any real, wrapped periodically); delta: device n_mesh^3 floats.
- * rho_bar = n / n_mesh^3. */
+/* CIC density contrast of arbitrary positions (Sec. 2.2, Sec. 2.5: cloud-in-cell assignment) by
+ * the step's own deposit: records binned by mesh tile, counting sort, per-tile accumulation in
+ * 32.32 fixed point, every cell written once (deterministic; no atomics to device memory).
+ * pos[d]: device arrays of n floats (absolute positions, any real, wrapped periodically),
+ * 1 <= n < 2^31; delta: device, dense n_mesh^3 floats, overwritten; rho_bar = n / n_mesh^3;
+ * 2 <= n_mesh <= 1536.  ws: device, cola_cic_workspace_bytes(n, n_mesh) bytes (0 for invalid
+ * arguments or a mesh whose tile keys would not fit 32 bits). */
 int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box, float* delta,
                      void* ws, size_t ws_bytes, void* stream);
 size_t cola_cic_workspace_bytes(int64_t n, int32_t n_mesh);

@@ -157,13 +157,20 @@ def power_spectrum(prob, cosmo, state, a_out, n_pk, n_bins, ws, out=None):
     return km, pk, nm
 
 
-def cic_density(pos, n_mesh, box):
-    """pos: (3, n) float32 device tensor of absolute positions -> (n_mesh,)*3 density contrast."""
+def cic_density(pos, n_mesh, box, ws=None):
+    """pos: (3, n) float32 device tensor of absolute positions -> (n_mesh,)*3 density contrast, by the
+    step's sorted tile deposit."""
     torch = _torch()
     _require_cuda_f32(pos, "pos")
+    n = int(pos.shape[1])
+    nb = int(_lib.lib().cola_cic_workspace_bytes(n, int(n_mesh)))
+    if nb == 0:
+        raise ColaError(-1, "cola_cic_workspace_bytes")
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=pos.device)
     out = torch.empty((n_mesh, n_mesh, n_mesh), dtype=torch.float32, device=pos.device)
     ptrs = (ctypes.c_void_p * 3)(*[pos[d].data_ptr() for d in range(3)])
-    _lib.check(_lib.lib().cola_cic_density(ptrs, pos.shape[1], int(n_mesh), float(box), _ptr(out), None, 0,
+    _lib.check(_lib.lib().cola_cic_density(ptrs, n, int(n_mesh), float(box), _ptr(out), _ptr(ws), ws.numel(),
                                            _stream()), "cola_cic_density")
     return out
 
@@ -468,6 +475,41 @@ def step_lc(prob, cosmo, state, j_end, net, lc_ws, ws):
     _lib.check(_lib.lib().cola_step_lc(ctypes.byref(prob), ctypes.byref(cosmo), state.c.node, int(j_end),
                                        ctypes.byref(state.c), ctypes.byref(net.c), _ptr(lc_ws), lc_ws.numel(),
                                        ws.ptr, ws.nbytes, _stream()), "cola_step_lc")
+
+
+def pm_force_lc(prob, state, net, lc_ws, ws, a=1.0, acc=None):
+    """Corrected acceleration (3, n) of the state's positions: the step's mesh force plus the
+    network's dF with the output scale of scale factor a."""
+    torch = _torch()
+    if acc is None:
+        acc = torch.empty((3, state.n), dtype=torch.float32, device=state.x.device)
+    _lib.check(_lib.lib().cola_pm_force_lc(ctypes.byref(prob), ctypes.byref(state.c), ctypes.byref(net.c), float(a),
+                                           _ptr(lc_ws), lc_ws.numel(), _ptrs3(acc), ws.ptr, ws.nbytes, _stream()),
+               "cola_pm_force_lc")
+    return acc
+
+
+def mesh_force(delta, box, ws=None, g=None):
+    """Force meshes g (3, n, n, n) of a density-contrast mesh delta (n, n, n) float32 on the device."""
+    torch = _torch()
+    _require_cuda_f32(delta, "delta")
+    n = int(delta.shape[0])
+    nb = int(_lib.lib().cola_pm_fields_workspace_bytes(n))
+    if nb == 0:
+        raise ColaError(-2, "cola_pm_fields_workspace_bytes")
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=delta.device)
+    if g is None:
+        g = torch.empty((3, n, n, n), dtype=torch.float32, device=delta.device)
+    _lib.check(_lib.lib().cola_mesh_force(n, float(box), _ptr(delta), _ptrs3(g), _ptr(ws), ws.numel(), _stream()),
+               "cola_mesh_force")
+    return g
+
+
+def fft_set_shape(n, kind, values_per_thread, width, use_static=True):
+    """Pin one FFT pass kind's kernel shape at mesh side n (see cola_fft_set_shape)."""
+    _lib.check(_lib.lib().cola_fft_set_shape(int(n), kind.encode(), int(values_per_thread), int(width),
+                                             1 if use_static else 0), "cola_fft_set_shape")
 
 
 def pm_fields(pos, n_mesh, box, delta=True, g=True, acc=True, ws=None):

@@ -4,7 +4,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "cola_internal.h"
@@ -18,6 +20,43 @@ namespace cola {
 int hip_fail(hipError_t e, const char* what) {
     std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
     return COLA_ERR_HIP;
+}
+
+// Which force the meshes of a workspace hold: the state that owns it (its x[0] array), the node
+// and the network that corrected it (its parameter array; nullptr for the plain mesh force).
+// Every call that writes a workspace forgets its entry; the calls that leave a node's force
+// behind record it.  A state's own (force_node, force_ws) fields can only veto a cached force,
+// so a workspace shared between states, or overwritten by any other call, is never trusted.
+namespace {
+struct ForceTag {
+    const void* owner;
+    int node;
+    const void* net;
+};
+std::mutex g_tag_mu;
+std::unordered_map<const void*, ForceTag> g_tags;
+}  // namespace
+
+void ws_forget(const void* ws) {
+    if (!ws) return;
+    std::lock_guard<std::mutex> lock(g_tag_mu);
+    g_tags.erase(ws);
+}
+
+void ws_record(const void* ws, const cola_particles* P, int node, const void* net) {
+    std::lock_guard<std::mutex> lock(g_tag_mu);
+    g_tags[ws] = ForceTag{P->x[0], node, net};
+}
+
+// any_net: accept the force of any network (or none) -- the caller only needs the force the
+// state's own run used at that node.
+bool ws_holds(const void* ws, const cola_particles* P, int node, const void* net, bool any_net) {
+    if (!(P->force_node == node && P->force_ws == ws)) return false;
+    std::lock_guard<std::mutex> lock(g_tag_mu);
+    auto it = g_tags.find(ws);
+    if (it == g_tags.end()) return false;
+    const ForceTag& t = it->second;
+    return t.owner == P->x[0] && t.node == node && (any_net || t.net == net);
 }
 }  // namespace cola
 
@@ -152,6 +191,7 @@ LatticeGeom force_geom(const cola_problem& p, const Layout& L) {
 // The network correction at each force evaluation: its parameters, activations (x0 per
 // realization, the rest shared) and scales.
 struct LcHook {
+    const void* id;  // the network's parameter array: identifies the corrected force in the cache
     LcParams P;
     LcActs A;
     long x0_stride;
@@ -243,7 +283,6 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     if (j_begin != io->node || j_begin < 0 || j_end < j_begin || j_end >= prob->n_steps) return COLA_ERR_STATE;
     Layout L = layout_of(*prob, 0);
     if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
-    if (j_end == j_begin) return COLA_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Ws w = carve(ws, L);
     const cola_problem& p = *prob;
@@ -254,9 +293,18 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     LatticeGeom fg = force_geom(p, L);
     ForceMeshes f = force_meshes(w);
 
+    const void* net_id = lc ? lc->id : nullptr;
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
-    if (!(io->force_node == j_begin && io->force_ws == ws)) COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j_begin]));
+    const bool cached = ws_holds(ws, io, j_begin, net_id, false);
+    ws_forget(ws);
+    if (!cached) COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j_begin]));
+    if (j_end == j_begin) {  // nothing to step: the node's force is now cached
+        io->force_node = j_begin;
+        io->force_ws = ws;
+        ws_record(ws, io, j_begin, net_id);
+        return COLA_OK;
+    }
     double pending = 0.0;  // kick still owed to the current node (merged with the next kick)
     for (int j = j_begin; j < j_end; ++j) {
         KickDrift kd;
@@ -278,6 +326,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     io->node = j_end;
     io->force_node = j_end;
     io->force_ws = ws;
+    ws_record(ws, io, j_end, net_id);
     return COLA_OK;
 }
 
@@ -353,6 +402,7 @@ int cola_ic_2lpt(const cola_problem* prob, const cola_cosmology* cosmo, const ui
     const float kf = (float)(2.0 * M_PI / p.box);
     const float inv_n3 = (float)(1.0 / (double)npr);
     ParticlePtrs P = ptrs_of(out);
+    ws_forget(ws);
 
     (void)hipGetLastError();  // drop a stale error left by other code on this thread
     COLA_TRY(launch_twiddles(w.twp, gp.n, st));
@@ -404,6 +454,7 @@ int cola_pm_force(const cola_problem* prob, const cola_particles* in, float* acc
     hipStream_t st = static_cast<hipStream_t>(stream);
     Ws w = carve(ws, L);
     ParticlePtrs P = ptrs_of(in);
+    ws_forget(ws);
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     COLA_TRY(compute_force(*prob, L, w, P, st));
@@ -418,9 +469,11 @@ int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, nullptr);
 }
 
-int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
-                 cola_particles* io, const cola_lc_net* net, void* lc_ws, size_t lc_ws_bytes, void* ws,
-                 size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+// Validates a network for a problem's force mesh and fills the step's hook; a cola_status.
+int make_hook(const cola_problem* prob, const cola_lc_net* net, void* lc_ws, size_t lc_ws_bytes, LcHook& h) {
     int s;
     if ((s = check_problem(prob)) != COLA_OK) return s;
     if ((s = lc_check_net(net, false)) != COLA_OK) return s;
@@ -429,7 +482,7 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
     if (!lc_ws) return COLA_ERR_INVALID_ARG;
     const LcWsLayout LL = lc_ws_layout(ng, net->channels, prob->n_real, false);
     if (lc_ws_bytes < LL.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
-    LcHook h;
+    h.id = net->params;
     h.P = lc_params_of(net);
     h.A = lc_carve(lc_ws, LL);
     h.x0_stride = LL.x0_stride;
@@ -442,7 +495,45 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
         h.knot_a[i] = net->knot_a[i];
         h.knot_v[i] = net->knot_v[i];
     }
+    return COLA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_begin, int32_t j_end,
+                 cola_particles* io, const cola_lc_net* net, void* lc_ws, size_t lc_ws_bytes, void* ws,
+                 size_t ws_bytes, void* stream) {
+    LcHook h;
+    const int s = make_hook(prob, net, lc_ws, lc_ws_bytes, h);
+    if (s != COLA_OK) return s;
     return step_impl(prob, cosmo, j_begin, j_end, io, ws, ws_bytes, stream, &h);
+}
+
+int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const cola_lc_net* net, double a,
+                     void* lc_ws, size_t lc_ws_bytes, float* acc[3], void* ws, size_t ws_bytes, void* stream) {
+    LcHook h;
+    int s = make_hook(prob, net, lc_ws, lc_ws_bytes, h);
+    if (s != COLA_OK) return s;
+    if ((s = check_particles(in)) != COLA_OK) return s;
+    if (!acc || !acc[0] || !acc[1] || !acc[2] || !ws || !(a > 0.0) || !std::isfinite(a)) return COLA_ERR_INVALID_ARG;
+    Layout L = layout_of(*prob, 0);
+    if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ws w = carve(ws, L);
+    ParticlePtrs P = ptrs_of(in);
+    ws_forget(ws);
+    (void)hipGetLastError();
+    COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
+    COLA_TRY(compute_force(*prob, L, w, P, st, &h, a));
+    ForceMeshes f = force_meshes(w);
+    const long npr = (long)prob->n_part * prob->n_part * prob->n_part;
+    COLA_TRY(gather_force(P, npr, prob->n_real, force_geom(*prob, L), f.fx, f.fy, f.fz, acc, st));
+    return COLA_OK;
+}
+
+int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, int32_t width, int32_t use_static) {
+    return set_fft_shape(n, kind, values_per_thread, width, use_static != 0);
 }
 
 int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,
@@ -475,10 +566,14 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     COLA_TRY(launch_twiddles(w.twk, n_pk, st));
     if (!on_node) {
-        if (!(in->force_node == j && in->force_ws == ws)) {
+        // the force the state's own run used at node j (any network); without one cached, the
+        // plain mesh force is evaluated and cached
+        if (!ws_holds(ws, in, j, nullptr, true)) {
+            ws_forget(ws);
             COLA_TRY(compute_force(p, L, w, P, st));
             in->force_node = j;
             in->force_ws = ws;
+            ws_record(ws, in, j, nullptr);
         }
         Growth go = growth(a_out, sc.omega_m);
         kd.kick = (float)(1.5 * sc.omega_m * sc.k_out[j]);
@@ -578,24 +673,28 @@ int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo,
 // ---------------------------------------------------------------- component entry points
 
 size_t cola_cic_workspace_bytes(int64_t n, int32_t n_mesh) {
-    (void)n;
-    (void)n_mesh;
-    return 0;
+    if (n < 1 || n > (int64_t)INT32_MAX - 1 || n_mesh < 2 || n_mesh > kMaxMesh) return 0;
+    const TileGeom tg = make_tiles(n_mesh, (long)n);
+    if (tg.nkeys + 1 > (long)INT32_MAX) return 0;  // 32-bit tile keys
+    return sort_bytes((long)n, tg, 1);
 }
 
 int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box, float* delta, void* ws,
                      size_t ws_bytes, void* stream) {
-    (void)ws;
-    (void)ws_bytes;
-    if (!pos || !pos[0] || !pos[1] || !pos[2] || !delta || n < 1 || n_mesh < 2 || n_mesh > kMaxMesh ||
-        !(box > 0.0))
+    if (!pos || !pos[0] || !pos[1] || !pos[2] || !delta || !ws || n < 1 || n > (int64_t)INT32_MAX - 1 ||
+        n_mesh < 2 || n_mesh > kMaxMesh || !(box > 0.0) || !std::isfinite(box))
         return COLA_ERR_INVALID_ARG;
+    const size_t need = cola_cic_workspace_bytes(n, n_mesh);
+    if (need == 0) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (ws_bytes < need) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    long cells = (long)n_mesh * n_mesh * n_mesh;
+    const TileGeom tg = make_tiles(n_mesh, (long)n);
+    const SortBufs sb = carve_sort(ws, (long)n, tg, 1);
+    const double cells = (double)n_mesh * n_mesh * n_mesh;
+    ws_forget(ws);
     (void)hipGetLastError();
-    COLA_TRY(launch_fill(delta, cells, 0.0f, st));
-    COLA_TRY(cic_deposit_absolute(pos, n, n_mesh, (float)(n_mesh / box), n_mesh, delta, st));
-    COLA_TRY(density_finish(delta, n_mesh, n_mesh, (float)((double)cells / (double)n), -1.0f, st));
+    COLA_TRY(sorted_deposit_absolute(pos, (long)n, n_mesh, (float)(n_mesh / box), tg, sb, delta, n_mesh,
+                                     (float)(cells / (double)n), -1.0f, st));
     return COLA_OK;
 }
 
@@ -609,6 +708,7 @@ int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_by
     if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Ws w = carve(ws, L);
+    ws_forget(ws);
     std::string rep;
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
@@ -649,6 +749,7 @@ int cola_fft_r2c(int32_t n, const float* in, float* out, void* ws, size_t ws_byt
     Mesh3 g = make_mesh(n);
     float2* spec = static_cast<float2*>(ws);
     float2* tw = reinterpret_cast<float2*>(static_cast<char*>(ws) + align256(g.bytes()));
+    ws_forget(ws);
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(tw, n, st));
     COLA_TRY(fft3d_r2c(in, n, 0, spec, 0, g, tw, 1, 1.0f, 0.0f, st));
@@ -664,6 +765,7 @@ int cola_fft_c2r(int32_t n, const float* in, float* out, void* ws, size_t ws_byt
     Mesh3 g = make_mesh(n);
     float2* spec = static_cast<float2*>(ws);
     float2* tw = reinterpret_cast<float2*>(static_cast<char*>(ws) + align256(g.bytes()));
+    ws_forget(ws);
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(tw, n, st));
     COLA_TRY(copy_unpad_to_pad(reinterpret_cast<const float2*>(in), spec, g, st));

@@ -17,6 +17,13 @@ namespace cola {
 // Records the failing call and HIP error for cola_last_error; returns COLA_ERR_HIP.
 int hip_fail(hipError_t e, const char* what);
 
+// Force cache of a workspace (api.cpp): forget whatever force the workspace held (every call that
+// writes a workspace), record that it holds the force of state P at node `node` corrected by the
+// network with parameter array `net` (nullptr: plain), and ask whether it holds that force.
+void ws_forget(const void* ws);
+void ws_record(const void* ws, const cola_particles* P, int node, const void* net);
+bool ws_holds(const void* ws, const cola_particles* P, int node, const void* net, bool any_net);
+
 // ------------------------------------------------------------------ profiler (profiler.cpp)
 enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
@@ -83,6 +90,10 @@ FftPlan make_plan_r(int n, int R, bool reverse);
 hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw, hipStream_t st,
                         std::string* report);
 
+// Pins the kernel shape of one pass kind ("z_r2c", "z_c2r", "cols_y", "cols_x", "x_green",
+// "y_split", "x_mult") at mesh size n for the rest of the process; a cola_status.
+int set_fft_shape(int n, const char* kind, int R, int width, bool stat);
+
 // ------------------------------------------------------------------ launchers (fft.hip)
 hipError_t launch_twiddles(float2* tw, int len, hipStream_t st);
 
@@ -146,14 +157,6 @@ struct KickDrift {
 hipError_t launch_fill(float* p, long n, float v, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_fill_d(double* p, long n, double v, hipStream_t st);
-hipError_t cic_deposit_lagrangian(const ParticlePtrs& P, long n_per_real, int n_real,
-                                  const LatticeGeom& dep, float* mesh, hipStream_t st);
-// Deposit of positions drifted on the fly: x' = x + (p + kick * bracket(g)) * drift + dd1 psi1 + dd2 psi2,
-// g gathered from the force mesh (fgeom) -- for outputs between nodes.
-hipError_t cic_deposit_drifted(const ParticlePtrs& P, long n_per_real, int n_real,
-                               const LatticeGeom& fgeom, const float* fx, const float* fy,
-                               const float* fz, const KickDrift& kd, const LatticeGeom& dep,
-                               float* mesh, hipStream_t st);
 hipError_t cic_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, long row,
                                 float* mesh, hipStream_t st);
 hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float offset, hipStream_t st);
@@ -198,6 +201,12 @@ hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const Lat
                           const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
                           const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
                           float scale, float offset, hipStream_t st);
+
+// The same deposit for absolute positions pos[3] (n floats each, wrapped into the mesh), one
+// realization, onto a mesh of n_mesh cells per side with rows of `row` floats.
+hipError_t sorted_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, const TileGeom& tg,
+                                   const SortBufs& sb, float* mesh, long row, float scale, float offset,
+                                   hipStream_t st);
 
 // ------------------------------------------------------------------ launchers (ic_kernels.hip)
 hipError_t ic_noise(float* w, int n_part, const uint64_t* seeds_host, int n_real, long bstride,

@@ -172,6 +172,39 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
     (void)wave_increment(sb.count + (long)r * sb.kstride, key, valid);
 }
 
+// Binning of absolute positions (the component entry point): the cell of a coordinate is
+// floor(pos / H) modulo the mesh, the fraction pos / H minus that floor.  Everything after the
+// binning is the step's deposit.
+__global__ void k_dep_bin_abs(const float* px, const float* py, const float* pz, long n, int n_mesh, float inv_h,
+                              TileGeom tg, SortBufs sb) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < n;
+    uint32_t key = 0;
+    if (valid) {
+        const float* ps[3] = {px, py, pz};
+        CellC c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            // rounded product: contracted into u - floor(u) as one fused multiply-add, the
+            // fraction of a coordinate that rounds up to a node would come out negative
+            const float u = __fmul_rn(__builtin_nontemporal_load(ps[d] + p), inv_h);
+            const float fl = floorf(u);
+            c[d].f = u - fl;
+            int m = (int)fl % n_mesh;
+            m = m < 0 ? m + n_mesh : m;
+            c[d].m = min(max(m, 0), n_mesh - 1);
+        }
+        const int lx = c[0].m % tg.tx, ly = c[1].m % tg.ty, lz = c[2].m % tg.tz;
+        const long tile = ((long)(c[0].m / tg.tx) * tg.nty + c[1].m / tg.ty) * tg.ntz + c[2].m / tg.tz;
+        const int cat = ((lx == tg.tx - 1) ? 4 : 0) | ((ly == tg.ty - 1) ? 2 : 0) | ((lz == tg.tz - 1) ? 1 : 0);
+        key = (uint32_t)(tile * 8 + cat);
+        const int local = (((lx << tg.ly) + ly) << tg.lz) + lz;
+        __builtin_nontemporal_store(key, sb.keys + p);
+        store_rec_stream(sb.recs + p, make_float4(__int_as_float(local), c[0].f, c[1].f, c[2].f));
+    }
+    (void)wave_increment(sb.count, key, valid);
+}
+
 // Exclusive scan, phase 1: each block scans 1024 counts (4 per thread) and stores its total.
 __global__ void k_scan_blocks(const uint32_t* count, uint32_t* start, uint32_t* block_sums, long nkeys,
                               long kstride, int nblocks) {
@@ -356,8 +389,9 @@ __global__ void __launch_bounds__(256) k_dep_tile(TileGeom tg, SortBufs sb, long
                 for (int cz = 0; cz < 2; ++cz) {
                     const int uz = hz + cz;
                     if (uz < 0 || uz >= tg.tz) continue;
+                    // clamped at 0: the conversion of a negative weight would wrap to ~2^32
                     atomicAdd(&acc[(((ux << tg.ly) + uy) << tg.lz) + uz],
-                              __float2ull_rn(wx[cx] * wy[cy] * wz[cz] * 4294967296.0f));
+                              __float2ull_rn(fmaxf(wx[cx] * wy[cy] * wz[cz] * 4294967296.0f, 0.0f)));
                 }
             }
         }
@@ -420,6 +454,48 @@ SortBufs carve_sort(void* base, long npr, const TileGeom& tg, int n_real) {
     return s;
 }
 
+namespace {
+// Scan of the key counts, scatter of the records into key order, tile accumulation: the passes
+// after the binning, shared by the step's deposit and the deposit of absolute positions.
+hipError_t sort_and_tile(long npr, int n_real, const TileGeom& tg, const SortBufs& sb, float* mesh, long row,
+                         long mesh_bstride, float scale, float offset, hipStream_t st) {
+    const dim3 pgrid((unsigned)((npr + 255) / 256), n_real);
+    {
+        ProfScope ps(PROF_DEP_SORT, st);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(sb.nblocks, n_real), dim3(256), 0, st, sb.count, sb.start,
+                           sb.block_sums, tg.nkeys, sb.kstride, sb.nblocks);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1, n_real), dim3(1024), 0, st, sb.block_sums, sb.nblocks);
+        hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)((tg.nkeys + 1 + 255) / 256), n_real), dim3(256), 0, st,
+                           sb.start, sb.cursor, sb.block_sums, tg.nkeys, sb.kstride, sb.nblocks,
+                           (uint32_t)npr);
+        hipLaunchKernelGGL(k_dep_scatter, pgrid, dim3(256), 0, st, npr, sb);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(PROF_DEP_TILE, st);
+        size_t lds = (size_t)tg.tx * tg.ty * tg.tz * sizeof(unsigned long long);
+        hipLaunchKernelGGL(k_dep_tile, dim3((unsigned)tg.ntiles, n_real), dim3(256), lds, st, tg, sb, npr, mesh, row,
+                           mesh_bstride, scale, offset);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t sorted_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, const TileGeom& tg,
+                                   const SortBufs& sb, float* mesh, long row, float scale, float offset,
+                                   hipStream_t st) {
+    hipError_t e = launch_fill(reinterpret_cast<float*>(sb.count), sb.kstride, 0.0f, st);
+    if (e != hipSuccess) return e;
+    {
+        ProfScope ps(PROF_DEPOSIT, st);
+        hipLaunchKernelGGL(k_dep_bin_abs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos[0], pos[1], pos[2],
+                           n, n_mesh, inv_h, tg, sb);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return sort_and_tile(n, 1, tg, sb, mesh, row, 0, scale, offset, st);
+}
+
 hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg, bool drift,
                           const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
                           const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
@@ -436,25 +512,7 @@ hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const Lat
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    {
-        ProfScope ps(PROF_DEP_SORT, st);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(sb.nblocks, n_real), dim3(256), 0, st, sb.count, sb.start,
-                           sb.block_sums, tg.nkeys, sb.kstride, sb.nblocks);
-        hipLaunchKernelGGL(k_scan_totals, dim3(1, n_real), dim3(1024), 0, st, sb.block_sums, sb.nblocks);
-        hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)((tg.nkeys + 1 + 255) / 256), n_real), dim3(256), 0, st,
-                           sb.start, sb.cursor, sb.block_sums, tg.nkeys, sb.kstride, sb.nblocks,
-                           (uint32_t)npr);
-        hipLaunchKernelGGL(k_dep_scatter, pgrid, dim3(256), 0, st, npr, sb);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    {
-        ProfScope ps(PROF_DEP_TILE, st);
-        size_t lds = (size_t)tg.tx * tg.ty * tg.tz * sizeof(unsigned long long);
-        hipLaunchKernelGGL(k_dep_tile, dim3((unsigned)tg.ntiles, n_real), dim3(256), lds, st, tg, sb, npr, mesh,
-                           dg.row, dg.mesh_bstride, scale, offset);
-    }
-    return hipGetLastError();
+    return sort_and_tile(npr, n_real, tg, sb, mesh, dg.row, dg.mesh_bstride, scale, offset, st);
 }
 
 }  // namespace cola

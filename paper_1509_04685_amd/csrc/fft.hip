@@ -243,6 +243,22 @@ static FftShape shape_for(FftKind k, int n) {
     return default_shape(k, n);
 }
 
+// Pins the shape of one pass kind at mesh size n (what the autotuner would otherwise choose).
+int set_fft_shape(int n, const char* kind, int R, int width, bool stat) {
+    if (!kind || !fft_size_ok(n)) return COLA_ERR_INVALID_ARG;
+    int k = -1;
+    for (int i = 0; i < FK_NUM; ++i)
+        if (std::string(kind) == kFftKindName[i]) k = i;
+    if (k < 0) return COLA_ERR_INVALID_ARG;
+    const FftShape sh{R, width, stat};
+    if (!shape_ok((FftKind)k, n, sh)) return COLA_ERR_INVALID_ARG;
+    if (stat && !static_available((FftKind)k, n, R, width)) return COLA_ERR_INVALID_ARG;
+    ShapeCache& c = shape_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    c.tuned[{k, n}] = sh;
+    return COLA_OK;
+}
+
 // ------------------------------------------------------------------ launchers
 
 static ColGeom cols_y(const Mesh3& g, int tk) {

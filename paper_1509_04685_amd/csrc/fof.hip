@@ -368,6 +368,7 @@ int cola_fof(const float* pos[3], int64_t n, double box, double link, int32_t* g
     const FofWs w = fof_ws((long)n, g, ws);
     if (ws_bytes < w.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    ws_forget(ws);
     (void)hipGetLastError();
     const float link2 = (float)link * (float)link;
     ProfScope ps(PROF_FOF, st, g.nc);
@@ -399,6 +400,7 @@ int cola_fof_catalogue(const float* pos[3], int64_t n, double box, const int32_t
     const FofWs w = fof_ws((long)n, FofGrid{1, 1.0f, 1}, ws);
     if (ws_bytes < w.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    ws_forget(ws);
     (void)hipGetLastError();
     ProfScope ps(PROF_FOF, st, -1);
     uint32_t* flag = w.cell_of;

@@ -145,6 +145,7 @@ int cola_lc_forward(const cola_lc_net* net, int32_t n_mesh, const float* delta, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const LcActs A = lc_carve(ws, L);
     const LcParams P = lc_params_of(net);
+    ws_forget(ws);
     (void)hipGetLastError();
     LC_TRY(lc_pack(delta, g, n_mesh, n_mesh, net->in_scale, A.x0, st));
     LC_TRY(lc_forward(P, A, n_mesh, net->out_scale, net->out_band, df, n_mesh, accumulate ? 1 : 0, training != 0,
@@ -218,6 +219,7 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
     const long row = 2L * gm.nzp;
     float* s_real = reinterpret_cast<float*>(S);
     const double cells = (double)n_mesh * n_mesh * n_mesh;
+    ws_forget(ws);
     (void)hipGetLastError();
     LC_TRY(launch_twiddles(tw, n_mesh, st));
     LC_TRY(launch_fill(s_real, 2L * gm.total_c(), 0.0f, st));
@@ -231,6 +233,30 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
     if (g)
         for (int d = 0; d < 3; ++d) LC_TRY(mesh_unpad(f[d], row, n_mesh, g[d], st));
     if (acc) LC_TRY(gather_absolute(pos, n, n_mesh, box, f, row, acc, st));
+    return COLA_OK;
+}
+
+int cola_mesh_force(int32_t n_mesh, double box, const float* delta, float* g[3], void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!fft_size_ok(n_mesh) || n_mesh > kMaxLcMesh) return COLA_ERR_UNSUPPORTED_SIZE;
+    if (!(box > 0.0) || !std::isfinite(box) || !delta || !ptrs3(g) || !ws) return COLA_ERR_INVALID_ARG;
+    if (ws_bytes < cola_pm_fields_workspace_bytes(n_mesh)) return COLA_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Mesh3 gm = make_mesh(n_mesh);
+    char* b = static_cast<char*>(ws);
+    float2* S = reinterpret_cast<float2*>(b);
+    float2* A = reinterpret_cast<float2*>(b + lc_align(gm.bytes()));
+    float2* B = reinterpret_cast<float2*>(b + 2 * lc_align(gm.bytes()));
+    float2* tw = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
+    const long row = 2L * gm.nzp;
+    ws_forget(ws);
+    (void)hipGetLastError();
+    LC_TRY(launch_twiddles(tw, n_mesh, st));
+    LC_TRY(fft_zy_forward(delta, n_mesh, 0, S, 0, gm, tw, 1, 1.0f, 0.0f, st));
+    LC_TRY(pm_force_from_spectrum(S, A, B, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
+    const float* f[3] = {reinterpret_cast<const float*>(B), reinterpret_cast<const float*>(A),
+                         reinterpret_cast<const float*>(S)};
+    for (int d = 0; d < 3; ++d) LC_TRY(mesh_unpad(f[d], row, n_mesh, g[d], st));
     return COLA_OK;
 }
 

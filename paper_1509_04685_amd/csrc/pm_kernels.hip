@@ -131,72 +131,6 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
 
 // ------------------------------------------------------------------ CIC deposit
 
-__global__ void k_deposit_lagr(ParticlePtrs P, long npr, int n_real, LatticeGeom dg, float* mesh) {
-    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= npr * n_real) return;
-    long r = gid / npr, p = gid - r * npr;
-    int i, j, l;
-    lagr_index((uint32_t)p, dg.n_part, i, j, l);
-    Cell cx = cell_of(i, P.x[0][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
-    Cell cy = cell_of(j, P.x[1][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
-    Cell cz = cell_of(l, P.x[2][gid], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
-    deposit8(mesh + r * dg.mesh_bstride, dg.row, dg.n_mesh, cx, cy, cz);
-}
-
-hipError_t cic_deposit_lagrangian(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg,
-                                  float* mesh, hipStream_t st) {
-    long n = npr * n_real;
-    ProfScope ps(PROF_DEPOSIT, st);
-    hipLaunchKernelGGL(k_deposit_lagr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
-                       dg, mesh);
-    return hipGetLastError();
-}
-
-__device__ __forceinline__ float bracket(float g, float d1, float d2m, float s1, float s2) {
-    return g - d1 * s1 - d2m * s2;
-}
-
-__global__ void k_deposit_drifted(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* fx,
-                                  const float* fy, const float* fz, KickDrift kd, LatticeGeom dg,
-                                  float* mesh) {
-    long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= npr * n_real) return;
-    long r = gid / npr, p = gid - r * npr;
-    int idx[3];
-    lagr_index((uint32_t)p, fg.n_part, idx[0], idx[1], idx[2]);
-    float x[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) x[d] = P.x[d][gid];
-    if (kd.drift != 0.0f || kd.dd1 != 0.0f) {
-        Cell c[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
-        float g[3];
-        long mo = r * fg.mesh_bstride;
-        gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            float s1 = P.psi1[d][gid], s2 = P.psi2[d][gid];
-            float ph = P.p[d][gid] + kd.kick * bracket(g[d], kd.d1, kd.d2m, s1, s2);
-            x[d] = x[d] + ph * kd.drift + kd.dd1 * s1 + kd.dd2 * s2;
-        }
-    }
-    Cell c[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], x[d], dg.n_part, dg.n_mesh, dg.inv_h, dg.qoff);
-    deposit8(mesh + r * dg.mesh_bstride, dg.row, dg.n_mesh, c[0], c[1], c[2]);
-}
-
-hipError_t cic_deposit_drifted(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg,
-                               const float* fx, const float* fy, const float* fz, const KickDrift& kd,
-                               const LatticeGeom& dg, float* mesh, hipStream_t st) {
-    long n = npr * n_real;
-    ProfScope ps(PROF_PK_DEPOSIT, st);
-    hipLaunchKernelGGL(k_deposit_drifted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
-                       fg, fx, fy, fz, kd, dg, mesh);
-    return hipGetLastError();
-}
-
 __global__ void k_deposit_abs(const float* px, const float* py, const float* pz, long n, int n_mesh,
                               float inv_h, long row, float* mesh) {
     long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,7 +139,7 @@ __global__ void k_deposit_abs(const float* px, const float* py, const float* pz,
     const float* ps[3] = {px, py, pz};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        float u = ps[d][gid] * inv_h;
+        float u = __fmul_rn(ps[d][gid], inv_h);  // rounded, so that u - floor(u) >= 0
         float fl = floorf(u);
         c[d].f = u - fl;
         int m = (int)fl % n_mesh;
@@ -242,6 +176,10 @@ hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float 
 }
 
 // ------------------------------------------------------------------ gather + kick + drift
+
+__device__ __forceinline__ float bracket(float g, float d1, float d2m, float s1, float s2) {
+    return g - d1 * s1 - d2m * s2;
+}
 
 // p += kick [g - D1 psi1 - (D2 - D1^2) psi2];  x += p Dr + dD1 psi1 + dD2 psi2.
 // Grid: (particle blocks, realizations).  Every particle array is read before the first store, so
