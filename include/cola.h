@@ -314,6 +314,17 @@ int cola_step_lc(const cola_problem* prob, const cola_cosmology* cosmo, int32_t 
 int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const cola_lc_net* net, double a,
                      void* lc_ws, size_t lc_ws_bytes, float* acc[3], void* ws, size_t ws_bytes, void* stream);
 
+/* cola_pm_force for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same passes and the same result, with
+ * the workspace taken from a fixed 64 MiB device array that the library holds on each GPU until
+ * the process ends, instead of a caller buffer.  The caller still passes the state and acc.
+ * Problems whose cola_workspace_bytes(prob, 0) exceeds 64 MiB (for example a 128^3 mesh with more
+ * than about 96^3 particles) return COLA_ERR_WORKSPACE_TOO_SMALL before any launch.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race, and a state's cached force is never kept in it.  No hipMalloc, hipFree or other
+ * allocating call is made. */
+int cola_pm_force_noalloc(const cola_problem* prob, const cola_particles* in, float* acc[3], void* stream);
+
 /* Mesh fields of arbitrary particles: CIC of the absolute positions pos[3] (device, n floats
  * each, any real, wrapped into the box) onto n_mesh^3 cells, delta = rho / rho_bar - 1, the force
  * g_k = i k delta_k / k^2 as in cola_pm_force, and its CIC interpolation to the particles.  Each

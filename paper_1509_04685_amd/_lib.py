@@ -28,7 +28,7 @@ EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
            "cola_pm_fields_workspace_bytes", "cola_pm_fields", "cola_positions", "cola_mfma_selftest",
            "cola_profiler_read_groups", "cola_fof_workspace_bytes", "cola_fof", "cola_fof_catalogue",
            "cola_fof_mass_histogram", "cola_particle_mass", "cola_power_multipoles", "cola_pm_force_lc",
-           "cola_mesh_force", "cola_fft_set_shape")
+           "cola_mesh_force", "cola_fft_set_shape", "cola_pm_force_noalloc")
 
 
 class ColaError(RuntimeError):
@@ -136,6 +136,7 @@ def _load():
         "cola_fof_mass_histogram": (ctypes.c_int, [vp, i64, i32, dbl, ctypes.POINTER(dbl), i32, vp, vp]),
         "cola_particle_mass": (dbl, [C, dbl, i32]),
         "cola_pm_force_lc": (ctypes.c_int, [P, PP, N, dbl, vp, sz, ctypes.POINTER(vp), vp, sz, vp]),
+        "cola_pm_force_noalloc": (ctypes.c_int, [P, PP, ctypes.POINTER(vp), vp]),
         "cola_mesh_force": (ctypes.c_int, [i32, dbl, vp, ctypes.POINTER(vp), vp, sz, vp]),
         "cola_fft_set_shape": (ctypes.c_int, [i32, ctypes.c_char_p, i32, i32, i32]),
         "cola_power_multipoles": (ctypes.c_int, [P, C, PP, dbl, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
