@@ -49,7 +49,9 @@ typedef enum {
     COLA_ERR_WORKSPACE_TOO_SMALL = -3,
     COLA_ERR_HIP = -4,                /* a HIP runtime call failed                         */
     COLA_ERR_STATE = -5,              /* particle state does not fit the call (node range)  */
-    COLA_ERR_NONFINITE = -6           /* a non-finite value was found where checked         */
+    COLA_ERR_NONFINITE = -6           /* a floating-point argument is NaN or infinite (box,
+                                         z_init, a_final, sampling power, cosmology, a_out,
+                                         network scales and knots, masses, mass edges)       */
 } cola_status;
 
 /* Flat LCDM, Omega_L = 1 - Omega_m, no radiation (Sec. 2.1: Omega_m 0.25, Omega_b 0.044,

@@ -118,7 +118,10 @@ Layout layout_of(const cola_problem& p, int n_pk) {
 
 int check_problem(const cola_problem* p) {
     if (!p) return COLA_ERR_INVALID_ARG;
-    if (!(p->box > 0.0) || !std::isfinite(p->box)) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(p->box) || !std::isfinite(p->z_init) || !std::isfinite(p->a_final) ||
+        (p->sampling == 2 && !std::isfinite(p->sampling_power)))
+        return COLA_ERR_NONFINITE;
+    if (!(p->box > 0.0)) return COLA_ERR_INVALID_ARG;
     if (p->n_part < 2 || p->pm_factor < 1 || p->n_real < 1) return COLA_ERR_INVALID_ARG;
     if (p->n_steps < 2 || p->sampling < 0 || p->sampling > 2) return COLA_ERR_INVALID_ARG;
     if (p->sampling == 2 && (!std::isfinite(p->sampling_power) || !(p->sampling_power > 0.0)))
@@ -134,6 +137,9 @@ int check_problem(const cola_problem* p) {
 
 int check_cosmo(const cola_cosmology* c) {
     if (!c) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(c->omega_m) || !std::isfinite(c->omega_b) || !std::isfinite(c->h) || !std::isfinite(c->n_s) ||
+        !std::isfinite(c->sigma_8))
+        return COLA_ERR_NONFINITE;
     if (!(c->omega_m > 0.0 && c->omega_m <= 1.0) || !(c->h > 0.0) || !(c->sigma_8 > 0.0) ||
         !(c->omega_b >= 0.0 && c->omega_b < c->omega_m) || !std::isfinite(c->n_s))
         return COLA_ERR_INVALID_ARG;
@@ -347,7 +353,7 @@ const char* cola_status_string(int status) {
         case COLA_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
         case COLA_ERR_HIP: return "HIP runtime error";
         case COLA_ERR_STATE: return "particle state does not fit the call (node range)";
-        case COLA_ERR_NONFINITE: return "non-finite value";
+        case COLA_ERR_NONFINITE: return "non-finite floating-point argument (NaN or infinity)";
         default: return "unknown status";
     }
 }
@@ -516,7 +522,8 @@ int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const c
     int s = make_hook(prob, net, lc_ws, lc_ws_bytes, h);
     if (s != COLA_OK) return s;
     if ((s = check_particles(in)) != COLA_OK) return s;
-    if (!acc || !acc[0] || !acc[1] || !acc[2] || !ws || !(a > 0.0) || !std::isfinite(a)) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(a)) return COLA_ERR_NONFINITE;
+    if (!acc || !acc[0] || !acc[1] || !acc[2] || !ws || !(a > 0.0)) return COLA_ERR_INVALID_ARG;
     Layout L = layout_of(*prob, 0);
     if (ws_bytes < L.total) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -544,6 +551,7 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
     if ((s = check_particles(in)) != COLA_OK) return s;
     if (!k_mean || !pk || !n_modes || !ws) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(a_out)) return COLA_ERR_NONFINITE;
     if (n_bins < 1 || n_bins > 4096) return COLA_ERR_INVALID_ARG;
     if (!fft_size_ok(n_pk) || n_pk > kMaxMesh) return COLA_ERR_UNSUPPORTED_SIZE;
     if (in->node < 0 || in->node >= prob->n_steps) return COLA_ERR_STATE;
@@ -617,6 +625,7 @@ int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo,
     if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
     if ((s = check_particles(in)) != COLA_OK) return s;
     if (!k_mean || !p0 || !p2 || !p4 || !n_modes || !ws) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(a_out)) return COLA_ERR_NONFINITE;
     if (n_bins < 1 || n_bins > 4096 || los < 0 || los > 2) return COLA_ERR_INVALID_ARG;
     if (!fft_size_ok(n_pk) || n_pk > kMaxMesh) return COLA_ERR_UNSUPPORTED_SIZE;
     if (in->node < 0 || in->node >= prob->n_steps) return COLA_ERR_STATE;
@@ -681,8 +690,9 @@ size_t cola_cic_workspace_bytes(int64_t n, int32_t n_mesh) {
 
 int cola_cic_density(const float* pos[3], int64_t n, int32_t n_mesh, double box, float* delta, void* ws,
                      size_t ws_bytes, void* stream) {
+    if (!std::isfinite(box)) return COLA_ERR_NONFINITE;
     if (!pos || !pos[0] || !pos[1] || !pos[2] || !delta || !ws || n < 1 || n > (int64_t)INT32_MAX - 1 ||
-        n_mesh < 2 || n_mesh > kMaxMesh || !(box > 0.0) || !std::isfinite(box))
+        n_mesh < 2 || n_mesh > kMaxMesh || !(box > 0.0))
         return COLA_ERR_INVALID_ARG;
     const size_t need = cola_cic_workspace_bytes(n, n_mesh);
     if (need == 0) return COLA_ERR_UNSUPPORTED_SIZE;

@@ -361,6 +361,7 @@ size_t cola_fof_workspace_bytes(int64_t n, double box, double link) {
 
 int cola_fof(const float* pos[3], int64_t n, double box, double link, int32_t* group, int32_t* group_size, void* ws,
              size_t ws_bytes, void* stream) {
+    if (!std::isfinite(box) || !std::isfinite(link)) return COLA_ERR_NONFINITE;
     if (!pos_ok(pos, (long)n) || !std::isfinite(box) || !(box > 0.0) || !std::isfinite(link) || !(link > 0.0) ||
         !(link < 0.5 * box) || !group || !group_size || !ws)
         return COLA_ERR_INVALID_ARG;
@@ -391,6 +392,7 @@ int cola_fof_catalogue(const float* pos[3], int64_t n, double box, const int32_t
                        int32_t n_min, double particle_mass, int64_t max_halos, int32_t* halo_root, int32_t* halo_n,
                        double* halo_mass, double* halo_com[3], int64_t* n_halos, void* ws, size_t ws_bytes,
                        void* stream) {
+    if (!std::isfinite(box) || !std::isfinite(particle_mass)) return COLA_ERR_NONFINITE;
     if (!pos_ok(pos, (long)n) || !std::isfinite(box) || !(box > 0.0) || !group || !group_size || n_min < 1 ||
         !std::isfinite(particle_mass) || !(particle_mass > 0.0) || !halo_root || !halo_n || !halo_mass ||
         !halo_com || !halo_com[0] || !halo_com[1] || !halo_com[2] || !n_halos || !ws)
@@ -421,6 +423,7 @@ int cola_fof_catalogue(const float* pos[3], int64_t n, double box, const int32_t
 
 int cola_fof_mass_histogram(const int32_t* group_size, int64_t n, int32_t n_min, double particle_mass,
                             const double* log10_mass_edges, int32_t n_bins, uint64_t* counts, void* stream) {
+    if (!std::isfinite(particle_mass)) return COLA_ERR_NONFINITE;
     if (!group_size || n < 1 || n > (int64_t)INT32_MAX - 1 || n_min < 1 || !std::isfinite(particle_mass) ||
         !(particle_mass > 0.0) || !log10_mass_edges || n_bins < 1 || n_bins > kFofMaxBins || !counts)
         return COLA_ERR_INVALID_ARG;
@@ -428,7 +431,8 @@ int cola_fof_mass_histogram(const int32_t* group_size, int64_t n, int32_t n_min,
     mb.nb = n_bins;
     for (int b = 0; b <= n_bins; ++b) {
         const double e = log10_mass_edges[b];
-        if (!std::isfinite(e) || (b > 0 && !(e > log10_mass_edges[b - 1]))) return COLA_ERR_INVALID_ARG;
+        if (!std::isfinite(e)) return COLA_ERR_NONFINITE;
+        if (b > 0 && !(e > log10_mass_edges[b - 1])) return COLA_ERR_INVALID_ARG;
         mb.lo[b] = std::max(first_n_reaching(std::pow(10.0, e), particle_mass), n_min);
     }
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -53,12 +53,12 @@ int lc_check_net(const cola_lc_net* net, bool training) {
     if (!net || !net->params || !net->packed) return COLA_ERR_INVALID_ARG;
     if (net->channels != 16 && net->channels != 32) return COLA_ERR_INVALID_ARG;
     for (int i = 0; i < 4; ++i)
-        if (!std::isfinite(net->in_scale[i])) return COLA_ERR_INVALID_ARG;
+        if (!std::isfinite(net->in_scale[i])) return COLA_ERR_NONFINITE;
     if (!std::isfinite(net->out_scale) || !std::isfinite(net->out_scale_slope) || !std::isfinite(net->out_band))
-        return COLA_ERR_INVALID_ARG;
+        return COLA_ERR_NONFINITE;
     if (net->n_knots != 0 && (net->n_knots < 2 || net->n_knots > 8)) return COLA_ERR_INVALID_ARG;
     for (int i = 0; i < net->n_knots; ++i) {
-        if (!std::isfinite(net->knot_a[i]) || !std::isfinite(net->knot_v[i])) return COLA_ERR_INVALID_ARG;
+        if (!std::isfinite(net->knot_a[i]) || !std::isfinite(net->knot_v[i])) return COLA_ERR_NONFINITE;
         if (i > 0 && !(net->knot_a[i] > net->knot_a[i - 1])) return COLA_ERR_INVALID_ARG;
     }
     if (training && (!net->grads || !net->adam_m || !net->adam_v)) return COLA_ERR_INVALID_ARG;
@@ -175,7 +175,8 @@ int cola_lc_backward(const cola_lc_net* net, int32_t n_mesh, const float* d_df, 
 
 int cola_lc_loss(int32_t n_mesh, double box, const float* pos[3], int64_t n, const float* df[3], const float* g1[3],
                  const float* g3[3], double* stats, float* d_df, void* stream) {
-    if (n_mesh < 2 || n_mesh > kMaxLcMesh || !(box > 0.0) || !std::isfinite(box) || n < 1) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(box)) return COLA_ERR_NONFINITE;
+    if (n_mesh < 2 || n_mesh > kMaxLcMesh || !(box > 0.0) || n < 1) return COLA_ERR_INVALID_ARG;
     if (!ptrs3(pos) || !ptrs3(df) || !ptrs3(g1) || !ptrs3(g3) || !stats || !d_df) return COLA_ERR_INVALID_ARG;
     (void)hipGetLastError();
     LC_TRY(lc_loss(pos, n, n_mesh, box, df, g1, g3, stats, d_df, static_cast<hipStream_t>(stream)));
@@ -205,7 +206,8 @@ size_t cola_pm_fields_workspace_bytes(int32_t n_mesh) {
 int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, float* delta, float* g[3],
                    float* acc[3], void* ws, size_t ws_bytes, void* stream) {
     if (!fft_size_ok(n_mesh) || n_mesh > kMaxLcMesh) return COLA_ERR_UNSUPPORTED_SIZE;
-    if (!(box > 0.0) || !std::isfinite(box) || n < 1 || !ptrs3(pos) || !ws) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(box)) return COLA_ERR_NONFINITE;
+    if (!(box > 0.0) || n < 1 || !ptrs3(pos) || !ws) return COLA_ERR_INVALID_ARG;
     if (g && !(g[0] && g[1] && g[2])) return COLA_ERR_INVALID_ARG;
     if (acc && !(acc[0] && acc[1] && acc[2])) return COLA_ERR_INVALID_ARG;
     if (ws_bytes < cola_pm_fields_workspace_bytes(n_mesh)) return COLA_ERR_WORKSPACE_TOO_SMALL;
@@ -239,7 +241,8 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
 int cola_mesh_force(int32_t n_mesh, double box, const float* delta, float* g[3], void* ws, size_t ws_bytes,
                     void* stream) {
     if (!fft_size_ok(n_mesh) || n_mesh > kMaxLcMesh) return COLA_ERR_UNSUPPORTED_SIZE;
-    if (!(box > 0.0) || !std::isfinite(box) || !delta || !ptrs3(g) || !ws) return COLA_ERR_INVALID_ARG;
+    if (!std::isfinite(box)) return COLA_ERR_NONFINITE;
+    if (!(box > 0.0) || !delta || !ptrs3(g) || !ws) return COLA_ERR_INVALID_ARG;
     if (ws_bytes < cola_pm_fields_workspace_bytes(n_mesh)) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Mesh3 gm = make_mesh(n_mesh);

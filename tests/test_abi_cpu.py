@@ -184,3 +184,47 @@ def test_particle_mass_matches_oracle():
         ref = ocosmo.particle_mass(ocosmo.Cosmology(), box, n)
         assert got == pytest.approx(ref, rel=1e-14)
     assert cola.particle_mass(COSMO, -1.0, 8) == 0.0
+
+
+def test_nonfinite_arguments_return_nonfinite():
+    """COLA_ERR_NONFINITE (-6): a NaN or infinite floating-point argument is found by the host
+    checks, before anything is launched (no device is touched; every pointer here is fake)."""
+    nan, inf = float("nan"), float("inf")
+    fake = ctypes.c_void_p(0x1000)
+    st = cola.Particles()
+    for d in range(3):
+        st.x[d] = st.p[d] = st.psi1[d] = st.psi2[d] = 0x1000
+    seeds = (ctypes.c_uint64 * 1)(1)
+    for kw in (dict(box=nan), dict(z_init=inf), dict(a_final=nan)):
+        p = prob()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        assert LIB.cola_ic_2lpt(ctypes.byref(p), ctypes.byref(COSMO), seeds, ctypes.byref(st), fake, 1 << 40,
+                                None) == -6, kw
+        assert LIB.cola_step(ctypes.byref(p), ctypes.byref(COSMO), 0, 1, ctypes.byref(st), fake, 1 << 40, None) == -6
+    p = cola.make_problem(256.0, 32, 3, 19.0, 10, sampling="power", sampling_power=2.0)
+    p.sampling_power = nan
+    assert LIB.cola_step(ctypes.byref(p), ctypes.byref(COSMO), 0, 1, ctypes.byref(st), fake, 1 << 40, None) == -6
+    for bad in (cola.make_cosmology(omega_m=nan), cola.make_cosmology(sigma_8=inf), cola.make_cosmology(n_s=nan)):
+        assert LIB.cola_step(ctypes.byref(prob()), ctypes.byref(bad), 0, 1, ctypes.byref(st), fake, 1 << 40,
+                             None) == -6
+    out = ctypes.c_void_p(0x2000)
+    assert LIB.cola_power_spectrum(ctypes.byref(prob()), ctypes.byref(COSMO), ctypes.byref(st), nan, 96, 48,
+                                   out, out, out, fake, 1 << 40, None) == -6
+    P3 = ctypes.c_void_p * 3
+    pos = P3(0x1000, 0x2000, 0x3000)
+    assert LIB.cola_cic_density(pos, 1000, 32, inf, fake, fake, 1 << 30, None) == -6
+    assert LIB.cola_fof(pos, 1000, 100.0, nan, fake, fake, fake, 1 << 30, None) == -6
+    edges = (ctypes.c_double * 3)(13.0, nan, 15.0)
+    assert LIB.cola_fof_mass_histogram(fake, 1000, 101, 1e12, edges, 2, fake, None) == -6
+    assert LIB.cola_mesh_force(32, nan, fake, P3(0x1000, 0x1000, 0x1000), fake, 1 << 30, None) == -6
+    # the network's scales: a NaN output scale
+    net = cola._lib.LcNet()
+    net.channels = 16
+    net.params = 0x1000
+    net.packed = 0x1000
+    net.out_scale = nan
+    p1 = cola.make_problem(64.0, 16, 1, 19.0, 5)
+    assert LIB.cola_step_lc(ctypes.byref(p1), ctypes.byref(COSMO), 0, 1, ctypes.byref(st), ctypes.byref(net), fake,
+                            1 << 40, fake, 1 << 40, None) == -6
+    assert LIB.cola_status_string(-6)
