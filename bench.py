@@ -74,7 +74,8 @@ def algorithmic_bytes(kind, tag, n_g, n_part):
         "fft_y_split": 8 * C + 16 * C,          # one in, two out
         "fft_y_inverse": 16 * C,
         "fft_z_c2r": 8 * C + 4 * G,
-        "gather_kick_drift": 12 * G + 72 * N,   # 3 force meshes; x,p,psi1,psi2 in; x,p out
+        "gather_kick_drift": 12 * G + 92 * N,   # 3 force meshes; x,p,psi1,psi2 in; x,p out; key +
+                                                # record of the next deposit out (binning fused in)
         "gather_kick": 12 * G + 60 * N,
         "pk_deposit": 12 * G + 68 * N,          # binning with the partial drift: x, p, psi1, psi2 and
                                                 # the force meshes in; key + record out

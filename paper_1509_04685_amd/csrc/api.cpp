@@ -73,15 +73,19 @@ constexpr int kMaxMesh = 1536;  // keeps per-realization mesh offsets below 2^31
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Workspace: four mesh buffers S, A, B, C (real fields or transposed spectra; the z passes are
+// out of place), two P(k) buffers K (the deposit) and K2 (its spectrum), the deposit's sort
+// buffers and the twiddle tables.  After a force evaluation F_x, F_y, F_z are in C, B, A.
 struct Layout {
     Mesh3 g;   // force mesh, N_g
     Mesh3 gp;  // Lagrangian lattice, N_p
     Mesh3 gk;  // P(k) mesh (n = 0 when absent)
-    long cstride = 0;  // float2 per realization in S, A, B
-    long kstride = 0;  // float2 per realization in K
+    long cstride = 0;  // float2 per realization in S, A, B, C
+    long kstride = 0;  // float2 per realization in K, K2
     TileGeom tg;  // force-mesh tiles of the deposit
     TileGeom tk;  // P(k)-mesh tiles
-    size_t off_s = 0, off_a = 0, off_b = 0, off_k = 0, off_twg = 0, off_twp = 0, off_twk = 0, off_sort = 0;
+    size_t off_s = 0, off_a = 0, off_b = 0, off_c = 0, off_k = 0, off_k2 = 0, off_twg = 0, off_twp = 0,
+           off_twk = 0, off_sort = 0;
     size_t total = 0;
 };
 
@@ -95,11 +99,13 @@ Layout layout_of(const cola_problem& p, int n_pk) {
     L.off_s = off; off += cb;
     L.off_a = off; off += cb;
     L.off_b = off; off += cb;
+    L.off_c = off; off += cb;
     if (n_pk > 0) {
         L.gk = make_mesh(n_pk);
         L.kstride = L.gk.total_c();
-        L.off_k = off;
-        off += align256((size_t)L.kstride * sizeof(float2) * p.n_real);
+        const size_t kb = align256((size_t)L.kstride * sizeof(float2) * p.n_real);
+        L.off_k = off; off += kb;
+        L.off_k2 = off; off += kb;
     }
     const long npr = (long)p.n_part * p.n_part * p.n_part;
     L.tg = make_tiles(L.g.n, npr);
@@ -165,7 +171,7 @@ ParticlePtrs ptrs_of(const cola_particles* P) {
 }
 
 struct Ws {
-    float2 *S, *A, *B, *K, *twg, *twp, *twk;
+    float2 *S, *A, *B, *C, *K, *K2, *twg, *twp, *twk;
     void* sort;
 };
 
@@ -175,7 +181,9 @@ Ws carve(void* ws, const Layout& L) {
     w.S = reinterpret_cast<float2*>(b + L.off_s);
     w.A = reinterpret_cast<float2*>(b + L.off_a);
     w.B = reinterpret_cast<float2*>(b + L.off_b);
+    w.C = reinterpret_cast<float2*>(b + L.off_c);
     w.K = L.kstride ? reinterpret_cast<float2*>(b + L.off_k) : nullptr;
+    w.K2 = L.kstride ? reinterpret_cast<float2*>(b + L.off_k2) : nullptr;
     w.twg = reinterpret_cast<float2*>(b + L.off_twg);
     w.twp = reinterpret_cast<float2*>(b + L.off_twp);
     w.twk = reinterpret_cast<float2*>(b + L.off_twk);
@@ -227,16 +235,20 @@ struct LcHook {
 };
 
 // Density, forward transform and force meshes for the current positions.  Force meshes end up
-// as real rows in B (x), A (y), S (z); with a network hook, dF is added to them.
+// as real rows in C (x), B (y), A (z); with a network hook, dF is added to them.  binned: the
+// particles were already binned for this deposit (gather_kick_drift_bin).
 hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, const ParticlePtrs& P,
-                         hipStream_t st, const LcHook* lc = nullptr, double a_node = 1.0) {
+                         hipStream_t st, const LcHook* lc = nullptr, double a_node = 1.0, bool binned = false) {
     const long npr = (long)p.n_part * p.n_part * p.n_part;
     LatticeGeom fg = force_geom(p, L);
     const double cells = (double)L.g.n * L.g.n * L.g.n;
     SortBufs sb = carve_sort(w.sort, npr, L.tg, p.n_real);
     KickDrift none{};
-    hipError_t e = sorted_deposit(P, npr, p.n_real, fg, false, fg, nullptr, nullptr, nullptr, none, L.tg, sb,
-                                  reinterpret_cast<float*>(w.S), (float)(cells / (double)npr), -1.0f, st);
+    float* dens = reinterpret_cast<float*>(w.S);
+    const float dscale = (float)(cells / (double)npr);
+    hipError_t e = binned ? sorted_deposit_binned(npr, p.n_real, fg, L.tg, sb, dens, dscale, -1.0f, st)
+                          : sorted_deposit(P, npr, p.n_real, fg, false, fg, nullptr, nullptr, nullptr, none, L.tg, sb,
+                                           dens, dscale, -1.0f, st);
     if (e != hipSuccess) return e;
     const long row = 2L * L.g.nzp, bs = 2L * L.cstride;
     if (lc)
@@ -244,27 +256,29 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
             if ((e = lc_pack_delta(reinterpret_cast<const float*>(w.S) + r * bs, row, L.g.n, lc->in_scale[0],
                                    lc->A.x0 + r * lc->x0_stride, st)) != hipSuccess)
                 return e;
-    e = fft_zy_forward(reinterpret_cast<const float*>(w.S), row, bs, w.S, L.cstride, L.g, w.twg, p.n_real, 1.0f,
+    e = fft_zy_forward(reinterpret_cast<const float*>(w.S), row, bs, w.A, L.cstride, L.g, w.twg, p.n_real, 1.0f,
                        0.0f, st);
     if (e != hipSuccess) return e;
-    e = pm_force_from_spectrum(w.S, w.A, w.B, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real, st);
+    e = pm_force_from_spectrum(w.A, w.B, w.S, w.C, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real,
+                               st);
     if (e != hipSuccess || !lc) return e;
     for (int r = 0; r < p.n_real; ++r) {
-        float* f[3] = {reinterpret_cast<float*>(w.B) + r * bs, reinterpret_cast<float*>(w.A) + r * bs,
-                       reinterpret_cast<float*>(w.S) + r * bs};
+        float* f[3] = {reinterpret_cast<float*>(w.C) + r * bs, reinterpret_cast<float*>(w.B) + r * bs,
+                       reinterpret_cast<float*>(w.A) + r * bs};
         if ((e = lc_forward_fields(lc->P, lc->A.a1, lc->A.x0 + r * lc->x0_stride, f, row, L.g.n, lc->in_scale,
                                    lc->scale_at(a_node), lc->out_band, lc->A.t, st)) != hipSuccess)
             return e;
     }
-    return hipSuccess;
+    float* f[3] = {reinterpret_cast<float*>(w.C), reinterpret_cast<float*>(w.B), reinterpret_cast<float*>(w.A)};
+    return mesh_ghosts(f, row, L.g.n, bs, p.n_real, st);  // the gathers read z pairs through the ghosts
 }
 
 struct ForceMeshes {
     const float *fx, *fy, *fz;
 };
 ForceMeshes force_meshes(const Ws& w) {
-    return {reinterpret_cast<const float*>(w.B), reinterpret_cast<const float*>(w.A),
-            reinterpret_cast<const float*>(w.S)};
+    return {reinterpret_cast<const float*>(w.C), reinterpret_cast<const float*>(w.B),
+            reinterpret_cast<const float*>(w.A)};
 }
 
 // With the LPT frame switched off (PM only) the kick uses g alone and the drift p alone: the
@@ -320,8 +334,9 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
         kd.drift = (float)sc.drift[j];
         kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
         kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
-        COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, frame_terms(kd, p), st));
-        COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j + 1]));
+        COLA_TRY(gather_kick_drift_bin(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, frame_terms(kd, p), L.tg,
+                                       carve_sort(w.sort, npr, L.tg, p.n_real), st));
+        COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j + 1], true));
         pending = sc.k_in[j];
     }
     KickDrift kd{};
@@ -604,13 +619,13 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     SortBufs sb = carve_sort(w.sort, npr, L.tk, p.n_real);
     COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, !on_node, fg, f.fx, f.fy, f.fz, kd, L.tk, sb,
                             reinterpret_cast<float*>(w.K), (float)(cells / (double)npr), -1.0f, st));
-    COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K, L.kstride, gk, w.twk,
+    COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K2, L.kstride, gk, w.twk,
                        p.n_real, 1.0f, 0.0f, st));
     const long nb = (long)n_bins * p.n_real;
     COLA_TRY(launch_fill_d(k_mean, nb, 0.0, st));
     COLA_TRY(launch_fill_d(pk, nb, 0.0, st));
     COLA_TRY(launch_fill_d(n_modes, nb, 0.0, st));
-    COLA_TRY(pk_bin(w.K, L.kstride, gk, p.n_real, n_bins, k_mean, pk, n_modes, 2.0 * M_PI / p.box, st));
+    COLA_TRY(pk_bin(w.K2, L.kstride, gk, p.n_real, n_bins, k_mean, pk, n_modes, 2.0 * M_PI / p.box, st));
     double pnorm = p.box * p.box * p.box / (cells * cells);
     COLA_TRY(pk_finish(k_mean, pk, n_modes, nb, pnorm, st));
     return COLA_OK;
@@ -669,11 +684,11 @@ int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo,
     SortBufs sb = carve_sort(w.sort, npr, L.tk, p.n_real);
     COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, redshift_space != 0, fg, f.fx, f.fy, f.fz, kd, L.tk, sb,
                             reinterpret_cast<float*>(w.K), (float)(cells / (double)npr), -1.0f, st));
-    COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K, L.kstride, gk, w.twk,
+    COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K2, L.kstride, gk, w.twk,
                        p.n_real, 1.0f, 0.0f, st));
     const long nb = (long)n_bins * p.n_real;
     for (double* o : {k_mean, p0, p2, p4, n_modes}) COLA_TRY(launch_fill_d(o, nb, 0.0, st));
-    COLA_TRY(pk_bin_multipoles(w.K, L.kstride, gk, p.n_real, n_bins, los, k_mean, p0, p2, p4, n_modes,
+    COLA_TRY(pk_bin_multipoles(w.K2, L.kstride, gk, p.n_real, n_bins, los, k_mean, p0, p2, p4, n_modes,
                                2.0 * M_PI / p.box, st));
     COLA_TRY(pk_finish_multipoles(k_mean, p0, p2, p4, n_modes, nb, p.box * p.box * p.box / (cells * cells), st));
     return COLA_OK;
@@ -730,7 +745,7 @@ int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_by
     if (n_pk > 0 && n_pk != L.g.n && n_pk != L.gp.n) {
         COLA_TRY(launch_twiddles(w.twk, n_pk, st));
         if (n_pk <= L.g.n) COLA_TRY(autotune_fft(n_pk, w.S, w.A, w.B, w.twk, st, &rep));
-        else COLA_TRY(autotune_fft(n_pk, w.K, w.K, w.K, w.twk, st, &rep));
+        else COLA_TRY(autotune_fft(n_pk, w.K, w.K2, w.K, w.twk, st, &rep));
     }
     if (report && report_len > 0) {
         std::snprintf(report, report_len, "%s", rep.c_str());

@@ -70,23 +70,28 @@ struct Schedule {
 Schedule make_schedule(const cola_problem& p, const cola_cosmology& c);
 
 // ------------------------------------------------------------------ mesh geometry
-// A cubic mesh of n cells per side held as a half spectrum [n][n][nzp] of float2, nzp >= n/2+1
-// rounded up to 16 so that rows start on 128-byte boundaries.  The same memory holds the real
-// field in place as [n][n][2 nzp] floats (first n used per row).
+// A cubic mesh of n cells per side.  A workspace buffer of total_c() float2 holds either a real
+// field [x][y][z] with rows of 2 nzp floats (nzp >= n/2 + 1 rounded up to 16: rows start on
+// 128-byte boundaries, and a row has room for the two ghost values after z = n - 1) or the
+// transposed half spectrum [kz][x][y], kz planes of n^2 values `plane` float2 apart.
 struct Mesh3 {
     int n = 0;
-    int m = 0;    // n / 2
-    int nzp = 0;  // padded complex row length
+    int m = 0;     // n / 2
+    int nzp = 0;   // padded complex row length of the real layout
+    long plane = 0;  // float2 between kz planes of the transposed spectrum (n^2 plus a pad)
     long row_c() const { return nzp; }
-    long total_c() const { return (long)n * n * nzp; }
+    long total_c() const {
+        const long real = (long)n * n * nzp, spec = (long)(m + 1) * plane;
+        return real > spec ? real : spec;
+    }
     size_t bytes() const { return (size_t)total_c() * sizeof(float2); }
 };
 Mesh3 make_mesh(int n);
 bool fft_size_ok(int n);  // even, >= 4, factors 2 and 3 only
 FftPlan make_plan(int n, bool reverse = false);
 FftPlan make_plan_r(int n, int R, bool reverse);
-// Times the admissible shapes of every FFT kernel at mesh size n on scratch spectra S, A, B
-// (overwritten) and keeps the fastest for the process.
+// Times the admissible shapes of every FFT kernel at mesh size n on scratch buffers S, A, B
+// (overwritten; A differs from S and B) and keeps the fastest for the process.
 hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw, hipStream_t st,
                         std::string* report);
 
@@ -98,32 +103,34 @@ int set_fft_shape(int n, const char* kind, int R, int width, bool stat);
 hipError_t launch_twiddles(float2* tw, int len, hipStream_t st);
 
 // Forward 3D r2c: real rows at `in` (in_row floats apart, batch stride in_bstride floats) with
-// y = pa * x + pb applied on load -> padded half spectrum `out` (batch stride out_bstride float2),
-// in place allowed (in == (float*)out with in_row = 2 nzp).  z, then y, then x.
+// y = pa * x + pb applied on load -> transposed half spectrum `out` (batch stride out_bstride
+// float2), out of place (the z pass transposes).  z, then y, then x.
 hipError_t fft3d_r2c(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                      const Mesh3& g, const float2* tw, int n_real, float pa, float pb, hipStream_t st);
 
-// PM force from the y-transformed spectrum in S (z and y forward passes done):
-//   fused x (forward, Green 1/(k^2 n^3), inverse) -> A = G S, B = i k_x G S;
-//   y inverse: A -> A (times i k_y), S (plain);  B -> B;  z c2r in place: B -> F_x,
-//   A -> F_y, S -> F_z (times i k_z).  Real force rows of 2 nzp floats.
-hipError_t pm_force_from_spectrum(float2* S, float2* A, float2* B, long bstride, const Mesh3& g,
+// PM force from the y-transformed spectrum in P (z and y forward passes done), with Q, R, T free
+// buffers of the same size (all distinct):
+//   fused x (forward, Green 1/(k^2 n^3), inverse) -> P = G P, Q = i k_x G P;
+//   y inverse: P -> P (times i k_y), R (plain);  Q -> Q;
+//   z c2r (out of place): Q -> T = F_x, P -> Q = F_y, R (times i k_z) -> P = F_z.
+// Real force rows of 2 nzp floats, with the ghost values of z = 0, 1 at z = n, n + 1.
+hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
                                   const float2* tw, float kf, int n_real, hipStream_t st);
-// z r2c + y forward only (first half of the PM force transform)
+// z r2c + y forward only (first half of the PM force transform), out of place
 hipError_t fft_zy_forward(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                           const Mesh3& g, const float2* tw, int n_real, float pa, float pb,
                           hipStream_t st);
 
 // Multiplier types for the inverse transforms of the initial conditions.
 enum MulType { MUL_SCALE = 0, MUL_IK = 1, MUL_KK = 2 };
-// Inverse 3D c2r of mult(k) * spec: spec is a full forward spectrum (padded), work a padded
-// scratch spectrum of the same size, out real rows of out_row floats.
+// Inverse 3D c2r of mult(k) * spec: spec is a full forward spectrum, work a scratch spectrum of
+// the same size (may be spec itself), out real rows of out_row floats (not overlapping work).
 hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, long work_bstride,
                           float* out, long out_row, long out_bstride, const Mesh3& g, const float2* tw,
                           int n_real, int mtype, int axis_a, int axis_b, float kf, float scale,
                           hipStream_t st);
 
-// padded <-> numpy rfftn layout copies
+// transposed spectrum <-> numpy rfftn layout [x][y][kz] copies
 hipError_t copy_unpad_to_pad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st);
 hipError_t copy_pad_to_unpad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st);
 
@@ -201,6 +208,18 @@ hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const Lat
                           const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
                           const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
                           float scale, float offset, hipStream_t st);
+
+// The step's gather, kick and drift (as gather_kick_drift with a drift) fused with the binning of
+// the moved particles onto fg's mesh for the next force evaluation; sorted_deposit_binned then
+// finishes that deposit (sort and tile passes).  The force meshes' rows carry the ghost values.
+hipError_t gather_kick_drift_bin(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
+                                 const float* fy, const float* fz, const KickDrift& kd, const TileGeom& tg,
+                                 const SortBufs& sb, hipStream_t st);
+hipError_t sorted_deposit_binned(long npr, int n_real, const LatticeGeom& dg, const TileGeom& tg, const SortBufs& sb,
+                                 float* mesh, float scale, float offset, hipStream_t st);
+// Rewrites the ghost values (z = 0, 1 again at z = n, n + 1) of n_real batches of force meshes with
+// `row` floats per row, after something other than the z c2r pass changed the meshes.
+hipError_t mesh_ghosts(float* const f[3], long row, int n, long bstride, int n_real, hipStream_t st);
 
 // The same deposit for absolute positions pos[3] (n floats each, wrapped into the mesh), one
 // realization, onto a mesh of n_mesh cells per side with rows of `row` floats.

@@ -97,29 +97,53 @@ __device__ __forceinline__ float4 load_rec_stream(const float4* p) {
     return v;
 }
 
-// CIC gather of three meshes (force at the particle, for positions drifted between nodes).
+// The two z corners of a mesh row as one 8-byte load: the force meshes' rows carry the values of
+// z = 0, 1 again at z = n, n + 1, so the pair (m, m + 1) never wraps.
+__device__ __forceinline__ float2 load_pair(const float* p) {
+    float2 v;
+    __builtin_memcpy(&v, p, sizeof(float2));
+    return v;
+}
+
+// CIC gather of three force meshes (rows with the ghost values) at one particle.
 __device__ __forceinline__ void gather3c(const float* fx, const float* fy, const float* fz, long row, int n,
                                          const CellC* c, float g[3]) {
-    const int xs[2] = {c[0].m, wrapn(c[0].m, n)}, ys[2] = {c[1].m, wrapn(c[1].m, n)},
-              zs[2] = {c[2].m, wrapn(c[2].m, n)};
+    const int xs[2] = {c[0].m, wrapn(c[0].m, n)}, ys[2] = {c[1].m, wrapn(c[1].m, n)};
     const float wx[2] = {1.0f - c[0].f, c[0].f}, wy[2] = {1.0f - c[1].f, c[1].f}, wz[2] = {1.0f - c[2].f, c[2].f};
+    float2 vx[4], vy[4], vz[4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {  // the twelve loads are issued together
+            const long r = ((long)xs[a] * n + ys[b]) * row + c[2].m;
+            vx[2 * a + b] = load_pair(fx + r);
+            vy[2 * a + b] = load_pair(fy + r);
+            vz[2 * a + b] = load_pair(fz + r);
+        }
     g[0] = g[1] = g[2] = 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            long r = ((long)xs[a] * n + ys[b]) * row;
-            float wab = wx[a] * wy[b];
-            float w0 = wab * wz[0], w1 = wab * wz[1];
-            g[0] += w0 * fx[r + zs[0]] + w1 * fx[r + zs[1]];
-            g[1] += w0 * fy[r + zs[0]] + w1 * fy[r + zs[1]];
-            g[2] += w0 * fz[r + zs[0]] + w1 * fz[r + zs[1]];
+            const float wab = wx[a] * wy[b];
+            const float w0 = wab * wz[0], w1 = wab * wz[1];
+            const int q = 2 * a + b;
+            g[0] += w0 * vx[q].x + w1 * vx[q].y;
+            g[1] += w0 * vy[q].x + w1 * vy[q].y;
+            g[2] += w0 * vz[q].x + w1 * vz[q].y;
         }
 }
 
-template <bool DRIFT>
-__global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg, LatticeGeom fg, const float* fx,
-                          const float* fy, const float* fz, KickDrift kd, SortBufs sb) {
+// Binning of the particles onto the mesh of dg (key and cell record per particle, counts per
+// key).  MODE 0: at their positions; 1: drifted on the fly (kick with the force gathered from fg's
+// meshes, then the drift of kd) without changing the state -- outputs between nodes and the
+// redshift-space mapping; 2: the step's gather, kick and drift, written back to p and x, then
+// binned at the new positions for the next force evaluation (dg = fg).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
+                                                 LatticeGeom fg, const float* fx, const float* fy, const float* fz,
+                                                 KickDrift kd, SortBufs sb) {
+    constexpr bool DRIFT = MODE != 0;
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     const bool valid = p < npr;
@@ -155,6 +179,10 @@ __global__ void k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
                 if (kd.los >= 0 && d != kd.los) continue;
                 const float ph = pv[d] + kd.kick * (g[d] - kd.d1 * s1[d] - kd.d2m * s2[d]);
                 x[d] = x[d] + ph * kd.drift + kd.dd1 * s1[d] + kd.dd2 * s2[d];
+                if (MODE == 2) {
+                    __builtin_nontemporal_store(ph, P.p[d] + gid);
+                    __builtin_nontemporal_store(x[d], P.x[d] + gid);
+                }
             }
         }
         CellC c[3];
@@ -506,12 +534,30 @@ hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const Lat
     {
         ProfScope ps(drift ? PROF_PK_DEPOSIT : PROF_DEPOSIT, st);
         if (drift)
-            hipLaunchKernelGGL(k_dep_bin<true>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
+            hipLaunchKernelGGL(k_dep_bin<1>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
         else
-            hipLaunchKernelGGL(k_dep_bin<false>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
+            hipLaunchKernelGGL(k_dep_bin<0>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return sort_and_tile(npr, n_real, tg, sb, mesh, dg.row, dg.mesh_bstride, scale, offset, st);
+}
+
+hipError_t gather_kick_drift_bin(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
+                                 const float* fy, const float* fz, const KickDrift& kd, const TileGeom& tg,
+                                 const SortBufs& sb, hipStream_t st) {
+    hipError_t e = launch_fill(reinterpret_cast<float*>(sb.count), sb.kstride * n_real, 0.0f, st);
+    if (e != hipSuccess) return e;
+    KickDrift k = kd;
+    k.los = -1;
+    ProfScope ps(PROF_GKD, st);
+    hipLaunchKernelGGL(k_dep_bin<2>, dim3((unsigned)((npr + 255) / 256), n_real), dim3(256), 0, st, P, npr, fg, tg,
+                       fg, fx, fy, fz, k, sb);
+    return hipGetLastError();
+}
+
+hipError_t sorted_deposit_binned(long npr, int n_real, const LatticeGeom& dg, const TileGeom& tg, const SortBufs& sb,
+                                 float* mesh, float scale, float offset, hipStream_t st) {
     return sort_and_tile(npr, n_real, tg, sb, mesh, dg.row, dg.mesh_bstride, scale, offset, st);
 }
 

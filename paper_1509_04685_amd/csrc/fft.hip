@@ -1,12 +1,15 @@
 // 3D FFT passes for cubic meshes on gfx950 (Sec. 2.2: one forward and three inverse FFTs per
-// particle-mesh force).  Layout: a half spectrum [x][y][kz] of float2 with kz rows padded to nzp
-// (a multiple of 16, so rows start on 128-byte lines); the same memory holds the real field as
-// [x][y][2 nzp] floats.
+// particle-mesh force).  Real fields are [x][y][z] rows of `row` floats; the half spectrum is
+// transposed, [kz][x][y] of float2 (y contiguous, kz planes of n^2 values), so that the y pass
+// works on contiguous rows and the x pass on columns n values apart -- no pass walks an axis at
+// the stride of a whole plane.
 //
 // Passes (each one HBM read and one write of the array):
-//   z: contiguous rows, real <-> half complex via an n/2-point complex FFT plus a split step;
-//   y, x: strided columns, a tile of TK adjacent columns per block so that every row access
-//         moves TK * 8 contiguous bytes.
+//   z: real rows <-> half complex via an n/2-point complex FFT plus a split step, each block
+//      moving W rows of one x plane and W consecutive y of every kz plane (out of place);
+//   y: contiguous complex rows, in place;
+//   x: columns, a tile of TK adjacent y columns per block so that every row access moves TK * 8
+//      contiguous bytes, in place.
 // The particle-mesh force fuses the forward x transform, the Green's function and the inverse x
 // transform in one pass that writes two outputs, so the full spectrum never goes to HBM.
 
@@ -33,11 +36,18 @@ bool fft_size_ok(int n) {
     return m == 1;
 }
 
+// Pad of the kz-plane stride of the transposed spectrum (float2): with planes exactly n^2 apart,
+// the values a z pass moves for one row group (the same (x, y) in every plane) differ only in
+// their high address bits.  Measured on the 768^3 step (ms per node): pad 0 9.76, 8 9.87, 16 9.41,
+// 32 9.30, 48 9.33, 64 9.46, 256 9.78.
+constexpr long kSpecPlanePad = 32;
+
 Mesh3 make_mesh(int n) {
     Mesh3 g;
     g.n = n;
     g.m = n / 2;
     g.nzp = ((g.m + 1) + 15) / 16 * 16;
+    g.plane = (long)n * n + kSpecPlanePad;
     return g;
 }
 
@@ -110,16 +120,16 @@ static hipError_t dispatch_r(int R, F&& f) {
 
 // ------------------------------------------------------------------ kernel shapes and autotuning
 
-// Shape of one FFT kernel launch: R values per thread, `width` lines per block (z passes) or
-// columns per tile (y/x passes), and whether the compile-time plan of that shape is used.
+// Shape of one FFT kernel launch: R values per thread, `width` lines per block (z passes, y rows)
+// or columns per tile (x columns), and whether the compile-time plan of that shape is used.
 struct FftShape {
     int R = 0;
     int width = 0;
     bool stat = false;
 };
 
-enum FftKind { FK_Z_R2C = 0, FK_Z_C2R, FK_COLS_Y, FK_COLS_X, FK_X_GREEN, FK_Y_SPLIT, FK_X_MULT, FK_NUM };
-static const char* const kFftKindName[FK_NUM] = {"z_r2c", "z_c2r", "cols_y", "cols_x", "x_green",
+enum FftKind { FK_Z_R2C = 0, FK_Z_C2R, FK_ROWS_Y, FK_COLS_X, FK_X_GREEN, FK_Y_SPLIT, FK_X_MULT, FK_NUM };
+static const char* const kFftKindName[FK_NUM] = {"z_r2c", "z_c2r", "rows_y", "cols_x", "x_green",
                                                  "y_split", "x_mult"};
 
 static bool plan_ok(int n, int R) {
@@ -157,6 +167,7 @@ static std::vector<int> valid_rs(int n) {
 }
 
 static bool is_z(FftKind k) { return k == FK_Z_R2C || k == FK_Z_C2R; }
+static bool is_rows(FftKind k) { return k == FK_ROWS_Y || k == FK_Y_SPLIT; }
 
 // Line length the kernel transforms: n/2 for the z passes, n otherwise.
 static int line_len(FftKind k, int n) { return is_z(k) ? n / 2 : n; }
@@ -165,10 +176,10 @@ static FftOp op_of(FftKind k) {
     switch (k) {
         case FK_Z_R2C: return OP_Z_R2C;
         case FK_Z_C2R: return OP_Z_C2R;
-        case FK_COLS_Y:
+        case FK_ROWS_Y: return OP_ROWS_FWD;
         case FK_COLS_X: return OP_COLS_FWD;
         case FK_X_GREEN: return OP_X_GREEN;
-        case FK_Y_SPLIT: return OP_Y_SPLIT;
+        case FK_Y_SPLIT: return OP_ROWS_SPLIT;
         default: return OP_X_MULT;
     }
 }
@@ -201,9 +212,17 @@ static size_t shape_lds(FftKind k, int n, const FftShape& sh) {
     return is_z(k) ? (size_t)sh.width * (L + 1) * sizeof(float2) : (size_t)sh.width * L * sizeof(float2);
 }
 
+static int log2_exact(int w) {  // log2 of a power of two, -1 otherwise
+    int l = 0;
+    while ((1 << l) < w) ++l;
+    return (1 << l) == w ? l : -1;
+}
+
 static bool shape_ok(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
-    if (!plan_ok(L, sh.R)) return false;
+    if (!plan_ok(L, sh.R) || sh.width < 1) return false;
+    // z passes: a power-of-two number of lines of one x plane per block
+    if (is_z(k) && (log2_exact(sh.width) < 0 || n % sh.width)) return false;
     long threads = (long)sh.width * (L / sh.R);
     if (threads > 512 || threads < 1) return false;
     return shape_lds(k, n, sh) <= 128 * 1024;
@@ -214,9 +233,14 @@ static FftShape default_shape(FftKind k, int n) {
     FftPlan pl = make_plan(L);
     FftShape sh;
     sh.R = pl.R;
-    if (is_z(k)) {
+    if (is_z(k) || is_rows(k)) {
         sh.width = std::max(1, 256 / pl.T);
         while ((long)sh.width * pl.T > 512) sh.width /= 2;
+        if (is_z(k)) {
+            int w = 1;  // the largest power of two <= width that divides n
+            while (w * 2 <= sh.width && n % (w * 2) == 0) w *= 2;
+            sh.width = w;
+        }
     } else {
         sh.width = pick_tk(n, pl.T);
     }
@@ -261,47 +285,29 @@ int set_fft_shape(int n, const char* kind, int R, int width, bool stat) {
 
 // ------------------------------------------------------------------ launchers
 
-static ColGeom cols_y(const Mesh3& g, int tk) {
-    ColGeom cg;
-    cg.es = g.nzp;
-    cg.inner = g.nzp;
-    cg.outer_stride = g.n * g.nzp;
-    cg.nzp = g.nzp;
-    cg.mvalid = g.m + 1;
-    cg.tk = tk;
-    cg.tiles = (cg.inner + tk - 1) / tk;
-    return cg;
-}
-
 static ColGeom cols_x(const Mesh3& g, int tk) {
     ColGeom cg;
-    cg.es = g.n * g.nzp;
-    cg.inner = g.n * g.nzp;
-    cg.outer_stride = 0;
-    cg.nzp = g.nzp;
-    cg.mvalid = g.m + 1;
+    cg.es = g.n;
+    cg.inner = g.n;
+    cg.plane_stride = (int)g.plane;
     cg.tk = tk;
-    cg.tiles = (cg.inner + tk - 1) / tk;
+    cg.tiles = (g.n + tk - 1) / tk;
     return cg;
-}
-
-static long col_blocks(const ColGeom& cg, const Mesh3& g, bool y_axis) {
-    return (y_axis ? (long)g.n : 1L) * cg.tiles;
 }
 
 // Launches L with the shape's static kernel or the dynamic kernel of the same shape.
 static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
-    L.n = L.op <= OP_Z_C2R_IKZ ? mesh_n / 2 : mesh_n;
+    const bool z = is_z_op(L.op);
+    L.n = z ? mesh_n / 2 : mesh_n;
     L.R = sh.R;
     L.width = sh.width;
     if (sh.stat) {
         hipError_t e = launch_static(L, mesh_n);
         if (e != hipErrorNotSupported) return e;
     }
-    const bool z = L.op <= OP_Z_C2R_IKZ;
     FftPlan pl = make_plan_r(L.n, sh.R, false);
     if (z) finish_plan(pl, 2);
-    const int les = z ? 1 : sh.width;
+    const int les = (z || is_rows_op(L.op)) ? 1 : sh.width;
     hipError_t err = hipSuccess;
     hipError_t de = dispatch_r(sh.R, [&](auto rr) {
         constexpr int R = decltype(rr)::value;
@@ -311,42 +317,62 @@ static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
             case OP_Z_R2C: err = go_z_r2c<D>(L, e); break;
             case OP_Z_C2R: err = go_z_c2r<D, false>(L, e); break;
             case OP_Z_C2R_IKZ: err = go_z_c2r<D, true>(L, e); break;
-            case OP_COLS_FWD: err = go_cols<D, 0, false>(L, e); break;
-            case OP_COLS_INV: err = go_cols<D, 0, true>(L, e); break;
+            case OP_ROWS_FWD: err = go_rows<D, 0>(L, e); break;
+            case OP_ROWS_INV: err = go_rows<D, 1>(L, e); break;
+            case OP_ROWS_SPLIT: err = go_rows<D, 2>(L, e); break;
+            case OP_COLS_FWD: err = go_cols<D, 0>(L, e); break;
             case OP_X_GREEN: {
                 D ei{make_plan_r(L.n, R, true), les};
                 err = go_x_green<D, D, 0>(L, e, ei);
                 break;
             }
-            case OP_Y_SPLIT: err = go_y_split<D, 0>(L, e); break;
             case OP_X_MULT: err = go_x_mult<D, 0>(L, e); break;
         }
     });
     return err != hipSuccess ? err : de;
 }
 
-template <bool INV>
-static hipError_t run_cols_shape(float2* data, long bstride, const Mesh3& g, bool y_axis, const float2* tw,
-                                 int n_real, const FftShape& sh, hipStream_t st) {
+// y rows of every kz plane: op OP_ROWS_FWD / OP_ROWS_INV on A, or OP_ROWS_SPLIT (A -> A, S).
+static hipError_t run_rows_shape(FftOp op, float2* A, float2* S, long bstride, const Mesh3& g, const float2* tw,
+                                 float kf, int n_real, const FftShape& sh, hipStream_t st) {
     FftLaunch L;
-    L.op = INV ? OP_COLS_INV : OP_COLS_FWD;
-    L.cg = y_axis ? cols_y(g, sh.width) : cols_x(g, sh.width);
+    L.op = op;
+    L.nrows = (long)(g.m + 1) * g.n;
     L.lds = (size_t)sh.width * g.n * sizeof(float2);
-    L.grid = dim3((unsigned)col_blocks(L.cg, g, y_axis), n_real);
+    L.grid = dim3((unsigned)((L.nrows + sh.width - 1) / sh.width), n_real);
+    L.block = dim3(sh.width * (g.n / sh.R));
+    L.st = st;
+    L.d0 = A;
+    L.d1 = S;
+    L.b0 = bstride;
+    L.plane = g.plane;
+    L.tw = tw;
+    L.kf = kf;
+    const int kind = op == OP_ROWS_FWD ? PROF_Y_FWD : (op == OP_ROWS_INV ? PROF_Y_INV : PROF_Y_SPLIT);
+    ProfScope ps(kind, st, g.n);
+    return launch_shape(L, g.n, sh);
+}
+
+static hipError_t run_rows(FftOp op, float2* A, float2* S, long bstride, const Mesh3& g, const float2* tw, float kf,
+                           int n_real, hipStream_t st) {
+    return run_rows_shape(op, A, S, bstride, g, tw, kf, n_real,
+                          shape_for(op == OP_ROWS_SPLIT ? FK_Y_SPLIT : FK_ROWS_Y, g.n), st);
+}
+
+static hipError_t run_cols_shape(float2* data, long bstride, const Mesh3& g, const float2* tw, int n_real,
+                                 const FftShape& sh, hipStream_t st) {
+    FftLaunch L;
+    L.op = OP_COLS_FWD;
+    L.cg = cols_x(g, sh.width);
+    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
     L.d0 = data;
     L.b0 = bstride;
     L.tw = tw;
-    ProfScope ps(INV ? (y_axis ? PROF_Y_INV : PROF_OTHER) : (y_axis ? PROF_Y_FWD : PROF_X_FWD), st, g.n);
+    ProfScope ps(PROF_X_FWD, st, g.n);
     return launch_shape(L, g.n, sh);
-}
-
-template <bool INV>
-static hipError_t run_cols(float2* data, long bstride, const Mesh3& g, bool y_axis, const float2* tw,
-                           int n_real, hipStream_t st) {
-    return run_cols_shape<INV>(data, bstride, g, y_axis, tw, n_real, shape_for(y_axis ? FK_COLS_Y : FK_COLS_X, g.n),
-                               st);
 }
 
 static hipError_t run_z_r2c_shape(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
@@ -355,17 +381,18 @@ static hipError_t run_z_r2c_shape(const float* in, long in_row, long in_bstride,
     FftLaunch L;
     L.op = OP_Z_R2C;
     const int lpb = sh.width;
-    L.nrows = (long)g.n * g.n;
     L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
-    L.grid = dim3((unsigned)((L.nrows + lpb - 1) / lpb), n_real);
+    L.grid = dim3((unsigned)((long)g.n * g.n / lpb), n_real);
     L.block = dim3(lpb * (g.m / sh.R));
     L.st = st;
     L.rin = in;
     L.in_row = in_row;
     L.in_bstride = in_bstride;
     L.cout = out;
-    L.out_row = g.nzp;
     L.out_bstride = out_bstride;
+    L.mesh_n = g.n;
+    L.plane = g.plane;
+    L.lw = log2_exact(lpb);
     L.tw = tw;
     L.pa = pa;
     L.pb = pb;
@@ -386,17 +413,19 @@ static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out,
     FftLaunch L;
     L.op = MUL ? OP_Z_C2R_IKZ : OP_Z_C2R;
     const int lpb = sh.width;
-    L.nrows = (long)g.n * g.n;
     L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
-    L.grid = dim3((unsigned)((L.nrows + lpb - 1) / lpb), n_real);
+    L.grid = dim3((unsigned)((long)g.n * g.n / lpb), n_real);
     L.block = dim3(lpb * (g.m / sh.R));
     L.st = st;
     L.cin = in;
-    L.in_row = g.nzp;
     L.in_bstride = in_bstride;
     L.rout = out;
     L.out_row = out_row;
     L.out_bstride = out_bstride;
+    L.mesh_n = g.n;
+    L.plane = g.plane;
+    L.lw = log2_exact(lpb);
+    L.ghost = out_row >= g.n + 2 ? 1 : 0;
     L.tw = tw;
     L.kf = kf;
     L.scale = scale;
@@ -418,7 +447,7 @@ static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstrid
     L.op = OP_X_GREEN;
     L.cg = cols_x(g, sh.width);
     L.lds = (size_t)sh.width * g.n * sizeof(float2);
-    L.grid = dim3((unsigned)col_blocks(L.cg, g, false), n_real);
+    L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
     L.c0 = S;
@@ -432,24 +461,6 @@ static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstrid
     return launch_shape(L, g.n, sh);
 }
 
-static hipError_t run_y_split_shape(float2* A, float2* S, long bstride, const Mesh3& g, const float2* tw,
-                                    float kf, int n_real, const FftShape& sh, hipStream_t st) {
-    FftLaunch L;
-    L.op = OP_Y_SPLIT;
-    L.cg = cols_y(g, sh.width);
-    L.lds = (size_t)sh.width * g.n * sizeof(float2);
-    L.grid = dim3((unsigned)col_blocks(L.cg, g, true), n_real);
-    L.block = dim3(sh.width * (g.n / sh.R));
-    L.st = st;
-    L.d0 = A;
-    L.d1 = S;
-    L.b0 = bstride;
-    L.tw = tw;
-    L.kf = kf;
-    ProfScope ps(PROF_Y_SPLIT, st, g.n);
-    return launch_shape(L, g.n, sh);
-}
-
 static hipError_t run_x_mult_shape(const float2* spec, long spec_bstride, float2* work, long work_bstride,
                                    const Mesh3& g, const float2* tw, int n_real, int mtype, int axis_a,
                                    int axis_b, float kf, float scale, const FftShape& sh, hipStream_t st) {
@@ -457,7 +468,7 @@ static hipError_t run_x_mult_shape(const float2* spec, long spec_bstride, float2
     L.op = OP_X_MULT;
     L.cg = cols_x(g, sh.width);
     L.lds = (size_t)sh.width * g.n * sizeof(float2);
-    L.grid = dim3((unsigned)col_blocks(L.cg, g, false), n_real);
+    L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
     L.c0 = spec;
@@ -479,30 +490,30 @@ hipError_t fft_zy_forward(const float* in, long in_row, long in_bstride, float2*
                           hipStream_t st) {
     hipError_t e = run_z_r2c(in, in_row, in_bstride, out, out_bstride, g, tw, n_real, pa, pb, st);
     if (e != hipSuccess) return e;
-    return run_cols<false>(out, out_bstride, g, true, tw, n_real, st);
+    return run_rows(OP_ROWS_FWD, out, nullptr, out_bstride, g, tw, 0.0f, n_real, st);
 }
 
 hipError_t fft3d_r2c(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                      const Mesh3& g, const float2* tw, int n_real, float pa, float pb, hipStream_t st) {
     hipError_t e = fft_zy_forward(in, in_row, in_bstride, out, out_bstride, g, tw, n_real, pa, pb, st);
     if (e != hipSuccess) return e;
-    return run_cols<false>(out, out_bstride, g, false, tw, n_real, st);
+    return run_cols_shape(out, out_bstride, g, tw, n_real, shape_for(FK_COLS_X, g.n), st);
 }
 
-hipError_t pm_force_from_spectrum(float2* S, float2* A, float2* B, long bstride, const Mesh3& g,
+hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
                                   const float2* tw, float kf, int n_real, hipStream_t st) {
-    hipError_t e = run_x_green_shape(S, A, B, bstride, g, tw, kf, n_real, shape_for(FK_X_GREEN, g.n), st);
+    hipError_t e = run_x_green_shape(P, P, Q, bstride, g, tw, kf, n_real, shape_for(FK_X_GREEN, g.n), st);
     if (e != hipSuccess) return e;
-    e = run_y_split_shape(A, S, bstride, g, tw, kf, n_real, shape_for(FK_Y_SPLIT, g.n), st);
+    e = run_rows(OP_ROWS_SPLIT, P, R, bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;
-    e = run_cols<true>(B, bstride, g, true, tw, n_real, st);
+    e = run_rows(OP_ROWS_INV, Q, nullptr, bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;
     const long rowf = 2L * g.nzp;
-    e = run_z_c2r<false>(B, bstride, reinterpret_cast<float*>(B), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
+    e = run_z_c2r<false>(Q, bstride, reinterpret_cast<float*>(T), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
     if (e != hipSuccess) return e;
-    e = run_z_c2r<false>(A, bstride, reinterpret_cast<float*>(A), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
+    e = run_z_c2r<false>(P, bstride, reinterpret_cast<float*>(Q), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
     if (e != hipSuccess) return e;
-    return run_z_c2r<true>(S, bstride, reinterpret_cast<float*>(S), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
+    return run_z_c2r<true>(R, bstride, reinterpret_cast<float*>(P), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
 }
 
 hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, long work_bstride,
@@ -512,14 +523,15 @@ hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, l
     hipError_t e = run_x_mult_shape(spec, spec_bstride, work, work_bstride, g, tw, n_real, mtype, axis_a, axis_b,
                                     kf, scale, shape_for(FK_X_MULT, g.n), st);
     if (e != hipSuccess) return e;
-    e = run_cols<true>(work, work_bstride, g, true, tw, n_real, st);
+    e = run_rows(OP_ROWS_INV, work, nullptr, work_bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;
     return run_z_c2r<false>(work, work_bstride, out, out_row, out_bstride, g, tw, n_real, kf, 1.0f, st);
 }
 
 // Times every admissible shape of each FFT kernel at mesh size n on the buffers S, A, B (each at
-// least one padded half spectrum of size n; their contents are overwritten) and keeps the fastest
-// per kind for the rest of the process.  `report` gets one line per kind.
+// least one workspace mesh buffer of size n; A differs from S and B, which may be one buffer;
+// their contents are overwritten)
+// and keeps the fastest per kind for the rest of the process.  `report` gets one line per kind.
 hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw, hipStream_t st,
                         std::string* report) {
     Mesh3 g = make_mesh(n);
@@ -544,15 +556,15 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
         auto launch = [&](const FftShape& sh) -> hipError_t {
             switch (kind) {
                 case FK_Z_R2C:
-                    return run_z_r2c_shape(reinterpret_cast<const float*>(S), 2L * g.nzp, 0, S, 0, g, tw, 1, 1.0f,
+                    return run_z_r2c_shape(reinterpret_cast<const float*>(S), 2L * g.nzp, 0, A, 0, g, tw, 1, 1.0f,
                                            0.0f, sh, st);
                 case FK_Z_C2R:
-                    return run_z_c2r_shape<false>(A, 0, reinterpret_cast<float*>(A), 2L * g.nzp, 0, g, tw, 1, kf,
+                    return run_z_c2r_shape<false>(A, 0, reinterpret_cast<float*>(B), 2L * g.nzp, 0, g, tw, 1, kf,
                                                   1.0f, sh, st);
-                case FK_COLS_Y: return run_cols_shape<false>(S, 0, g, true, tw, 1, sh, st);
-                case FK_COLS_X: return run_cols_shape<false>(S, 0, g, false, tw, 1, sh, st);
-                case FK_X_GREEN: return run_x_green_shape(S, A, B, 0, g, tw, kf, 1, sh, st);
-                case FK_Y_SPLIT: return run_y_split_shape(A, S, 0, g, tw, kf, 1, sh, st);
+                case FK_ROWS_Y: return run_rows_shape(OP_ROWS_FWD, S, nullptr, 0, g, tw, kf, 1, sh, st);
+                case FK_COLS_X: return run_cols_shape(S, 0, g, tw, 1, sh, st);
+                case FK_X_GREEN: return run_x_green_shape(S, S, A, 0, g, tw, kf, 1, sh, st);
+                case FK_Y_SPLIT: return run_rows_shape(OP_ROWS_SPLIT, A, S, 0, g, tw, kf, 1, sh, st);
                 case FK_X_MULT: return run_x_mult_shape(S, 0, A, 0, g, tw, 1, MUL_IK, 0, 0, kf, 1.0f, sh, st);
                 default: return hipErrorInvalidValue;
             }
@@ -598,30 +610,40 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
 
 // ------------------------------------------------------------------ layout copies
 
-__global__ void k_copy_rows(const float2* src, long src_row, float2* dst, long dst_row, long nrows, int len) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    long total = nrows * len;
+// numpy rfftn layout [x][y][kz] (m + 1 per row) <-> the transposed spectrum [kz][x][y].  One
+// thread per mode; the component FFT entry points use them, the hot path does not.
+__global__ void k_to_numpy(const float2* spec, long plane, float2* out, int n, int m1) {
+    const long total = (long)n * n * m1;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // index in the numpy layout
     if (i >= total) return;
-    long r = i / len;
-    int c = (int)(i % len);
-    dst[r * dst_row + c] = src[r * src_row + c];
+    const long xy = i / m1;
+    const int kz = (int)(i - xy * m1);
+    out[i] = spec[(long)kz * plane + xy];
+}
+
+__global__ void k_from_numpy(const float2* in, float2* spec, long plane, int n, int m1) {
+    const long nn = (long)n * n;
+    const long total = nn * m1;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // mode (kz, x, y) in that order
+    if (i >= total) return;
+    const int kz = (int)(i / nn);
+    const long xy = i - kz * nn;
+    spec[(long)kz * plane + xy] = in[xy * m1 + kz];
 }
 
 hipError_t copy_unpad_to_pad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st) {
-    long nrows = (long)g.n * g.n;
-    long total = nrows * (g.m + 1);
+    long total = (long)g.n * g.n * (g.m + 1);
     ProfScope ps(PROF_COPY, st);
-    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src,
-                       (long)(g.m + 1), dst, (long)g.nzp, nrows, g.m + 1);
+    hipLaunchKernelGGL(k_from_numpy, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, dst, g.plane, g.n,
+                       g.m + 1);
     return hipGetLastError();
 }
 
 hipError_t copy_pad_to_unpad(const float2* src, float2* dst, const Mesh3& g, hipStream_t st) {
-    long nrows = (long)g.n * g.n;
-    long total = nrows * (g.m + 1);
+    long total = (long)g.n * g.n * (g.m + 1);
     ProfScope ps(PROF_COPY, st);
-    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src,
-                       (long)g.nzp, dst, (long)(g.m + 1), nrows, g.m + 1);
+    hipLaunchKernelGGL(k_to_numpy, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, g.plane, dst, g.n,
+                       g.m + 1);
     return hipGetLastError();
 }
 

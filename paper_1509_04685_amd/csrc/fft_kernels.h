@@ -3,11 +3,14 @@
 // host logic and the dynamic instantiations) and by the fft_static_*.hip files (the static
 // instantiations for the mesh sizes of the workloads).
 //
-// Layout: a half spectrum [x][y][kz] of float2 with kz rows padded to nzp (a multiple of 16, so
-// rows start on 128-byte lines); the same memory holds the real field as [x][y][2 nzp] floats.
-//   z: contiguous rows, real <-> half complex via an n/2-point complex FFT plus a split step;
-//   y, x: strided columns, a tile of TK adjacent columns per block so that every row access
-//         moves TK * 8 contiguous bytes.
+// Layouts: real fields are [x][y][z] with rows of `row` floats (2 nzp in the workspace meshes, z
+// contiguous); the half spectrum is transposed, [kz][x][y] of float2 with y contiguous, so that no
+// pass walks an axis at the stride of a whole plane:
+//   z: real rows in, one kz plane chunk of W consecutive y out per kz (and the reverse), through
+//      an n/2-point complex FFT per row plus a split step; W lines of one x plane per block;
+//   y: contiguous complex rows (kz, x) of n values;
+//   x: columns at a stride of n values, a tile of TK adjacent y columns of one kz plane per block,
+//      so that every row access moves TK * 8 contiguous bytes.
 #pragma once
 
 #include "cola_internal.h"
@@ -16,15 +19,13 @@ namespace cola {
 
 // ------------------------------------------------------------------ column geometry
 
-// Columns of a realization's padded spectrum (offsets fit 32 bits: meshes up to 1536^3).
+// x columns of a realization's transposed spectrum (offsets fit 32 bits: meshes up to 1536^3).
 struct ColGeom {
-    int es;           // element stride along the transform axis (float2)
-    int inner;        // contiguous columns per outer block
-    int outer_stride;
-    int nzp;          // columns c are valid when c % nzp < mvalid
-    int mvalid;
+    int es;           // element stride along x (n)
+    int inner;        // columns per kz plane (n)
+    int plane_stride; // float2 between kz planes (n^2 plus the plane pad)
     int tk;           // columns per tile
-    int tiles;        // tiles per outer block
+    int tiles;        // tiles per plane
 };
 
 // Block b runs on XCD b % 8 (round-robin dispatch); hand each XCD a contiguous run of tiles so
@@ -36,18 +37,19 @@ __device__ __forceinline__ int xcd_block() {
     return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// TK > 0: columns per tile fixed at compile time (cg.tk is then equal to it).
+// TK > 0: columns per tile fixed at compile time (cg.tk is then equal to it).  c: the column (y),
+// plane: the kz plane of the block's tile.
 template <int TK>
-__device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& base, int& c) {
+__device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& base, int& c, int& plane) {
     const int tk = TK > 0 ? TK : cg.tk;
     const int ct = threadIdx.x % tk;
     t = threadIdx.x / tk;
     const int blk = xcd_block();
-    const int outer = blk / cg.tiles;
-    const int tile = blk - outer * cg.tiles;
+    plane = blk / cg.tiles;
+    const int tile = blk - plane * cg.tiles;
     c = tile * tk + ct;
-    base = (uint32_t)outer * (uint32_t)cg.outer_stride + (uint32_t)c;
-    return c < cg.inner && (c % cg.nzp) < cg.mvalid;
+    base = (uint32_t)plane * (uint32_t)cg.plane_stride + (uint32_t)c;
+    return c < cg.inner;
 }
 
 __device__ __forceinline__ int signed_mode(int e, int n) { return e < n / 2 ? e : e - n; }
@@ -80,10 +82,10 @@ __device__ __forceinline__ const float2* stage_twiddles(const float2* tw, float2
 
 // ------------------------------------------------------------------ streaming row access
 
-// Non-temporal loads and stores for the z passes: a block moves whole contiguous rows that no
-// other block touches, and the measured z c2r time falls by a tenth (0.66 -> 0.59 ms on 768^3)
-// with both.  The column passes keep cached access: a 64-byte tile row shares its 128-byte line
-// with the neighbouring tile, which finds it in L2.
+// Non-temporal loads and stores for the row passes: a block moves data that no other block
+// touches (the z c2r time fell by a tenth, 0.66 -> 0.59 ms on 768^3, with both).  The column
+// passes keep cached access unless a tile row fills a whole 128-byte line: a 64-byte tile row
+// shares its line with the neighbouring tile, which finds it in L2.
 __device__ __forceinline__ float2 load_stream(const float2* p) {
     float2 v;
     v.x = __builtin_nontemporal_load(&p->x);
@@ -111,134 +113,196 @@ __device__ __forceinline__ void store_col(float2* p, float2 v) {
 
 // Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
 // X_k = (Z_k + conj Z_{M-k})/2 - i W_n^k (Z_k - conj Z_{M-k})/2, k = 0..M.
+// Block: W = 2^lw lines (x, y0 .. y0 + W - 1) of one x plane (W divides n); output X_k of line j
+// at out[k plane + x n + y0 + j].
 template <class LE>
-__global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row, long in_bstride,
-                                                   float2* out, long out_row, long out_bstride,
-                                                   long nrows, LE eng, const float2* tw,
-                                                   float pa, float pb) {
+__global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row, long in_bstride, float2* out,
+                                                   long out_bstride, int n, long plane, int lw, LE eng,
+                                                   const float2* tw, float pa, float pb) {
     constexpr int R = LE::kR;
     constexpr int TW = z_tw_entries<LE>();
     extern __shared__ float2 lds[];
     const int T = eng.T(), M = eng.n();
+    const int W = 1 << lw;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const long row = (long)blockIdx.x * (blockDim.x / T) + line;
-    const bool active = row < nrows;
+    const long first = (long)blockIdx.x * W;  // line index x n + y of the block's first line
+    const int x = (int)(first / n), y0 = (int)(first - (long)x * n);
     in += (long)blockIdx.y * in_bstride;
     out += (long)blockIdx.y * out_bstride;
-    float2* L = lds + TW + line * (M + 1);
+    float2* const Lb = lds + TW;
+    float2* L = Lb + line * (M + 1);
     float2 v[R];
-    if (active) {
-        const float2* src = reinterpret_cast<const float2*>(in + row * in_row);
-        eng.first(t, [&](int q, int e) {
-            float2 z = load_stream(src + e);
-            v[q] = make_float2(fmaf(z.x, pa, pb), fmaf(z.y, pa, pb));
-        });
-    }
+    const float2* src = reinterpret_cast<const float2*>(in + (first + line) * in_row);
+    eng.first(t, [&](int q, int e) {
+        float2 z = load_stream(src + e);
+        v[q] = make_float2(fmaf(z.x, pa, pb), fmaf(z.y, pa, pb));
+    });
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
-    eng.template run<false>(v, L, t, twl, active);
-    if (active) eng.last(t, [&](int q, int e) { L[e] = v[q]; });
+    eng.template run<false>(v, L, t, twl, true);
+    eng.last(t, [&](int q, int e) { L[e] = v[q]; });
     __syncthreads();
-    if (!active) return;
-    float2* dst = out + row * out_row;
+    // split and transposed store: consecutive threads take consecutive lines of one k, so every
+    // kz plane receives W contiguous values; R outputs per thread plus the k = M column
+    float2* dst = out + (long)x * n + y0;
+    const int bd = blockDim.x;
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-        int k = t + u * T;
-        float2 zk = L[k];
-        float2 zc = cconj(L[k == 0 ? 0 : M - k]);
-        float2 e = cscale(cadd(zk, zc), 0.5f);
-        float2 d = csub(zk, zc);
-        float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
-        store_stream(dst + k, cadd(e, cmul(twl[k], o)));
+        const int o = threadIdx.x + u * bd;
+        const int k = o >> lw, j = o & (W - 1);
+        const float2* Lj = Lb + j * (M + 1);
+        const float2 zk = Lj[k];
+        const float2 zc = cconj(Lj[k == 0 ? 0 : M - k]);
+        const float2 e = cscale(cadd(zk, zc), 0.5f);
+        const float2 d = csub(zk, zc);
+        const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
+        store_stream(dst + (long)k * plane + j, cadd(e, cmul(twl[k], od)));
     }
-    if (t == 0) {
-        float2 z0 = L[0];
-        store_stream(dst + M, make_float2(z0.x - z0.y, 0.0f));
+    if (threadIdx.x < W) {
+        const float2 z0 = Lb[threadIdx.x * (M + 1)];
+        store_stream(dst + (long)M * plane + threadIdx.x, make_float2(z0.x - z0.y, 0.0f));
     }
 }
 
 // ------------------------------------------------------------------ z pass: half complex -> real
 
 // Z_k = (X_k + conj X_{M-k}) + i conj(W_n^k) (X_k - conj X_{M-k}); x_{2j} + i x_{2j+1} = IFFT_M(Z)_j.
-// MUL_IKZ multiplies X by i k_z first (the kz = M Nyquist column becomes 0).
+// MUL_IKZ multiplies X by i k_z first (the kz = M Nyquist plane becomes 0).  Block: the W = 2^lw
+// lines (x, y0 .. y0 + W - 1) of one x plane; line j reads in[k plane + x n + y0 + j] and writes the
+// real row (x, y0 + j).  ghost: the row also gets x_0, x_1 again at n, n + 1 (rows of at least
+// n + 2 floats), so that a CIC pair (z, z + 1) never wraps.
 template <class LE, bool MUL_IKZ>
-__global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_row, long in_bstride,
-                                                   float* out, long out_row, long out_bstride,
-                                                   long nrows, LE eng, const float2* tw,
-                                                   float kf, float scale) {
+__global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bstride, float* out, long out_row,
+                                                   long out_bstride, int n, long plane, int lw, int ghost, LE eng,
+                                                   const float2* tw, float kf, float scale) {
     constexpr int R = LE::kR;
     constexpr int TW = z_tw_entries<LE>();
     extern __shared__ float2 lds[];
     const int T = eng.T(), M = eng.n();
+    const int W = 1 << lw;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const long row = (long)blockIdx.x * (blockDim.x / T) + line;
-    const bool active = row < nrows;
+    const long first = (long)blockIdx.x * W;
+    const int x = (int)(first / n), y0 = (int)(first - (long)x * n);
     in += (long)blockIdx.y * in_bstride;
     out += (long)blockIdx.y * out_bstride;
-    float2* L = lds + TW + line * (M + 1);
+    float2* const Lb = lds + TW;
     const float2* twl = stage_twiddles<TW>(tw, lds);  // visible after the barrier below
-    if (active) {
-        // issue all R loads of this thread before the first LDS store
-        const float2* src = in + row * in_row;
-        float2 x[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) x[u] = load_stream(src + t + u * T);
-        float2 xm = (t == 0) ? load_stream(src + M) : make_float2(0.0f, 0.0f);
+    {
+        // every load of this thread is issued before the first LDS store
+        const float2* src = in + (long)x * n + y0;
+        const int bd = blockDim.x;
+        float2 xv[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-            int e = t + u * T;
-            float2 y = x[u];
+            const int o = threadIdx.x + u * bd;
+            xv[u] = load_stream(src + (long)(o >> lw) * plane + (o & (W - 1)));
+        }
+        const float2 xm = threadIdx.x < W ? load_stream(src + (long)M * plane + threadIdx.x) : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int o = threadIdx.x + u * bd;
+            const int k = o >> lw, j = o & (W - 1);
+            float2 y = xv[u];
             if (MUL_IKZ) {
-                float kz = kf * (float)e;
+                const float kz = kf * (float)k;
                 y = make_float2(-kz * y.y, kz * y.x);
             }
-            L[e] = cscale(y, scale);
+            Lb[j * (M + 1) + k] = cscale(y, scale);
         }
-        if (t == 0) L[M] = MUL_IKZ ? make_float2(0.0f, 0.0f) : cscale(xm, scale);  // kz Nyquist
+        if (threadIdx.x < W)  // kz Nyquist plane
+            Lb[threadIdx.x * (M + 1) + M] = MUL_IKZ ? make_float2(0.0f, 0.0f) : cscale(xm, scale);
     }
     __syncthreads();
+    float2* L = Lb + line * (M + 1);
     float2 v[R];
-    if (active) {
-        eng.first(t, [&](int q, int k) {
-            float2 xk = L[k];
-            float2 xc = cconj(L[M - k]);
-            float2 d = cmul(cconj(twl[k]), csub(xk, xc));
-            v[q] = make_float2(xk.x + xc.x - d.y, xk.y + xc.y + d.x);  // (xk + xc) + i d
-        });
-    }
+    eng.first(t, [&](int q, int k) {
+        float2 xk = L[k];
+        float2 xc = cconj(L[M - k]);
+        float2 d = cmul(cconj(twl[k]), csub(xk, xc));
+        v[q] = make_float2(xk.x + xc.x - d.y, xk.y + xc.y + d.x);  // (xk + xc) + i d
+    });
     __syncthreads();
-    eng.template run<true>(v, L, t, twl, active);
-    if (!active) return;
-    float2* dst = reinterpret_cast<float2*>(out + row * out_row);
-    eng.last(t, [&](int q, int e) { store_stream(dst + e, v[q]); });
+    eng.template run<true>(v, L, t, twl, true);
+    float2* dst = reinterpret_cast<float2*>(out + (first + line) * out_row);
+    eng.last(t, [&](int q, int e) {
+        store_stream(dst + e, v[q]);
+        if (ghost && e == 0) store_stream(dst + M, v[q]);
+    });
 }
 
-// ------------------------------------------------------------------ strided column passes
+// ------------------------------------------------------------------ y rows
 
-template <class LE, int TK, bool INV>
-__global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, ColGeom cg, LE eng,
-                                                  const float2* tw) {
+// Complex rows of n contiguous values (the rows (kz, x) of the transposed spectrum), transformed
+// in place, W lines per block: OPR 0 forward, 1 inverse, 2 the y inverse of the force: A <-
+// IFFT_y[i k_y A] (the k_y Nyquist entry set to 0) and S <- IFFT_y[A].
+template <class LE, int OPR>
+__global__ void __launch_bounds__(512) k_fft_rows(float2* A, float2* S, long bstride, long nrows, long plane,
+                                                  LE eng, const float2* tw, float kf) {
     constexpr int R = LE::kR;
     constexpr int TW = LE::kTwN;
     extern __shared__ float2 lds[];
-    int t, c;
+    const int T = eng.T(), n = eng.n();
+    const int W = blockDim.x / T;
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const long row = (long)blockIdx.x * W + line;
+    const bool active = row < nrows;
+    const long kz = row / n;
+    const long roff = kz * plane + (row - kz * n) * n;  // row (kz, x) of the transposed spectrum
+    A += (long)blockIdx.y * bstride + roff;
+    float2* L = lds + TW + line * n;
+    float2 v[R], h[R];
+    if (active) {
+        eng.first(t, [&](int q, int e) {
+            const float2 a = load_stream(A + e);
+            if constexpr (OPR == 2) {
+                h[q] = a;
+                const int my = signed_mode(e, n);
+                const float ky = (2 * my == -n) ? 0.0f : kf * (float)my;
+                v[q] = make_float2(-ky * a.y, ky * a.x);
+            } else {
+                v[q] = a;
+            }
+        });
+    }
+    const float2* twl = stage_twiddles<TW>(tw, lds);
+    if constexpr (TW > 0) __syncthreads();
+    eng.template run<OPR != 0>(v, L, t, twl, active);
+    if (active) eng.last(t, [&](int q, int e) { store_stream(A + e, v[q]); });
+    if constexpr (OPR == 2) {
+        eng.template run<true>(h, L, t, twl, active);
+        if (active) {
+            float2* Sd = S + (long)blockIdx.y * bstride + roff;
+            eng.last(t, [&](int q, int e) { store_stream(Sd + e, h[q]); });
+        }
+    }
+}
+
+// ------------------------------------------------------------------ x columns
+
+// Forward x transform of every (kz, y) column.
+template <class LE, int TK>
+__global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, ColGeom cg, LE eng, const float2* tw) {
+    constexpr int R = LE::kR;
+    constexpr int TW = LE::kTwN;
+    extern __shared__ float2 lds[];
+    int t, c, plane;
     uint32_t base;
-    const bool active = col_setup<TK>(cg, t, base, c);
+    const bool active = col_setup<TK>(cg, t, base, c, plane);
     data += (long)blockIdx.y * bstride;
     const uint32_t es = (uint32_t)cg.es;
     float2 v[R];
     if (active) eng.first(t, [&](int q, int e) { v[q] = load_col<TK>(data + base + (uint32_t)e * es); });
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
-    eng.template run<INV>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
+    eng.template run<false>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
     if (!active) return;
     eng.last(t, [&](int q, int e) { store_col<TK>(data + base + (uint32_t)e * es, v[q]); });
 }
 
-// Fused x pass of the particle-mesh force.  Columns are (y, kz); the transform axis is x.
-// Forward x FFT, V = S / (k^2 n^3) (k = 0 -> 0), then A = IFFT_x[V] and B = IFFT_x[i k_x V]
-// (the k_x Nyquist plane of B set to 0).  ef: forward engine; ei: the same radices reversed, so
-// the inverse starts from the forward's output pattern without an LDS round trip.
+// Fused x pass of the particle-mesh force on the (kz, y) columns: forward x FFT,
+// V = S / (k^2 n^3) (k = 0 -> 0), then A = IFFT_x[V] and B = IFFT_x[i k_x V] (the k_x Nyquist plane
+// of B set to 0).  ef: forward engine; ei: the same radices reversed, so the inverse starts from
+// the forward's output pattern without an LDS round trip.
 template <class LF, class LI, int TK>
 __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A, float2* B, long bstride,
                                                      ColGeom cg, LF ef, LI ei, const float2* tw, float kf,
@@ -246,17 +310,16 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
     constexpr int R = LF::kR;
     constexpr int TW = pair_tw_entries<LF, LI>();
     extern __shared__ float2 lds[];
-    int t, c;
+    int t, c, plane;
     uint32_t base;
-    const bool active = col_setup<TK>(cg, t, base, c);
+    const bool active = col_setup<TK>(cg, t, base, c, plane);
     const long boff = (long)blockIdx.y * bstride;
     S += boff;
     A += boff;
     B += boff;
     const uint32_t es = (uint32_t)cg.es;
     const int n = ef.n();
-    const int yrow = c / cg.nzp;
-    const int my = signed_mode(yrow, n), mz = c - yrow * cg.nzp;
+    const int my = signed_mode(c, n), mz = plane;
     float2* L = lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk);
     float2 v[R], h[R];
     if (active) ef.first(t, [&](int q, int e) { v[q] = load_col<TK>(S + base + (uint32_t)e * es); });
@@ -280,42 +343,6 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
     ei.last(t, [&](int q, int e) { store_col<TK>(B + base + (uint32_t)e * es, h[q]); });
 }
 
-// y inverse of A giving two outputs: A <- IFFT_y[i k_y A] (Nyquist of k_y set to 0) and
-// S <- IFFT_y[A].  Columns are kz within one x plane.
-template <class LE, int TK>
-__global__ void __launch_bounds__(512) k_fft_y_split(float2* A, float2* S, long bstride, ColGeom cg, LE eng,
-                                                     const float2* tw, float kf) {
-    constexpr int R = LE::kR;
-    constexpr int TW = LE::kTwN;
-    extern __shared__ float2 lds[];
-    int t, c;
-    uint32_t base;
-    const bool active = col_setup<TK>(cg, t, base, c);
-    const long boff = (long)blockIdx.y * bstride;
-    A += boff;
-    S += boff;
-    const uint32_t es = (uint32_t)cg.es;
-    const int n = eng.n();
-    float2* L = lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk);
-    float2 v[R], h[R];
-    if (active) {
-        eng.first(t, [&](int q, int e) {
-            float2 a = load_col<TK>(A + base + (uint32_t)e * es);
-            h[q] = a;
-            int my = signed_mode(e, n);
-            float ky = (2 * my == -n) ? 0.0f : kf * (float)my;
-            v[q] = make_float2(-ky * a.y, ky * a.x);
-        });
-    }
-    const float2* twl = stage_twiddles<TW>(tw, lds);
-    if constexpr (TW > 0) __syncthreads();
-    eng.template run<true>(v, L, t, twl, active);
-    if (active) eng.last(t, [&](int q, int e) { store_col<TK>(A + base + (uint32_t)e * es, v[q]); });
-    eng.template run<true>(h, L, t, twl, active);
-    if (!active) return;
-    eng.last(t, [&](int q, int e) { store_col<TK>(S + base + (uint32_t)e * es, h[q]); });
-}
-
 // x inverse with a multiplier taken from the full spectrum: W = IFFT_x[M(k) spec].
 //   MUL_SCALE: M = scale;  MUL_IK: M = i k_a / k^2 * scale;  MUL_KK: M = k_a k_b / k^2 * scale.
 // A factor k_d is zeroed on the Nyquist plane of axis d when it appears to an odd power.
@@ -326,17 +353,15 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
     constexpr int R = LE::kR;
     constexpr int TW = LE::kTwN;
     extern __shared__ float2 lds[];
-    int t, c;
+    int t, c, plane;
     uint32_t base;
-    const bool active = col_setup<TK>(cg, t, base, c);
+    const bool active = col_setup<TK>(cg, t, base, c, plane);
     spec += (long)blockIdx.y * spec_bstride;
     W += (long)blockIdx.y * w_bstride;
     const uint32_t es = (uint32_t)cg.es;
     const int n = eng.n();
-    const int yrow = c / cg.nzp;
-    const int my = signed_mode(yrow, n);
-    const int mzr = c - yrow * cg.nzp;
-    const int mz = (2 * mzr == n) ? -mzr : mzr;  // the kz = n/2 column is the Nyquist plane
+    const int my = signed_mode(c, n);
+    const int mz = (2 * plane == n) ? -plane : plane;  // the kz = n/2 plane is the Nyquist plane
     float2 v[R];
     if (active) {
         eng.first(t, [&](int q, int e) {
@@ -369,14 +394,20 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
 
 // ------------------------------------------------------------------ launches
 
-enum FftOp { OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ, OP_COLS_FWD, OP_COLS_INV, OP_X_GREEN, OP_Y_SPLIT, OP_X_MULT };
+enum FftOp {
+    OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ,          // z passes (line length n/2)
+    OP_ROWS_FWD, OP_ROWS_INV, OP_ROWS_SPLIT,       // y rows
+    OP_COLS_FWD, OP_X_GREEN, OP_X_MULT             // x columns
+};
+inline bool is_z_op(FftOp op) { return op <= OP_Z_C2R_IKZ; }
+inline bool is_rows_op(FftOp op) { return op >= OP_ROWS_FWD && op <= OP_ROWS_SPLIT; }
 
 // Everything one pass launch needs; each op reads its own subset.
 struct FftLaunch {
     FftOp op;
     int n = 0;      // line length of the kernel's transform (n/2 for the z passes)
     int R = 0;      // values per thread
-    int width = 0;  // lines per block (z) or columns per tile
+    int width = 0;  // lines per block (z, rows) or columns per tile (x)
     bool probe = false;  // static launchers: only report whether the shape exists
     dim3 grid, block;
     size_t lds = 0;
@@ -386,10 +417,13 @@ struct FftLaunch {
     float* rout = nullptr;
     const float2* cin = nullptr;
     float2* cout = nullptr;
-    long in_row = 0, in_bstride = 0, out_row = 0, out_bstride = 0, nrows = 0;
+    long in_row = 0, in_bstride = 0, out_row = 0, out_bstride = 0;
+    long plane = 0;  // kz-plane stride of the transposed spectrum (z passes, y rows)
+    int mesh_n = 0, lw = 0, ghost = 0;
     float pa = 1.0f, pb = 0.0f;
-    // column passes: x_green (S = c0, A = d0, B = d1), y_split (A = d0, S = d1), cols (d0),
+    // rows: A = d0, S = d1, b0, nrows; columns: x_green (S = c0, A = d0, B = d1), cols (d0),
     // x_mult (spec = c0, W = d0)
+    long nrows = 0;
     const float2* c0 = nullptr;
     float2* d0 = nullptr;
     float2* d1 = nullptr;
@@ -412,8 +446,8 @@ inline hipError_t go_z_r2c(const FftLaunch& L, LE e) {
     auto kern = k_fft_z_r2c<LE>;
     const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.rin, L.in_row, L.in_bstride, L.cout, L.out_row,
-                       L.out_bstride, L.nrows, e, L.tw, L.pa, L.pb);
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.rin, L.in_row, L.in_bstride, L.cout, L.out_bstride,
+                       L.mesh_n, L.plane, L.lw, e, L.tw, L.pa, L.pb);
     return hipGetLastError();
 }
 
@@ -422,14 +456,23 @@ inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
     auto kern = k_fft_z_c2r<LE, MUL>;
     const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.in_row, L.in_bstride, L.rout, L.out_row,
-                       L.out_bstride, L.nrows, e, L.tw, L.kf, L.scale);
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.in_bstride, L.rout, L.out_row, L.out_bstride,
+                       L.mesh_n, L.plane, L.lw, L.ghost, e, L.tw, L.kf, L.scale);
     return hipGetLastError();
 }
 
-template <class LE, int TK, bool INV>
+template <class LE, int OPR>
+inline hipError_t go_rows(const FftLaunch& L, LE e) {
+    auto kern = k_fft_rows<LE, OPR>;
+    const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.d0, L.d1, L.b0, L.nrows, L.plane, e, L.tw, L.kf);
+    return hipGetLastError();
+}
+
+template <class LE, int TK>
 inline hipError_t go_cols(const FftLaunch& L, LE e) {
-    auto kern = k_fft_cols<LE, TK, INV>;
+    auto kern = k_fft_cols<LE, TK>;
     const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
     hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.d0, L.b0, L.cg, e, L.tw);
@@ -446,15 +489,6 @@ inline hipError_t go_x_green(const FftLaunch& L, LF f, LI i) {
 }
 
 template <class LE, int TK>
-inline hipError_t go_y_split(const FftLaunch& L, LE e) {
-    auto kern = k_fft_y_split<LE, TK>;
-    const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
-    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.d0, L.d1, L.b0, L.cg, e, L.tw, L.kf);
-    return hipGetLastError();
-}
-
-template <class LE, int TK>
 inline hipError_t go_x_mult(const FftLaunch& L, LE e) {
     auto kern = k_fft_x_mult<LE, TK>;
     const size_t lds = L.lds + tw_lds_bytes(LE::kTwN);
@@ -464,19 +498,29 @@ inline hipError_t go_x_mult(const FftLaunch& L, LE e) {
     return hipGetLastError();
 }
 
-// Static-plan launchers for column passes of line length N with R values per thread and TK
-// columns per tile, and for z passes of line length M with R values per thread.
+// Static-plan launchers: x columns of line length N with R values per thread and TK columns per
+// tile, y rows of length N, z passes of line length M.
 template <int N, int R, int TK>
 inline hipError_t static_cols_ops(const FftLaunch& L) {
     using F = StatLine<N, R, TK, 1, false>;
     using I = StatLine<N, R, TK, 1, true>;
     if (L.probe) return hipSuccess;
     switch (L.op) {
-        case OP_COLS_FWD: return go_cols<F, TK, false>(L, F{});
-        case OP_COLS_INV: return go_cols<F, TK, true>(L, F{});
+        case OP_COLS_FWD: return go_cols<F, TK>(L, F{});
         case OP_X_GREEN: return go_x_green<F, I, TK>(L, F{}, I{});
-        case OP_Y_SPLIT: return go_y_split<F, TK>(L, F{});
         case OP_X_MULT: return go_x_mult<F, TK>(L, F{});
+        default: return hipErrorNotSupported;
+    }
+}
+
+template <int N, int R>
+inline hipError_t static_rows_ops(const FftLaunch& L) {
+    using E = StatLine<N, R, 1, 1, false>;
+    if (L.probe) return hipSuccess;
+    switch (L.op) {
+        case OP_ROWS_FWD: return go_rows<E, 0>(L, E{});
+        case OP_ROWS_INV: return go_rows<E, 1>(L, E{});
+        case OP_ROWS_SPLIT: return go_rows<E, 2>(L, E{});
         default: return hipErrorNotSupported;
     }
 }

@@ -60,27 +60,29 @@ __device__ double bbks_t(double k, double gamma) {
     return log1p(2.34 * q) / (2.34 * q) * pow(poly, -0.25);
 }
 
-__global__ void k_ic_scale(float2* spec, long bstride, int n, int nzp, int mvalid, float kf, double amp,
+// Over the transposed half spectrum [kz][x][y] (kz planes `plane` apart), kz < mvalid = n/2 + 1.
+__global__ void k_ic_scale(float2* spec, long bstride, int n, long plane, int mvalid, float kf, double amp,
                            double gamma, double n_s, double norm) {
-    long total = (long)n * n * nzp;
+    const long nn = (long)n * n;
+    const long total = nn * mvalid;
     spec += (long)blockIdx.y * bstride;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-        int kz = (int)(i % nzp);
-        if (kz >= mvalid) continue;
-        long rr = i / nzp;
+        const int kz = (int)(i / nn);
+        const long rr = i - kz * nn;
         int ky = (int)(rr % n), kx = (int)(rr / n);
         int mx = kx < n / 2 ? kx : kx - n, my = ky < n / 2 ? ky : ky - n;
         double m2 = (double)mx * mx + (double)my * my + (double)kz * kz;
-        float2 v = spec[i];
+        float2* sp = spec + (long)kz * plane + rr;
+        float2 v = *sp;
         if (m2 == 0.0) {
-            spec[i] = make_float2(0.0f, 0.0f);
+            *sp = make_float2(0.0f, 0.0f);
             continue;
         }
         double k = (double)kf * sqrt(m2);
         double t = bbks_t(k, gamma);
         double pk = amp * pow(k, n_s) * t * t;
         float f = (float)sqrt(pk * norm);
-        spec[i] = make_float2(v.x * f, v.y * f);
+        *sp = make_float2(v.x * f, v.y * f);
     }
 }
 
@@ -90,7 +92,7 @@ hipError_t ic_scale_spectrum(float2* spec, long bstride, const Mesh3& g, int n_r
     long blocks = (total + 255) / 256;
     if (blocks > 65535) blocks = 65535;
     ProfScope ps(PROF_IC, st);
-    hipLaunchKernelGGL(k_ic_scale, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.nzp,
+    hipLaunchKernelGGL(k_ic_scale, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.plane,
                        g.m + 1, kf, amp, gamma, n_s, norm);
     return hipGetLastError();
 }

@@ -200,7 +200,7 @@ int cola_lc_adam(const cola_lc_net* net, int32_t t, float lr, float beta1, float
 size_t cola_pm_fields_workspace_bytes(int32_t n_mesh) {
     if (!fft_size_ok(n_mesh) || n_mesh > kMaxLcMesh) return 0;
     const Mesh3 g = make_mesh(n_mesh);
-    return 3 * lc_align(g.bytes()) + lc_align((size_t)n_mesh * sizeof(float2));
+    return 4 * lc_align(g.bytes()) + lc_align((size_t)n_mesh * sizeof(float2));
 }
 
 int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, float* delta, float* g[3],
@@ -217,7 +217,8 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
     float2* S = reinterpret_cast<float2*>(b);
     float2* A = reinterpret_cast<float2*>(b + lc_align(gm.bytes()));
     float2* B = reinterpret_cast<float2*>(b + 2 * lc_align(gm.bytes()));
-    float2* tw = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
+    float2* C = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
+    float2* tw = reinterpret_cast<float2*>(b + 4 * lc_align(gm.bytes()));
     const long row = 2L * gm.nzp;
     float* s_real = reinterpret_cast<float*>(S);
     const double cells = (double)n_mesh * n_mesh * n_mesh;
@@ -228,10 +229,10 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
     LC_TRY(cic_deposit_absolute(pos, n, n_mesh, (float)(n_mesh / box), row, s_real, st));
     LC_TRY(density_finish(s_real, row, n_mesh, (float)(cells / (double)n), -1.0f, st));
     if (delta) LC_TRY(mesh_unpad(s_real, row, n_mesh, delta, st));
-    LC_TRY(fft_zy_forward(s_real, row, 0, S, 0, gm, tw, 1, 1.0f, 0.0f, st));
-    LC_TRY(pm_force_from_spectrum(S, A, B, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
-    const float* f[3] = {reinterpret_cast<const float*>(B), reinterpret_cast<const float*>(A),
-                         reinterpret_cast<const float*>(S)};
+    LC_TRY(fft_zy_forward(s_real, row, 0, A, 0, gm, tw, 1, 1.0f, 0.0f, st));
+    LC_TRY(pm_force_from_spectrum(A, B, S, C, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
+    const float* f[3] = {reinterpret_cast<const float*>(C), reinterpret_cast<const float*>(B),
+                         reinterpret_cast<const float*>(A)};
     if (g)
         for (int d = 0; d < 3; ++d) LC_TRY(mesh_unpad(f[d], row, n_mesh, g[d], st));
     if (acc) LC_TRY(gather_absolute(pos, n, n_mesh, box, f, row, acc, st));
@@ -250,15 +251,16 @@ int cola_mesh_force(int32_t n_mesh, double box, const float* delta, float* g[3],
     float2* S = reinterpret_cast<float2*>(b);
     float2* A = reinterpret_cast<float2*>(b + lc_align(gm.bytes()));
     float2* B = reinterpret_cast<float2*>(b + 2 * lc_align(gm.bytes()));
-    float2* tw = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
+    float2* C = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
+    float2* tw = reinterpret_cast<float2*>(b + 4 * lc_align(gm.bytes()));
     const long row = 2L * gm.nzp;
     ws_forget(ws);
     (void)hipGetLastError();
     LC_TRY(launch_twiddles(tw, n_mesh, st));
-    LC_TRY(fft_zy_forward(delta, n_mesh, 0, S, 0, gm, tw, 1, 1.0f, 0.0f, st));
-    LC_TRY(pm_force_from_spectrum(S, A, B, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
-    const float* f[3] = {reinterpret_cast<const float*>(B), reinterpret_cast<const float*>(A),
-                         reinterpret_cast<const float*>(S)};
+    LC_TRY(fft_zy_forward(delta, n_mesh, 0, A, 0, gm, tw, 1, 1.0f, 0.0f, st));
+    LC_TRY(pm_force_from_spectrum(A, B, S, C, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
+    const float* f[3] = {reinterpret_cast<const float*>(C), reinterpret_cast<const float*>(B),
+                         reinterpret_cast<const float*>(A)};
     for (int d = 0; d < 3; ++d) LC_TRY(mesh_unpad(f[d], row, n_mesh, g[d], st));
     return COLA_OK;
 }

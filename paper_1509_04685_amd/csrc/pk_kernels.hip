@@ -3,7 +3,8 @@
 //
 // Bin b >= 1 holds the modes with b^2 <= |m|^2 < (b+1)^2, decided on integers so that every
 // implementation bins a mode identically; k = 0 is excluded.  Each half-spectrum mode counts
-// twice (itself and its mirror) except on the kz = 0 and kz = n/2 planes.
+// twice (itself and its mirror) except on the kz = 0 and kz = n/2 planes.  The spectrum is the
+// transposed half spectrum [kz][x][y] of the FFT passes.
 
 #include "cola_internal.h"
 
@@ -22,7 +23,7 @@ __device__ __forceinline__ float sinc_pi(float x) {  // sin(pi x) / (pi x)
     return x == 0.0f ? 1.0f : sinpif(x) / (3.14159265358979323846f * x);
 }
 
-__global__ void k_pk_bin(const float2* spec, long bstride, int n, int nzp, int n_bins, double* ksum,
+__global__ void k_pk_bin(const float2* spec, long bstride, int n, long plane, int n_bins, double* ksum,
                          double* psum, double* cnt, double kf) {
     __shared__ double sk[kMaxBinsLds], sp[kMaxBinsLds], sc[kMaxBinsLds];
     const bool use_lds = n_bins <= kMaxBinsLds;
@@ -37,16 +38,17 @@ __global__ void k_pk_bin(const float2* spec, long bstride, int n, int nzp, int n
     const int m = n / 2;
     const long total = (long)n * n * (m + 1);
     const float inv_n = 1.0f / (float)n;
+    const long nn = (long)n * n;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-        int kz = (int)(i % (m + 1));
-        long rr = i / (m + 1);
+        const int kz = (int)(i / nn);  // transposed spectrum [kz][x][y], planes `plane` apart
+        const long rr = i - kz * nn;
         int ky = (int)(rr % n), kx = (int)(rr / n);
         int mx = kx < m ? kx : kx - n, my = ky < m ? ky : ky - n;
         long m2 = (long)mx * mx + (long)my * my + (long)kz * kz;
         if (m2 == 0) continue;
         int b = isqrt_floor(m2);
         if (b >= n_bins) continue;
-        float2 d = spec[rr * nzp + kz];
+        float2 d = spec[(long)kz * plane + rr];
         float w1 = sinc_pi(mx * inv_n) * sinc_pi(my * inv_n) * sinc_pi(kz * inv_n);
         float w2 = w1 * w1;
         float pw = (d.x * d.x + d.y * d.y) / (w2 * w2);
@@ -79,7 +81,7 @@ hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, 
     long blocks = (total + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     ProfScope ps(PROF_PK, st);
-    hipLaunchKernelGGL(k_pk_bin, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.nzp,
+    hipLaunchKernelGGL(k_pk_bin, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.plane,
                        n_bins, ksum, psum, cnt, kf);
     return hipGetLastError();
 }
@@ -87,7 +89,7 @@ hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, 
 // Multipoles about the line of sight `los` (Sec. 6): the same shells, each mode weighted by the
 // Legendre polynomials L_2(mu) = (3 mu^2 - 1) / 2 and L_4(mu) = (35 mu^4 - 30 mu^2 + 3) / 8 of
 // mu = m_los / |m| (mu^2 from integers, so it is exact up to one division).
-__global__ void k_pk_bin_ell(const float2* spec, long bstride, int n, int nzp, int n_bins, int los, double* ksum,
+__global__ void k_pk_bin_ell(const float2* spec, long bstride, int n, long plane, int n_bins, int los, double* ksum,
                              double* p0, double* p2, double* p4, double* cnt, double kf) {
     __shared__ double sk[kMaxBinsLds], s0[kMaxBinsLds], s2[kMaxBinsLds], s4[kMaxBinsLds], sc[kMaxBinsLds];
     const bool use_lds = n_bins <= kMaxBinsLds;
@@ -104,16 +106,17 @@ __global__ void k_pk_bin_ell(const float2* spec, long bstride, int n, int nzp, i
     const int m = n / 2;
     const long total = (long)n * n * (m + 1);
     const float inv_n = 1.0f / (float)n;
+    const long nn = (long)n * n;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-        int kz = (int)(i % (m + 1));
-        long rr = i / (m + 1);
+        const int kz = (int)(i / nn);  // transposed spectrum [kz][x][y], planes `plane` apart
+        const long rr = i - kz * nn;
         int ky = (int)(rr % n), kx = (int)(rr / n);
         int mx = kx < m ? kx : kx - n, my = ky < m ? ky : ky - n;
         long m2 = (long)mx * mx + (long)my * my + (long)kz * kz;
         if (m2 == 0) continue;
         int b = isqrt_floor(m2);
         if (b >= n_bins) continue;
-        float2 d = spec[rr * nzp + kz];
+        float2 d = spec[(long)kz * plane + rr];
         float w1 = sinc_pi(mx * inv_n) * sinc_pi(my * inv_n) * sinc_pi(kz * inv_n);
         float w2 = w1 * w1;
         const double pw = (double)((d.x * d.x + d.y * d.y) / (w2 * w2));
@@ -156,7 +159,7 @@ hipError_t pk_bin_multipoles(const float2* spec, long bstride, const Mesh3& g, i
     long blocks = (total + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     ProfScope ps(PROF_PK, st);
-    hipLaunchKernelGGL(k_pk_bin_ell, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.nzp,
+    hipLaunchKernelGGL(k_pk_bin_ell, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.plane,
                        n_bins, los, ksum, p0, p2, p4, cnt, kf);
     return hipGetLastError();
 }

@@ -44,23 +44,40 @@ __device__ __forceinline__ void lagr_index(uint32_t p, int n_part, int& i, int& 
     l = (int)(r - jj * np);
 }
 
-// CIC gather of three meshes at one particle.
+// The two z corners of a mesh row as one 8-byte load: the force meshes' rows carry the values of
+// z = 0, 1 again at z = n, n + 1, so the pair (m, m + 1) never wraps.
+__device__ __forceinline__ float2 load_pair(const float* p) {
+    float2 v;
+    __builtin_memcpy(&v, p, sizeof(float2));
+    return v;
+}
+
+// CIC gather of three force meshes (rows with the ghost values) at one particle.
 __device__ __forceinline__ void gather3(const float* fx, const float* fy, const float* fz, long row, int n,
                                         const Cell& cx, const Cell& cy, const Cell& cz, float g[3]) {
-    const int x0 = cx.m, x1 = wrap1(cx.m, n), y0 = cy.m, y1 = wrap1(cy.m, n), z0 = cz.m, z1 = wrap1(cz.m, n);
+    const int xs[2] = {cx.m, wrap1(cx.m, n)}, ys[2] = {cy.m, wrap1(cy.m, n)};
     const float wx[2] = {1.0f - cx.f, cx.f}, wy[2] = {1.0f - cy.f, cy.f}, wz[2] = {1.0f - cz.f, cz.f};
-    const int xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    float2 vx[4], vy[4], vz[4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {  // the twelve loads are issued together
+            const long r = ((long)xs[a] * n + ys[b]) * row + cz.m;
+            vx[2 * a + b] = load_pair(fx + r);
+            vy[2 * a + b] = load_pair(fy + r);
+            vz[2 * a + b] = load_pair(fz + r);
+        }
     g[0] = g[1] = g[2] = 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            long r = ((long)xs[a] * n + ys[b]) * row;
-            float wab = wx[a] * wy[b];
-            float w0 = wab * wz[0], w1 = wab * wz[1];
-            g[0] += w0 * fx[r + z0] + w1 * fx[r + z1];
-            g[1] += w0 * fy[r + z0] + w1 * fy[r + z1];
-            g[2] += w0 * fz[r + z0] + w1 * fz[r + z1];
+            const float wab = wx[a] * wy[b];
+            const float w0 = wab * wz[0], w1 = wab * wz[1];
+            const int q = 2 * a + b;
+            g[0] += w0 * vx[q].x + w1 * vx[q].y;
+            g[1] += w0 * vy[q].x + w1 * vy[q].y;
+            g[2] += w0 * vz[q].x + w1 * vz[q].y;
         }
 }
 
@@ -165,6 +182,26 @@ __global__ void k_density_finish(float* mesh, long row, int n, float scale, floa
         float* c = mesh + r * row + z;
         *c = fmaf(*c, scale, offset);
     }
+}
+
+// z = 0, 1 copied to z = n, n + 1 in every row of the three meshes.
+__global__ void k_mesh_ghosts(float* fx, float* fy, float* fz, long row, int n, long bstride) {
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;  // row index
+    if (r >= (long)n * n) return;
+    const long o = (long)blockIdx.y * bstride + r * row;
+    float* f[3] = {fx, fy, fz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        f[d][o + n] = f[d][o];
+        f[d][o + n + 1] = f[d][o + 1];
+    }
+}
+
+hipError_t mesh_ghosts(float* const f[3], long row, int n, long bstride, int n_real, hipStream_t st) {
+    ProfScope ps(PROF_OTHER, st);
+    hipLaunchKernelGGL(k_mesh_ghosts, dim3((unsigned)(((long)n * n + 255) / 256), n_real), dim3(256), 0, st, f[0], f[1],
+                       f[2], row, n, bstride);
+    return hipGetLastError();
 }
 
 hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float offset, hipStream_t st) {
