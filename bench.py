@@ -243,6 +243,61 @@ def ensemble_bench(cola, torch, reps):
            "first_launch_with_capture_s": t_capture, "replays_timed": reps,
            "classes": "24 x (96^3 particles, 288^3 mesh, L 300) + 24 x (128^3, 384^3, L 400), 40 nodes, "
                       "P(k) at z=0, one hipGraph (classes on forked streams)"}
+    # z = 0 spectra of every member (k, P) for the learned ensemble's comparison
+    spectra = [(it["out"][0][0].cpu().numpy(), it["out"][1][0].cpu().numpy()) for it in ens.items]
+    del ens
+    cola.ensemble_release()
+    torch.cuda.empty_cache()
+    return out, spectra
+
+
+def learned_ensemble_bench(cola, torch, reps, plain, plain_spectra):
+    """The batched learned-correction form: the same 48 seeds on 1x meshes (96^3 and 128^3 cells, the
+    trained network's 3 h^-1 Mpc resolution) with the network in every step, captured in one
+    hipGraph, against the plain 3x ensemble above: realizations per hour, and max |P/P_3x - 1| for
+    k < 1 of every member at z = 0 on the plain ensemble's analysis meshes (288^3, 384^3)."""
+    import numpy as np
+    from paper_1509_04685_amd import learned as L
+    path = os.path.join(ROOT, "paper_1509_04685_amd", "lc_weights_c16.json")
+    if not os.path.exists(path):
+        return {"skipped": "no trained weights"}
+    net, _ = L.load_net(path)
+    spec = []
+    total_ps = 0
+    for name in ("ens_96_288", "ens_128_384"):
+        c = W.CONFIGS[name]
+        prob = cola.make_problem(c["box"], c["n_part"], 1, c["z_init"], c["n_steps"], n_real=len(c["seeds"]))
+        n_pk = c["n_part"] * c["pm_factor"]
+        spec.append(dict(prob=prob, seeds=c["seeds"], a_out=(1.0,), n_pk=n_pk, n_bins=n_pk // 2, net=net))
+        total_ps += len(c["seeds"]) * c["n_part"] ** 3 * c["n_steps"]
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    ens = cola.Ensemble(spec, cosmo)
+    ens.autotune()
+    ens.run(graph=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ens.run(graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    n_real = sum(len(x["seeds"]) for x in spec)
+    errs = []
+    for it, (k3, p3) in zip(ens.items, plain_spectra):
+        kk, pp = it["out"][0][0].cpu().numpy(), it["out"][1][0].cpu().numpy()
+        for r in range(pp.shape[0]):
+            errs.append(L.max_error(kk[r], pp[r], p3[r]))
+    errs = np.array(errs)
+    out = {"realizations": n_real, "seconds_per_ensemble": sec, "realizations_per_hour": n_real * 3600.0 / sec,
+           "particle_steps_per_s": total_ps / sec,
+           "speedup_vs_plain_3x_ensemble": round(plain["seconds_per_ensemble"] / sec, 3),
+           "max_pk_error_k_lt_1": {"worst": round(float(errs.max()), 4), "median": round(float(np.median(errs)), 4),
+                                   "members_within_1pct": int((errs <= 0.01).sum())},
+           "classes": "24 x (96^3 particles, 96^3 mesh, L 300) + 24 x (128^3, 128^3, L 400) with the trained network "
+                      "(cola_step_lc), 40 nodes, P(k) at z=0 on 288^3 / 384^3, one hipGraph; error of each member "
+                      "against the plain 3x ensemble member of the same seed"}
     del ens
     cola.ensemble_release()
     torch.cuda.empty_cache()
@@ -632,9 +687,14 @@ def main():
         del st, ws, outs
         torch.cuda.empty_cache()
         print("[bench] ensemble: 48 seeds in two shape classes, hipGraph", file=sys.stderr, flush=True)
-        result["ensemble"] = ensemble_bench(cola, torch, reps=2)
+        result["ensemble"], plain_spectra = ensemble_bench(cola, torch, reps=2)
         print(f"[bench] ensemble: {result['ensemble']['seconds_per_ensemble']:.2f} s per 48 realizations, "
               f"{result['ensemble']['realizations_per_hour']:.0f} realizations/hour", file=sys.stderr, flush=True)
+        if not args.no_learned:
+            print("[bench] learned ensemble: the same 48 seeds on 1x meshes with the network", file=sys.stderr,
+                  flush=True)
+            result["learned_ensemble"] = learned_ensemble_bench(cola, torch, 2, result["ensemble"], plain_spectra)
+            print(f"[bench] learned ensemble: {json.dumps(result['learned_ensemble'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline: float64 oracle, one step", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(cfg, seed)

@@ -174,54 +174,6 @@ int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo,
                           double* k_mean, double* p0, double* p2, double* p4, double* n_modes, void* ws,
                           size_t ws_bytes, void* stream);
 
-/* ---- ensembles ------------------------------------------------------------------------- */
-
-/* One shape class of an ensemble: n_real = prob.n_real realizations of one problem. */
-typedef struct {
-    cola_problem prob;
-    const uint64_t* seeds;   /* host, n_real seeds                                          */
-    cola_particles* parts;   /* device arrays of n_real * N_p^3 floats                       */
-    void* ws;                /* device workspace of cola_workspace_bytes(&prob, n_pk) bytes  */
-    size_t ws_bytes;
-    int32_t n_out;           /* P(k) outputs at the scale factors a_out (host, ascending)    */
-    const double* a_out;
-    int32_t n_pk, n_bins;
-    double* k_mean;          /* device, [n_out][n_real][n_bins] each                         */
-    double* pk;
-    double* n_modes;
-} cola_ensemble_class;
-
-/* Mock ensembles (Sec. 2.3: realizations that differ only in their seed; the paper's purpose is
- * ensembles of mocks, Sec. 1).  For every class: cola_ic_2lpt, then cola_step up to each output
- * node with cola_power_spectrum at each a_out, then cola_step to the last node -- all
- * realizations of a class advance together in batched launches.
- *   mode 0: launch eagerly on `stream`, classes one after the other.
- *   mode 1: capture the whole ensemble into one hipGraph, each class on its own stream forked
- *           from `stream` so the classes overlap, instantiate it, launch it on `stream` and keep
- *           the executable graph; a later call with identical arguments (same pointers, sizes,
- *           seeds, outputs, cosmology) relaunches it without host work.
- * On return every class's particles are at their last node.  cola_ensemble_release frees the
- * cached graphs and streams. */
-int cola_ensemble_run(int32_t n_classes, cola_ensemble_class* classes, const cola_cosmology* cosmo,
-                      int32_t mode, void* stream);
-int cola_ensemble_release(void);
-
-/* FFT autotuner.  Times every admissible kernel shape (values per thread, lines or columns per
- * block) of each FFT pass at the problem's force-mesh, lattice and P(k) sizes, on `stream`, and
- * keeps the fastest for every later call in this process (until then a fixed heuristic is
- * used).  Uses ws as scratch: its contents, including a cached force mesh, are destroyed --
- * call it before cola_ic_2lpt or set force_node = -1 afterwards.  Synchronises the stream.
- * report (host, may be NULL): one line per pass with the chosen shape and its time. */
-int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_bytes, void* stream,
-                  char* report, size_t report_len);
-
-/* Pins the kernel shape of one FFT pass kind at mesh side n for the rest of the process, as the
- * autotuner would: kind one of "z_r2c", "z_c2r", "cols_y", "cols_x", "x_green", "y_split",
- * "x_mult"; values_per_thread and width (lines per block for the z passes, columns per tile
- * otherwise) must form an admissible shape; use_static selects the compile-time plan of that
- * shape (COLA_ERR_INVALID_ARG if the library has none).  Host only: nothing is launched. */
-int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, int32_t width, int32_t use_static);
-
 /* ---- learned coarse-mesh force correction ---------------------------------------------- */
 
 /* Sec. 4.4 shows that a force mesh coarser than PM_grid = 3 biases haloes through the force
@@ -296,6 +248,62 @@ int cola_lc_loss(int32_t n_mesh, double box, const float* pos[3], int64_t n, con
  * clears net->grads and repacks the BF16 weights. */
 int cola_lc_adam(const cola_lc_net* net, int32_t t, float lr, float beta1, float beta2, float eps,
                  void* stream);
+
+/* ---- ensembles ------------------------------------------------------------------------- */
+
+/* One shape class of an ensemble: n_real = prob.n_real realizations of one problem. */
+typedef struct {
+    cola_problem prob;
+    const uint64_t* seeds;   /* host, n_real seeds                                          */
+    cola_particles* parts;   /* device arrays of n_real * N_p^3 floats                       */
+    void* ws;                /* device workspace of cola_workspace_bytes(&prob, n_pk) bytes  */
+    size_t ws_bytes;
+    int32_t n_out;           /* P(k) outputs at the scale factors a_out (host, ascending)    */
+    const double* a_out;
+    int32_t n_pk, n_bins;
+    double* k_mean;          /* device, [n_out][n_real][n_bins] each                         */
+    double* pk;
+    double* n_modes;
+    const cola_lc_net* net;  /* NULL: plain steps; else the class runs cola_step_lc with this
+                                network (N_g a multiple of 16)                               */
+    void* lc_ws;             /* device, cola_lc_workspace_bytes(N_g, C, n_real, 0) bytes when
+                                net is set                                                   */
+    size_t lc_ws_bytes;
+} cola_ensemble_class;
+
+/* Mock ensembles (Sec. 2.3: realizations that differ only in their seed; the paper's purpose is
+ * ensembles of mocks, Sec. 1).  For every class: cola_ic_2lpt, then cola_step (cola_step_lc with
+ * the class's network) up to each output node with cola_power_spectrum at each a_out, then to the
+ * last node -- all realizations of a class advance together in batched launches.  A captured
+ * graph reads the network's parameters from device memory at every replay, but keeps the scales
+ * and schedule it was captured with.
+ *   mode 0: launch eagerly on `stream`, classes one after the other.
+ *   mode 1: capture the whole ensemble into one hipGraph, each class on its own stream forked
+ *           from `stream` so the classes overlap, instantiate it, launch it on `stream` and keep
+ *           the executable graph; a later call with identical arguments (same pointers, sizes,
+ *           seeds, outputs, cosmology) relaunches it without host work.
+ * On return every class's particles are at their last node.  cola_ensemble_release frees the
+ * cached graphs and streams. */
+int cola_ensemble_run(int32_t n_classes, cola_ensemble_class* classes, const cola_cosmology* cosmo,
+                      int32_t mode, void* stream);
+int cola_ensemble_release(void);
+
+/* FFT autotuner.  Times every admissible kernel shape (values per thread, lines or columns per
+ * block) of each FFT pass at the problem's force-mesh, lattice and P(k) sizes, on `stream`, and
+ * keeps the fastest for every later call in this process (until then a fixed heuristic is
+ * used).  Uses ws as scratch: its contents, including a cached force mesh, are destroyed --
+ * call it before cola_ic_2lpt or set force_node = -1 afterwards.  Synchronises the stream.
+ * report (host, may be NULL): one line per pass with the chosen shape and its time. */
+int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_bytes, void* stream,
+                  char* report, size_t report_len);
+
+/* Pins the kernel shape of one FFT pass kind at mesh side n for the rest of the process, as the
+ * autotuner would: kind one of "z_r2c", "z_c2r", "rows_y", "cols_x", "x_green", "y_split",
+ * "x_mult"; values_per_thread and width (lines per block for the z passes and the y rows, a power
+ * of two dividing n for the z passes; columns per tile for the x passes) must form an admissible
+ * shape; use_static selects the compile-time plan of that
+ * shape (COLA_ERR_INVALID_ARG if the library has none).  Host only: nothing is launched. */
+int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, int32_t width, int32_t use_static);
 
 /* cola_step with the network's correction: at each force evaluation the density contrast and the
  * mesh force of every realization feed the network and dF is added to the force mesh before the

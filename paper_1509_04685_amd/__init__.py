@@ -228,8 +228,9 @@ def autotune(prob, ws, n_pk=0, state=None):
 class Ensemble:
     """Shape classes of seeded realizations run together (cola_ensemble_run).
 
-    classes: list of dicts with keys prob, seeds, a_out (tuple), n_pk, n_bins.  Allocates the
-    particle states, workspaces and P(k) outputs of every class.
+    classes: list of dicts with keys prob, seeds, a_out (tuple), n_pk, n_bins, and optionally net
+    (an LcNet: the class runs the corrected steps).  Allocates the particle states, workspaces and
+    P(k) outputs of every class.
     """
 
     def __init__(self, classes, cosmo, device="cuda"):
@@ -257,7 +258,15 @@ class Ensemble:
             e.n_pk = int(c["n_pk"])
             e.n_bins = n_bins
             e.k_mean, e.pk, e.n_modes = (_ptr(t) for t in out)
-            self.items.append(dict(prob=prob, state=st, ws=ws, seeds=seeds, a_out=a_out, out=out))
+            net = c.get("net")
+            lws = None
+            if net is not None:
+                lws = lc_workspace(prob.n_part * prob.pm_factor, net.channels, prob.n_real, device=device)
+                e.net = ctypes.cast(ctypes.pointer(net.c), ctypes.c_void_p)
+                e.lc_ws = _ptr(lws)
+                e.lc_ws_bytes = lws.numel()
+            self.items.append(dict(prob=prob, state=st, ws=ws, seeds=seeds, a_out=a_out, out=out, net=net,
+                                   lc_ws=lws))
         self.arr = arr
 
     def autotune(self):

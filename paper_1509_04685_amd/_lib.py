@@ -66,7 +66,8 @@ class EnsembleClass(ctypes.Structure):
                 ("parts", ctypes.POINTER(Particles)), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
                 ("n_out", ctypes.c_int32), ("a_out", ctypes.POINTER(ctypes.c_double)),
                 ("n_pk", ctypes.c_int32), ("n_bins", ctypes.c_int32),
-                ("k_mean", ctypes.c_void_p), ("pk", ctypes.c_void_p), ("n_modes", ctypes.c_void_p)]
+                ("k_mean", ctypes.c_void_p), ("pk", ctypes.c_void_p), ("n_modes", ctypes.c_void_p),
+                ("net", ctypes.c_void_p), ("lc_ws", ctypes.c_void_p), ("lc_ws_bytes", ctypes.c_size_t)]
 
 
 class LcNet(ctypes.Structure):

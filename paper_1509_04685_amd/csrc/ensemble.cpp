@@ -51,6 +51,22 @@ std::string make_key(int n_classes, const cola_ensemble_class* cls, const cola_c
         put(key, e.k_mean);
         put(key, e.pk);
         put(key, e.n_modes);
+        put(key, e.net);
+        put(key, e.lc_ws);
+        put(key, e.lc_ws_bytes);
+        if (e.net) {  // the host-side scales are baked into the captured launches
+            put(key, e.net->params);
+            put(key, e.net->packed);
+            for (int i = 0; i < 4; ++i) put(key, e.net->in_scale[i]);
+            put(key, e.net->out_scale);
+            put(key, e.net->out_scale_slope);
+            put(key, e.net->out_band);
+            put(key, e.net->n_knots);
+            for (int i = 0; i < 8; ++i) {
+                put(key, e.net->knot_a[i]);
+                put(key, e.net->knot_v[i]);
+            }
+        }
     }
     return key;
 }
@@ -62,6 +78,14 @@ int node_of(const std::vector<double>& a, double a_out) {
     return j;
 }
 
+// The class's steps to node j: plain, or corrected by the class's network.
+int advance(cola_ensemble_class& e, const cola_cosmology* cosmo, int j, hipStream_t st) {
+    if (e.net)
+        return cola_step_lc(&e.prob, cosmo, e.parts->node, j, e.parts, e.net, e.lc_ws, e.lc_ws_bytes, e.ws,
+                            e.ws_bytes, st);
+    return cola_step(&e.prob, cosmo, e.parts->node, j, e.parts, e.ws, e.ws_bytes, st);
+}
+
 int run_class(cola_ensemble_class& e, const cola_cosmology* cosmo, hipStream_t st) {
     int s = cola_ic_2lpt(&e.prob, cosmo, e.seeds, e.parts, e.ws, e.ws_bytes, st);
     if (s != COLA_OK) return s;
@@ -69,16 +93,17 @@ int run_class(cola_ensemble_class& e, const cola_cosmology* cosmo, hipStream_t s
     const long nb = (long)e.n_bins * e.prob.n_real;
     for (int k = 0; k < e.n_out; ++k) {
         int j = node_of(a, e.a_out[k]);
-        if (j > e.parts->node) {
-            s = cola_step(&e.prob, cosmo, e.parts->node, j, e.parts, e.ws, e.ws_bytes, st);
+        if (j > e.parts->node || (e.net && e.parts->force_node != j)) {
+            // a corrected class always steps (even to its own node) so that the corrected force
+            // of node j is cached for an output between nodes
+            s = advance(e, cosmo, j, st);
             if (s != COLA_OK) return s;
         }
         s = cola_power_spectrum(&e.prob, cosmo, e.parts, e.a_out[k], e.n_pk, e.n_bins, e.k_mean + k * nb,
                                 e.pk + k * nb, e.n_modes + k * nb, e.ws, e.ws_bytes, st);
         if (s != COLA_OK) return s;
     }
-    if (e.parts->node < e.prob.n_steps - 1)
-        s = cola_step(&e.prob, cosmo, e.parts->node, e.prob.n_steps - 1, e.parts, e.ws, e.ws_bytes, st);
+    if (e.parts->node < e.prob.n_steps - 1) s = advance(e, cosmo, e.prob.n_steps - 1, st);
     return s;
 }
 
@@ -91,6 +116,15 @@ int validate(int n_classes, const cola_ensemble_class* cls, const cola_cosmology
         size_t need = cola_workspace_bytes(&e.prob, e.n_out > 0 ? e.n_pk : 0);
         if (need == 0) return COLA_ERR_INVALID_ARG;
         if (e.ws_bytes < need) return COLA_ERR_WORKSPACE_TOO_SMALL;
+        if (e.net) {
+            if (!e.lc_ws) return COLA_ERR_INVALID_ARG;
+            const size_t lneed = cola_lc_workspace_bytes(e.prob.n_part * e.prob.pm_factor, e.net->channels,
+                                                         e.prob.n_real, 0);
+            if (lneed == 0) return COLA_ERR_UNSUPPORTED_SIZE;
+            if (e.lc_ws_bytes < lneed) return COLA_ERR_WORKSPACE_TOO_SMALL;
+            for (int c2 = 0; c2 < c; ++c2)
+                if (cls[c2].lc_ws == e.lc_ws) return COLA_ERR_INVALID_ARG;  // classes run concurrently
+        }
         for (int k = 1; k < e.n_out; ++k)
             if (!(e.a_out[k] > e.a_out[k - 1])) return COLA_ERR_INVALID_ARG;
         for (int c2 = 0; c2 < c; ++c2)

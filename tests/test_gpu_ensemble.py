@@ -162,3 +162,60 @@ def test_ensemble_pm_only_and_sampled_classes(cola):
         torch.cuda.synchronize()
         for (xe, _), (xg, _) in zip(eager, snapshot(ens)):
             assert np.array_equal(xg, xe), rep
+
+
+def test_learned_ensemble_matches_single_corrected_runs(cola):
+    """A class run with the learned correction (cola_step_lc per class): every member equals the
+    same seed advanced alone by cola_step_lc, including its output between nodes (which drifts with
+    the cached corrected force), eagerly and in graph replays; a plain class beside it is unchanged."""
+    say("learned ensemble vs single corrected runs")
+    from oracle import learned as olc
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    onet = olc.Net(channels=16, seed=5, in_scale=(0.25, 1.0, 1.0, 1.0), out_scale=0.5)
+    onet.w3 *= 10.0
+    flat = np.asarray(olc.flat_params(onet), dtype=np.float32)
+    net = cola.LcNet(16, params=flat, in_scale=onet.in_scale, out_scale=onet.out_scale, training=False)
+    box, n_part, n_steps, seeds, a_out = 64.0, 16, 6, (51, 52, 53), (0.5, 1.0)
+    prob = cola.make_problem(box, n_part, 1, 19.0, n_steps, n_real=len(seeds))
+    plain = cola.make_problem(120.0, 16, 3, 19.0, n_steps, n_real=2)
+    spec = [dict(prob=prob, seeds=seeds, a_out=a_out, n_pk=48, n_bins=24, net=net),
+            dict(prob=plain, seeds=(61, 62), a_out=(1.0,), n_pk=48, n_bins=24)]
+    ens = cola.Ensemble(spec, cosmo)
+    ens.run(graph=False)
+    torch.cuda.synchronize()
+    eager = snapshot(ens)
+    n = n_part ** 3
+    p1 = cola.make_problem(box, n_part, 1, 19.0, n_steps)
+    tab = cola.schedule_table(p1, cosmo)
+    lws = cola.lc_workspace(n_part, 16, 1)
+    for r, seed in enumerate(seeds):
+        st = cola.ParticleState(p1)
+        ws = cola.Workspace(p1, n_pk=48)
+        cola.ic_2lpt(p1, cosmo, [seed], st, ws)
+        for k, a in enumerate(a_out):
+            j = int((tab[:, 0] <= a * (1 + 1e-12)).sum()) - 1
+            cola.step_lc(p1, cosmo, st, j, net, lws, ws)
+            pk = cola.power_spectrum(p1, cosmo, st, a, 48, 24, ws)[1].cpu().numpy()[0]
+            got = ens.items[0]["out"][1][k, r].cpu().numpy()
+            sel = pk > 0
+            assert np.abs(got[sel] / pk[sel] - 1).max() < 1e-4, (seed, a)
+        cola.step_lc(p1, cosmo, st, n_steps - 1, net, lws, ws)
+        assert rel_rms(ens.items[0]["state"].x[:, r * n:(r + 1) * n].cpu().numpy(), st.x.cpu().numpy()) < 1e-6
+    # the plain class beside it is the plain run
+    for r, seed in enumerate((61, 62)):
+        pp = cola.make_problem(120.0, 16, 3, 19.0, n_steps)
+        st = cola.ParticleState(pp)
+        ws = cola.Workspace(pp, n_pk=48)
+        cola.ic_2lpt(pp, cosmo, [seed], st, ws)
+        cola.step(pp, cosmo, st, n_steps - 1, ws)
+        assert rel_rms(ens.items[1]["state"].x[:, r * n:(r + 1) * n].cpu().numpy(), st.x.cpu().numpy()) < 1e-5
+    for rep in range(2):
+        for it in ens.items:
+            it["state"].x.fill_(3.0)
+            it["out"][1].fill_(-1.0)
+        ens.run(graph=True)
+        torch.cuda.synchronize()
+        for (xe, pe), (xg, pg) in zip(eager, snapshot(ens)):
+            assert np.array_equal(xg, xe), rep
+            sel = pe > 0
+            assert np.abs(pg[sel] / pe[sel] - 1).max() < 1e-4, rep
