@@ -567,3 +567,131 @@ def test_p14_output_between_nodes_leaves_run_unchanged():
     near = cola.displacement_at(st, prob, sched, sched.a[j + 1] - 1e-12)
     cola.step(st, prob, sched, j + 1)
     assert np.allclose(near, st.disp, rtol=0, atol=1e-8)
+
+
+# --------------------------------------------------------------------------- P15: aliasing correction
+
+def _abs_modes(n):
+    m = [np.abs(v).astype(np.float64) for v in np.broadcast_arrays(*lpt.mode_integers(n))]
+    return m, m[0] ** 2 + m[1] ** 2 + m[2] ** 2
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_p15_aliasing_sum_flat_spectrum_closed_form(n):
+    """At n_eff = 0 the CIC aliasing sum is separable, and each axis sums to
+    sum_j sinc^4(pi (x + j)) = 1 - (2/3) sin^2(pi x) (the sum of (x + j)^-4 is
+    pi^4 (1 + 2 cos^2(pi x)) / (3 sin^4(pi x))).  The images dropped beyond |j_d| = J add at most
+    2 / (3 pi^4 (J - 1/2)^3) per axis, against a per-axis sum of at least 1/3."""
+    m, _ = _abs_modes(n)
+    closed = np.prod([1 - 2 / 3 * np.sin(np.pi * v / n) ** 2 for v in m], axis=0)
+    for J in (2, 6):
+        bound = 3 * 3 * 2 / (3 * np.pi ** 4 * (J - 0.5) ** 3)
+        err = np.abs(power.aliasing_sum(n, 0.0, J) / closed - 1).max()
+        assert 0 < err < bound, (J, err, bound)
+
+
+def test_p15_aliasing_sum_k_squared_closed_form():
+    """At n_eff = 2 the factor |u|^2 = sum_d u_d^2 splits the sum into three separable products;
+    with sum_j (x + j)^-2 = pi^2 / sin^2(pi x), the untruncated sum is
+      C = (n^2 / (pi^2 |m|^2)) sum_d sin^2(pi m_d / n) prod_{e != d} [1 - (2/3) sin^2(pi m_e / n)].
+    The truncated series approaches it from below, within 2 / (pi^2 (J - 1/2)) relative."""
+    n = 6
+    m, m2 = _abs_modes(n)
+    f = [1 - 2 / 3 * np.sin(np.pi * v / n) ** 2 for v in m]
+    g = [n * n * np.sin(np.pi * v / n) ** 2 / np.pi ** 2 for v in m]
+    ok = m2 > 0
+    closed = (g[0] * f[1] * f[2] + f[0] * g[1] * f[2] + f[0] * f[1] * g[2])[ok] / m2[ok]
+    prev = None
+    for J in (4, 12):
+        c = power.aliasing_sum(n, 2.0, J)[ok]
+        rel = 1 - c / closed
+        assert rel.min() > 0 and rel.max() < 2 / (np.pi ** 2 * (J - 0.5)), (J, rel.max())
+        if prev is not None:
+            assert np.all(rel < prev)
+        prev = rel
+
+
+def test_p15_aliasing_sum_reduces_to_the_window_without_images():
+    """No images: C = W^2, the plain CIC deconvolution, for any slope; and C is even in each m_d."""
+    n = 10
+    w2 = power.cic_window(n) ** 2
+    for a in (-2.5, 0.0, 1.0):
+        c = power.aliasing_sum(n, a, images=0)
+        assert np.allclose(c.ravel()[1:], w2.ravel()[1:], rtol=1e-13)
+    c = power.aliasing_sum(n, -1.5)
+    assert np.allclose(c[1:n // 2, :, :], c[n - 1:n // 2:-1, :, :][:n // 2 - 1], rtol=1e-13)
+
+
+def test_p15_local_slopes_of_a_power_law():
+    """An exact power law gives its exponent in every bin whose window holds two bins (whatever the
+    mode counts); empty bins and lone bins get 0; slopes are clamped to [-4, 4]."""
+    k = np.array([0.0, 0.1, 0.2, 0.0, 0.25, 0.3, 0.36, 0.8])
+    cnt = np.array([0.0, 6, 26, 0, 58, 80, 140, 900])
+    for a in (-2.3, 0.7):
+        pk = np.where(k > 0, 3.0 * np.where(k > 0, k, 1.0) ** a, 0.0)
+        s = power.local_slopes(k, pk, cnt)
+        assert np.allclose(s[[2, 4, 5, 6]], a, rtol=1e-12)
+        assert s[0] == 0 and s[3] == 0 and s[1] == 0 and s[7] == 0  # 0.1 and 0.8: no neighbour in the window
+    steep = np.where(k > 0, np.where(k > 0, k, 1.0) ** -9, 0.0)
+    assert np.all(power.local_slopes(k, steep, cnt)[[2, 4, 5, 6]] == -4.0)
+    # a kink: the slope of a window straddling it lies between the two exponents
+    kk = np.where(k > 0, k, 1.0) / 0.22
+    pk = np.where(k > 0, np.where(kk <= 1.0, kk ** -2.0, kk ** -1.0), 0.0)
+    s = power.local_slopes(k, pk, cnt)
+    assert -2.0 < s[4] < -1.0
+
+
+def test_p15_corrected_shot_noise_is_flat():
+    """Poisson particles have a flat spectrum 1/n_bar; the window-deconvolved estimate rises
+    towards the mesh corners (the aliased CIC sum over W^2), the corrected estimate stays flat."""
+    rng = np.random.default_rng(15)
+    box, n, n_part = 100.0, 32, 400_000
+    n_bar = n_part / box ** 3
+    pos = rng.uniform(0, box, (3, n_part))
+    _, pu, cnt = power.power_spectrum(pos, n, box, 27)
+    _, pc, cnt2 = power.power_spectrum_corrected(pos, n, box, 27)
+    assert np.array_equal(cnt, cnt2)
+    sel = cnt > 50
+    sig = np.sqrt(2.0 / cnt[sel])  # an exponential variable per mode pair
+    r = pc[sel] * n_bar
+    assert np.all(np.abs(r - 1) < 4 * sig + 0.005), np.abs(r - 1).max()
+    assert abs(np.average(r, weights=cnt[sel]) - 1) < 0.01
+    assert pu[20] * n_bar > 1.5  # what the correction removes near the corner (|m| = 20 > n/2)
+
+
+def _zeldovich_lattice(n_p, box, n_eff, sigma, seed):
+    """A lattice of n_p^3 particles displaced by a power-law Gaussian field (P ~ k^n_eff, rms
+    density sigma) to first order; no shot noise, the lattice harmonics alias only to k = 0 on a
+    mesh whose size divides n_p."""
+    rng = np.random.default_rng(seed)
+    f = np.fft.fftfreq(n_p, 1.0 / n_p)
+    mx, my, mz = f[:, None, None], f[None, :, None], np.arange(n_p // 2 + 1)[None, None, :]
+    m2 = mx ** 2 + my ** 2 + mz ** 2
+    safe = np.where(m2 > 0, m2, 1.0)
+    dk = sfft.rfftn(rng.standard_normal((n_p,) * 3)) * np.where(m2 > 0, safe ** (n_eff / 4), 0.0)
+    dk *= sigma / sfft.irfftn(dk, s=(n_p,) * 3).std()
+    kf = 2 * np.pi / box
+    q = (np.indices((n_p,) * 3).reshape(3, -1) + 0.5) * (box / n_p)
+    psi = [sfft.irfftn(1j * v / (safe * kf) * np.where(m2 > 0, dk, 0), s=(n_p,) * 3).ravel() for v in (mx, my, mz)]
+    return np.mod(q + np.array(psi), box)
+
+
+def test_p15_corrected_coarse_mesh_matches_a_fine_mesh():
+    """Jing (2005) in practice: a 16^3 mesh's corrected P(k) of power-law particles agrees with
+    the P(k) of the same particles on a 256^3 mesh (whose own aliasing is negligible at these k)
+    up to the coarse Nyquist frequency, where the window-deconvolved estimate is 20-40% high.
+    Averaged over four realizations: the correction works on expectation values, and each
+    realization's aliased modes add coherently (a few per cent of scatter per bin)."""
+    box, n, nb = 100.0, 16, 10
+    rc, ru = [], []
+    for seed in range(4):
+        pos = _zeldovich_lattice(128, box, -1.5, 0.2, 40 + seed)
+        _, pu, cnt = power.power_spectrum(pos, n, box, nb)
+        _, pc, _ = power.power_spectrum_corrected(pos, n, box, nb)
+        _, pf, _ = power.power_spectrum(pos, 256, box, nb)
+        rc.append(pc[1:] / pf[1:] - 1)
+        ru.append(pu[1:] / pf[1:] - 1)
+    rc, ru = np.mean(rc, 0), np.mean(ru, 0)
+    assert np.all(np.abs(rc[:8]) < 0.03), rc  # bins 1..8 (8 = Nyquist)
+    assert np.abs(rc[:8]).max() < 0.25 * np.abs(ru[:8]).max()
+    assert ru[7] > 0.2
