@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
     ap.add_argument("--no-haloes", action="store_true", help="skip the friends-of-friends halo measurement")
     ap.add_argument("--no-multipoles", action="store_true", help="skip the redshift-space multipole measurement")
+    ap.add_argument("--no-aliasing", action="store_true", help="skip the aliasing-corrected P(k) measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 512^3-particle runs (1536^3 plain mesh and 512^3 learned mesh)")
     ap.add_argument("--no-stepping", action="store_true",
                     help="skip the PM-only / time-sampling comparison (needs the halo measurement)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default FFT kernel shapes")
@@ -340,18 +343,24 @@ def abundance_error(counts, ref, min_count=20):
 
 
 def stepping_bench(cola, torch, cfg, pk_ref, halo_ref):
-    """What the 2LPT frame and the time sampling buy (Sec. 4.1, 4.3, Appendix B) on the headline
-    workload and seed: COLA and PM-only runs with 10, 20 and 40 nodes, and 40 logarithmic /
-    a^0.8 nodes, each against the timed 40-node linear COLA run (P(k) at z = 0 and haloes)."""
+    """What the 2LPT frame, the time sampling and the initial redshift buy (Sec. 4.1, 4.3, Appendix B)
+    on the headline workload and seed: COLA and PM-only runs with 10, 20 and 40 nodes, 40
+    logarithmic / a^0.8 nodes, 40 linear nodes from z_i = 9, 39 and 100, and 10 nodes from z_i = 9,
+    each against the timed 40-node linear COLA run from z_i = 19 (P(k) at z = 0 and haloes)."""
     import numpy as np
     from paper_1509_04685_amd import learned as L
     cosmo = cola.make_cosmology(**W.COSMOLOGY)
     n_pk = cfg["n_part"] * cfg["pm_factor"]
-    runs = [("cola", "linear", 10), ("cola", "linear", 20), ("pm", "linear", 10), ("pm", "linear", 20),
-            ("pm", "linear", 40), ("cola", "log", 40), ("cola", "power", 40)]
+    z0 = cfg["z_init"]
+    # (frame, sampling, nodes, z_i): step count and frame at the fiducial z_i, the samplings of
+    # Eq. 3, the initial-redshift sweep of Sec. 4.3 (40 linear nodes) and the 10-node default
+    runs = [("cola", "linear", 10, z0), ("cola", "linear", 20, z0), ("pm", "linear", 10, z0), ("pm", "linear", 20, z0),
+            ("pm", "linear", 40, z0), ("cola", "log", 40, z0), ("cola", "power", 40, z0),
+            ("cola", "linear", 40, 9.0), ("cola", "linear", 40, 39.0), ("cola", "linear", 40, 100.0),
+            ("cola", "linear", 10, 9.0)]
     out = {}
-    for frame, sampling, n_steps in runs:
-        prob = cola.make_problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], cfg["z_init"], n_steps,
+    for frame, sampling, n_steps, z_init in runs:
+        prob = cola.make_problem(cfg["box"], cfg["n_part"], cfg["pm_factor"], z_init, n_steps,
                                  sampling=sampling, sampling_power=0.8, frame=frame)
         st = cola.ParticleState(prob)
         ws = cola.Workspace(prob, n_pk=n_pk)
@@ -364,6 +373,8 @@ def stepping_bench(cola, torch, cfg, pk_ref, halo_ref):
         sel = (k > 0) & (k < 1.0)
         at = {f"{kk:g}": round(float(np.interp(kk, k[sel], pk[sel] / pk_ref[sel])) - 1.0, 4) for kk in (0.1, 0.3, 1.0)}
         name = f"{frame}_{sampling if sampling != 'power' else 'a0.8'}_{n_steps}"
+        if z_init != z0:
+            name += f"_zi{z_init:g}"
         out[name] = {"max_pk_error_k_lt_1": round(L.max_error(k, pk, pk_ref), 4), "pk_ratio_minus_1": at,
                      "haloes_gt_100": int(h["counts"].sum()), "halo_total_ratio": round(total, 4),
                      "max_halo_abundance_error": round(worst, 4)}
@@ -412,6 +423,91 @@ def multipoles_bench(cola, torch, prob, st, cfg, n_pk=1024):
             "p0_p2_p4_at_k": pick,
             "what": "plane-parallel redshift space (Eq. 5) at z = 0, multipoles in the P(k) shells (Eq. 6); "
                     "mode-weighted sums over k < 0.05 h/Mpc against linear theory"}
+
+
+def aliasing_bench(cola, torch, prob, cosmo, st, ws, n_pk, n_bins, reps=3, iterations=4):
+    """P(k) of the state at a = 1 with and without the Jing (2005) aliasing correction (Sec. 2.5):
+    the time of each estimate and what the correction changes."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    ms0, (km, p0, nm) = timed(lambda: cola.power_spectrum(prob, cosmo, st, 1.0, n_pk, n_bins, ws))
+    ms1, (_, p1, _) = timed(lambda: cola.power_spectrum_jing(prob, cosmo, st, 1.0, n_pk, n_bins, ws,
+                                                             iterations=iterations))
+    cola.profiler_enable(True)
+    cola.power_spectrum_jing(prob, cosmo, st, 1.0, n_pk, n_bins, ws, iterations=iterations)
+    groups = cola.profiler_read_groups()
+    cola.profiler_enable(False)
+    k, p0, p1 = km.cpu().numpy()[0], p0.cpu().numpy()[0], p1.cpu().numpy()[0]
+    sel = (k > 0) & (p0 > 0)
+    r = p1[sel] / p0[sel] - 1.0
+    k_nyq = np.pi * n_pk / prob.box
+    at = {f"{kk:g}": round(float(np.interp(kk, k[sel], r)), 5) for kk in (0.5, 1.0, 2.0) if kk < k[sel].max()}
+    at["k_nyquist"] = round(float(np.interp(k_nyq, k[sel], r)), 5)
+    passes = {f"{name}@{tag}": {"ms_per_launch": round(ms / cnt, 4), "launches": cnt}
+              for (name, tag), (ms, cnt) in groups.items() if name == "pk_alias"}
+    return {"ms_plain": round(ms0, 3), "ms_corrected": round(ms1, 3), "iterations": iterations,
+            "corrected_over_plain_minus_1": at, "k_nyquist": round(k_nyq, 4), "passes": passes,
+            "what": f"P(k) of the z = 0 state on the {n_pk}^3 mesh ({n_bins} bins): plain CIC-deconvolved "
+                    f"estimator vs the Jing (2005) aliasing correction; passes: @1 slopes + aliasing table "
+                    f"(one evaluation per class of sorted |m|), @2 rebinning, per iteration"}
+
+
+def large_bench(cola, torch):
+    """The 512^3-particle workload: plain COLA on the 1536^3 mesh (PM_grid 3), one realization after
+    a warm-up, then the learned form on the 512^3 mesh beside it (same seed, P(k) at z = 0 on the
+    1536^3 analysis mesh)."""
+    cfg = W.CONFIGS["plain_512_1536"]
+    box, n_part, pm = cfg["box"], cfg["n_part"], cfg["pm_factor"]
+    n_g, n_steps, seed = n_part * pm, cfg["n_steps"], cfg["seeds"][0]
+    n_pk, n_bins = n_g, n_g // 2
+    prob = cola.make_problem(box, n_part, pm, cfg["z_init"], n_steps)
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    st = cola.ParticleState(prob)
+    ws = cola.Workspace(prob, n_pk=n_pk)
+    t_at = time.perf_counter()
+    cola.autotune(prob, ws, n_pk=n_pk, state=st)
+    t_at = time.perf_counter() - t_at
+    out = tuple(torch.empty((1, n_bins), dtype=torch.float64, device="cuda") for _ in range(3))
+
+    def realization():
+        cola.ic_2lpt(prob, cosmo, [seed], st, ws)
+        cola.step(prob, cosmo, st, n_steps - 1, ws)
+        cola.power_spectrum(prob, cosmo, st, 1.0, n_pk, n_bins, ws, out=out)
+
+    realization()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    realization()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    pk_plain = out[1].cpu().numpy()[0]
+    res = {"plain_512_1536": {"ms_per_realization": round(ms, 1),
+                              "particle_steps_per_s": round(n_part ** 3 * n_steps / (ms / 1e3), 1),
+                              "realizations_per_hour": round(3.6e6 / ms, 1), "autotune_s": round(t_at, 1)}}
+    del st, ws, out
+    torch.cuda.empty_cache()
+    print(f"[bench] large: plain 512^3 / 1536^3 {ms:.0f} ms per realization", file=sys.stderr, flush=True)
+    res["learned_512_512"] = learned_bench(cola, torch, "plain_512_1536", [pk_plain], (1.0,), n_pk, n_bins, ms,
+                                           reps=1)
+    res["workload"] = (f"plain_512_1536: {n_part}^3 particles, {n_g}^3 mesh (PM_grid {pm}), box {box:g} h^-1 Mpc, "
+                       f"{n_steps} nodes linear in a from z={cfg['z_init']:g}, seed {seed}, P(k) at z = 0 on "
+                       f"{n_pk}^3; learned_512_512: the same particles on the {n_part}^3 mesh with the network")
+    return res
 
 
 def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps, halo3=None):
@@ -621,6 +717,19 @@ def main():
                         "traffic": traffic, "kernel": name, "mesh": tag or n_g, "bytes_per_launch": b,
                         "ms_per_launch": round(ms / cnt, 4), "launches_per_step": cnt / args.steps,
                         "share_of_step": round(ms / ms_total, 4)}
+            # every kernel with at least 5% of the realization, against the same byte model
+            roofline["kernels"] = []
+            for (kname, ktag), (kms, kcnt) in ranked:
+                if kms / ms_total < 0.05:
+                    continue
+                kb = algorithmic_bytes(kname, ktag, n_g, n_part)
+                kach = kb / (kms / kcnt / 1e3) / 1e9 if kb else None
+                roofline["kernels"].append({
+                    "kernel": kname, "mesh": ktag or n_g, "share_of_step": round(kms / ms_total, 4),
+                    "ms_per_launch": round(kms / kcnt, 4), "bytes_per_launch": kb,
+                    "achieved": round(kach, 1) if kach else None,
+                    "frac": round(kach / HBM_PEAK_GBS, 4) if kach else None,
+                    "traffic": read_traffic(kname, ktag)})
 
     result = {
         "metric": METRIC,
@@ -662,6 +771,9 @@ def main():
         print("[bench] redshift-space multipoles on the 1024^3 analysis mesh", file=sys.stderr, flush=True)
         result["multipoles"] = multipoles_bench(cola, torch, prob, st, cfg)
         print(f"[bench] multipoles: {json.dumps(result['multipoles'])}", file=sys.stderr, flush=True)
+    if not args.no_aliasing:
+        result["aliasing"] = aliasing_bench(cola, torch, prob, cosmo, st, ws, n_pk, n_bins)
+        print(f"[bench] aliasing: {json.dumps(result['aliasing'])}", file=sys.stderr, flush=True)
     halo3 = None
     if not args.no_haloes:
         # the state holds the last timed realization at z = 0
@@ -695,6 +807,10 @@ def main():
                   flush=True)
             result["learned_ensemble"] = learned_ensemble_bench(cola, torch, 2, result["ensemble"], plain_spectra)
             print(f"[bench] learned ensemble: {json.dumps(result['learned_ensemble'])}", file=sys.stderr, flush=True)
+    if not args.no_large and args.workload == "plain_256_768":
+        print("[bench] large: 512^3 particles, plain 1536^3 mesh and learned 512^3 mesh", file=sys.stderr, flush=True)
+        result["large"] = large_bench(cola, torch)
+        print(f"[bench] large: {json.dumps(result['large'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline: float64 oracle, one step", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(cfg, seed)

@@ -147,8 +147,8 @@ int cola_step(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
  * momentum (the main run is unchanged).  CIC onto n_pk^3 cells, FFT, |delta_k|^2 / W^2 with
  * W = prod_d sinc^2(pi m_d / n_pk); bin b >= 1 holds b^2 <= |m|^2 < (b+1)^2 (integer test,
  * k = 0 excluded); P_b = (L^3 / n_pk^6) sum w |delta|^2 / W^2 / sum w, w the full-k-space
- * multiplicity of each half-spectrum mode; sums in float64.  No shot-noise or aliasing
- * correction.  Outputs (device, n_real * n_bins each, bin 0 empty): k_mean [h/Mpc], pk
+ * multiplicity of each half-spectrum mode; sums in float64.  No shot-noise subtraction; the aliasing
+ * correction is cola_power_spectrum_jing.  Outputs (device, n_real * n_bins each, bin 0 empty): k_mean [h/Mpc], pk
  * [(h^-1 Mpc)^3], n_modes.  n_pk: even, factors 2 and 3 only.  ws: cola_workspace_bytes(prob,
  * n_pk) bytes at least.  Between nodes it uses the force of node j that the workspace holds for
  * this state (from cola_step or cola_step_lc); with none cached it evaluates and caches the plain
@@ -157,6 +157,21 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo,
                         cola_particles* in, double a_out, int32_t n_pk, int32_t n_bins,
                         double* k_mean, double* pk, double* n_modes,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* cola_power_spectrum with the aliasing correction of Jing (2005) that Sec. 2.5 applies.  For a
+ * spectrum that is locally a power law P ~ k^n_eff, a mode's expected |delta_m|^2 is C(m) P(|m|),
+ *   C(m) = sum_{|j_d| <= 2} W^2(u) (|u| / |m|)^n_eff,  u = |m| + j n_pk,  W(u) = prod_d sinc^2(pi u_d / n_pk)
+ * (images about the absolute mode integers).  Starting from cola_power_spectrum's estimate, each of
+ * `iterations` passes (1..16; 4 converge on noisy spectra) takes n_eff per bin as the
+ * mode-weighted least-squares slope of ln P on ln k over the bins within a factor 1.35 in k
+ * (clamped to [-4, 4]; 0 where that window holds one bin) and rebins |delta_m|^2 / C(m).  Shot
+ * noise is corrected with the signal (a flat spectrum has n_eff = 0).  C is evaluated in float32
+ * once per class of sorted absolute mode integers.  Outputs, workspace and state rules are those of
+ * cola_power_spectrum (k_mean and n_modes are identical to it). */
+int cola_power_spectrum_jing(const cola_problem* prob, const cola_cosmology* cosmo,
+                             cola_particles* in, double a_out, int32_t n_pk, int32_t n_bins,
+                             int32_t iterations, double* k_mean, double* pk, double* n_modes,
+                             void* ws, size_t ws_bytes, void* stream);
 
 /* Redshift-space multipoles (Sec. 6: Eq. 5 mapping, Eq. 6 multipoles).  Plane-parallel: the line
  * of sight is axis `los` (0, 1, 2).  With redshift_space != 0 each particle is moved along the line

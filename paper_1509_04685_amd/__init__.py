@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import ColaError, Cosmology, Problem, Particles  # noqa: F401
 
 __all__ = ["Cosmology", "Problem", "ParticleState", "Workspace", "ic_2lpt", "pm_force", "step",
-           "power_spectrum", "cic_density", "fft_r2c", "fft_c2r", "schedule_table",
+           "power_spectrum", "power_spectrum_jing", "cic_density", "fft_r2c", "fft_c2r", "schedule_table",
            "linear_power", "workspace_bytes", "ColaError"]
 
 
@@ -154,6 +154,21 @@ def power_spectrum(prob, cosmo, state, a_out, n_pk, n_bins, ws, out=None):
                                               ctypes.byref(state.c), float(a_out), int(n_pk),
                                               int(n_bins), _ptr(km), _ptr(pk), _ptr(nm), ws.ptr,
                                               ws.nbytes, _stream()), "cola_power_spectrum")
+    return km, pk, nm
+
+
+def power_spectrum_jing(prob, cosmo, state, a_out, n_pk, n_bins, ws, iterations=4, out=None):
+    """power_spectrum with the Jing (2005) aliasing correction: (k_mean, pk, n_modes)."""
+    torch = _torch()
+    if out is None:
+        out = tuple(torch.empty((prob.n_real, n_bins), dtype=torch.float64, device=state.x.device)
+                    for _ in range(3))
+    km, pk, nm = out
+    _lib.check(_lib.lib().cola_power_spectrum_jing(ctypes.byref(prob), ctypes.byref(cosmo),
+                                                   ctypes.byref(state.c), float(a_out), int(n_pk),
+                                                   int(n_bins), int(iterations), _ptr(km), _ptr(pk),
+                                                   _ptr(nm), ws.ptr, ws.nbytes, _stream()),
+               "cola_power_spectrum_jing")
     return km, pk, nm
 
 

@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "COLA_OK", -1: "COLA_ERR_INVALID_ARG", -2: "COLA_ERR_UNSUPPOR
 
 # every exported symbol of include/cola.h
 EXPORTS = ("cola_workspace_bytes", "cola_ic_2lpt", "cola_pm_force", "cola_step",
-           "cola_power_spectrum", "cola_cic_density", "cola_cic_workspace_bytes",
+           "cola_power_spectrum", "cola_power_spectrum_jing", "cola_cic_density", "cola_cic_workspace_bytes",
            "cola_fft_workspace_bytes", "cola_fft_r2c", "cola_fft_c2r", "cola_schedule_table",
            "cola_linear_power", "cola_status_string", "cola_version", "cola_profiler_enable",
            "cola_profiler_num_kinds", "cola_profiler_kind_name", "cola_profiler_read", "cola_copy",
@@ -95,6 +95,7 @@ def _load():
         "cola_pm_force": (ctypes.c_int, [P, PP, ctypes.POINTER(vp), vp, sz, vp]),
         "cola_step": (ctypes.c_int, [P, C, i32, i32, PP, vp, sz, vp]),
         "cola_power_spectrum": (ctypes.c_int, [P, C, PP, dbl, i32, i32, vp, vp, vp, vp, sz, vp]),
+        "cola_power_spectrum_jing": (ctypes.c_int, [P, C, PP, dbl, i32, i32, i32, vp, vp, vp, vp, sz, vp]),
         "cola_cic_density": (ctypes.c_int, [ctypes.POINTER(vp), i64, i32, dbl, vp, vp, sz, vp]),
         "cola_cic_workspace_bytes": (sz, [i64, i32]),
         "cola_fft_workspace_bytes": (sz, [i32]),

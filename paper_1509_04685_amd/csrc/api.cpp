@@ -558,9 +558,13 @@ int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, i
     return set_fft_shape(n, kind, values_per_thread, width, use_static != 0);
 }
 
-int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,
-                        double a_out, int32_t n_pk, int32_t n_bins, double* k_mean, double* pk,
-                        double* n_modes, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+
+// P(k) of the state (Sec. 2.5); alias_iters > 0 adds that many iterations of the Jing (2005)
+// aliasing correction.
+int power_spectrum_impl(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in, double a_out,
+                        int32_t n_pk, int32_t n_bins, int alias_iters, double* k_mean, double* pk, double* n_modes,
+                        void* ws, size_t ws_bytes, void* stream) {
     int s;
     if ((s = check_problem(prob)) != COLA_OK) return s;
     if ((s = check_cosmo(cosmo)) != COLA_OK) return s;
@@ -628,7 +632,31 @@ int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, c
     COLA_TRY(pk_bin(w.K2, L.kstride, gk, p.n_real, n_bins, k_mean, pk, n_modes, 2.0 * M_PI / p.box, st));
     double pnorm = p.box * p.box * p.box / (cells * cells);
     COLA_TRY(pk_finish(k_mean, pk, n_modes, nb, pnorm, st));
+    if (alias_iters > 0) {
+        // the density mesh K is free once transformed: it holds the aliasing tables
+        const long sstride = 2L * L.kstride;
+        if (pk_alias_scratch_floats(n_pk, n_bins) > sstride) return COLA_ERR_WORKSPACE_TOO_SMALL;
+        for (int it = 0; it < alias_iters; ++it)
+            COLA_TRY(pk_alias_pass(w.K2, L.kstride, gk, p.n_real, n_bins, k_mean, pk, n_modes, pnorm,
+                                   2.0 * M_PI / p.box, reinterpret_cast<float*>(w.K), sstride, st));
+    }
     return COLA_OK;
+}
+
+}  // namespace
+
+int cola_power_spectrum(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,
+                        double a_out, int32_t n_pk, int32_t n_bins, double* k_mean, double* pk,
+                        double* n_modes, void* ws, size_t ws_bytes, void* stream) {
+    return power_spectrum_impl(prob, cosmo, in, a_out, n_pk, n_bins, 0, k_mean, pk, n_modes, ws, ws_bytes, stream);
+}
+
+int cola_power_spectrum_jing(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in,
+                             double a_out, int32_t n_pk, int32_t n_bins, int32_t iterations, double* k_mean,
+                             double* pk, double* n_modes, void* ws, size_t ws_bytes, void* stream) {
+    if (iterations < 1 || iterations > 16) return COLA_ERR_INVALID_ARG;
+    return power_spectrum_impl(prob, cosmo, in, a_out, n_pk, n_bins, iterations, k_mean, pk, n_modes, ws, ws_bytes,
+                               stream);
 }
 
 int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo, cola_particles* in, double a_out,

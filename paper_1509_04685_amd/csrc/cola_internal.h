@@ -29,7 +29,7 @@ enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
     PROF_Y_INV, PROF_Z_C2R, PROF_GKD, PROF_GATHER, PROF_IC, PROF_X_INV_MULT, PROF_PK, PROF_COPY,
     PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_LC_CONV, PROF_LC_WGRAD, PROF_LC_MISC,
-    PROF_FOF,
+    PROF_FOF, PROF_PK_ALIAS,
     PROF_NUM_KINDS
 };
 // Brackets one kernel launch with an event pair when the profiler is enabled.  tag: a size label
@@ -249,5 +249,14 @@ hipError_t pk_bin_multipoles(const float2* spec, long bstride, const Mesh3& g, i
 hipError_t pk_finish_multipoles(double* kmean, double* p0, double* p2, double* p4, const double* cnt, long n,
                                 double pnorm, hipStream_t st);
 hipError_t pk_finish(double* kmean, double* pk, double* cnt, long n, double pnorm, hipStream_t st);
+// Jing (2005) aliasing correction (pk_kernels.hip): floats of scratch per realization that
+// pk_alias_pass needs (the aliasing table of every mode class and the bin slopes)
+long pk_alias_scratch_floats(int n, int n_bins);
+// One iteration: slopes from the current estimate (k_mean, pk, n_modes final), the aliasing sum
+// of every mode class for its bin's slope, then pk rebinned as |delta|^2 / C and finished.
+// scratch: n_real * sstride floats, sstride >= pk_alias_scratch_floats.
+hipError_t pk_alias_pass(const float2* spec, long bstride, const Mesh3& g, int n_real, int n_bins,
+                         const double* k_mean, double* pk, const double* n_modes, double pnorm, double kf,
+                         float* scratch, long sstride, hipStream_t st);
 
 }  // namespace cola
