@@ -123,7 +123,8 @@ def node_index(table, a_out):
 
 KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h", "fft_kernels.h", "fft_static_1536.hip", "fft_static_768.hip",
                           "fft_static_512.hip", "fft_static_384.hip", "fft_static_288.hip", "fft_static_256.hip"), "cic": ("deposit_sorted.hip",),
-                  "pk_deposit": ("deposit_sorted.hip",), "gather": ("pm_kernels.hip",), "lc": ("lc_kernels.hip",)}
+                  "pk_deposit": ("deposit_sorted.hip",), "gather_kick_drift": ("deposit_sorted.hip", "pm_kernels.hip"),
+                  "gather": ("pm_kernels.hip",), "lc": ("lc_kernels.hip",), "pk_alias": ("pk_kernels.hip",)}
 
 
 def source_hash(kind):
