@@ -344,7 +344,7 @@ def abundance_error(counts, ref, min_count=20):
 
 
 def stepping_bench(cola, torch, cfg, pk_ref, halo_ref):
-    """What the 2LPT frame, the time sampling and the initial redshift buy (Sec. 4.1, 4.3, Appendix B)
+    """What the 2LPT frame, the time sampling and the initial redshift buy (Sec. 4.1-4.3, Appendix B)
     on the headline workload and seed: COLA and PM-only runs with 10, 20 and 40 nodes, 40
     logarithmic / a^0.8 nodes, 40 linear nodes from z_i = 9, 39 and 100, and 10 nodes from z_i = 9,
     each against the timed 40-node linear COLA run from z_i = 19 (P(k) at z = 0 and haloes)."""

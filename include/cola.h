@@ -71,7 +71,7 @@ typedef struct {
     double  a_final;    /* last node, normally 1                                              */
     int32_t n_steps;    /* number of time nodes n of Eq. 3, both ends included (n >= 2);
                            one force evaluation per node, n - 1 drifts                        */
-    int32_t sampling;   /* time sampling f(a) of Eq. 3, nodes equally spaced in f (Sec. 4.3):
+    int32_t sampling;   /* time sampling f(a) of Eq. 3, nodes equally spaced in f (Sec. 4.2):
                            0 = linear, f = a (the paper's choice); 1 = logarithmic, f = ln a;
                            2 = power, f = a^sampling_power                                    */
     int32_t n_real;     /* realizations in the batch, >= 1                                    */
@@ -343,8 +343,9 @@ int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const c
  * tight serving loops, harnesses that forbid hipMalloc): the same passes and the same result, with
  * the workspace taken from a fixed 64 MiB device array that the library holds on each GPU until
  * the process ends, instead of a caller buffer.  The caller still passes the state and acc.
- * Problems whose cola_workspace_bytes(prob, 0) exceeds 64 MiB (for example a 128^3 mesh with more
- * than about 96^3 particles) return COLA_ERR_WORKSPACE_TOO_SMALL before any launch.  Every call on
+ * Problems whose cola_workspace_bytes(prob, 0) exceeds 64 MiB (for example 128^3 particles on a
+ * 128^3 mesh; 64^3 particles on a 128^3 mesh need 49 MiB) return COLA_ERR_WORKSPACE_TOO_SMALL before
+ * any launch.  Every call on
  * one GPU shares that GPU's array: calls that overlap on one GPU (other streams, other threads)
  * race, and a state's cached force is never kept in it.  No hipMalloc, hipFree or other
  * allocating call is made. */

@@ -122,7 +122,7 @@ def test_host_linear_power_matches_oracle():
 
 
 def test_host_schedule_samplings_match_oracle():
-    """Eq. 3 with f = ln a and f = a^p (Sec. 4.3: 0.5 and 0.8), 40 nodes from z_i = 39."""
+    """Eq. 3 with f = ln a and f = a^p (Sec. 4.2: 0.5 and 0.8), 40 nodes from z_i = 39."""
     for sampling, power in (("log", None), ("power", 0.5), ("power", 0.8)):
         p = cola.make_problem(256.0, 32, 3, 39.0, 40, sampling=sampling, sampling_power=power or 1.0)
         tab = cola.schedule_table(p, COSMO)

@@ -1,4 +1,4 @@
-"""Pins of the time samplings of Eq. 3 (Sec. 4.3, Fig. 4): nodes equally spaced in f(a) for
+"""Pins of the time samplings of Eq. 3 (Sec. 4.2, Fig. 4): nodes equally spaced in f(a) for
 f = a, ln a, a^0.5 and a^0.8, 40 nodes from z_i = 39 to a = 1.
 
   * linear: constant step density rho = 1 / da = (n - 1) / (1 - a_i), which is 40 for these nodes;
