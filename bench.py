@@ -478,8 +478,9 @@ def large_bench(cola, torch):
     st = cola.ParticleState(prob)
     ws = cola.Workspace(prob, n_pk=n_pk)
     t_at = time.perf_counter()
-    cola.autotune(prob, ws, n_pk=n_pk, state=st)
+    report = cola.autotune(prob, ws, n_pk=n_pk, state=st)
     t_at = time.perf_counter() - t_at
+    print(f"[bench] large: FFT autotune ({t_at:.1f} s):\n" + report.rstrip(), file=sys.stderr, flush=True)
     out = tuple(torch.empty((1, n_bins), dtype=torch.float64, device="cuda") for _ in range(3))
 
     def realization():

@@ -316,8 +316,10 @@ int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_by
  * autotuner would: kind one of "z_r2c", "z_c2r", "rows_y", "cols_x", "x_green", "y_split",
  * "x_mult"; values_per_thread and width (lines per block for the z passes and the y rows, a power
  * of two dividing n for the z passes; columns per tile for the x passes) must form an admissible
- * shape; use_static selects the compile-time plan of that
- * shape (COLA_ERR_INVALID_ARG if the library has none).  Host only: nothing is launched. */
+ * shape; use_static: 0 the plan built at run time, 1 the compile-time plan of that shape, 2 (x-column
+ * kinds) the compile-time plan whose LDS exchanges move the real and then the imaginary parts
+ * through half the LDS (COLA_ERR_INVALID_ARG if the library has no such plan).  Host only: nothing
+ * is launched. */
 int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, int32_t width, int32_t use_static);
 
 /* cola_step with the network's correction: at each force evaluation the density contrast and the

@@ -530,10 +530,12 @@ def mesh_force(delta, box, ws=None, g=None):
     return g
 
 
-def fft_set_shape(n, kind, values_per_thread, width, use_static=True):
-    """Pin one FFT pass kind's kernel shape at mesh side n (see cola_fft_set_shape)."""
-    _lib.check(_lib.lib().cola_fft_set_shape(int(n), kind.encode(), int(values_per_thread), int(width),
-                                             1 if use_static else 0), "cola_fft_set_shape")
+def fft_set_shape(n, kind, values_per_thread, width, use_static=True, split=False):
+    """Pin one FFT pass kind's kernel shape at mesh side n (see cola_fft_set_shape); split: the
+    compile-time plan with real/imaginary LDS exchanges (x-column kinds)."""
+    mode = 2 if split else (1 if use_static else 0)
+    _lib.check(_lib.lib().cola_fft_set_shape(int(n), kind.encode(), int(values_per_thread), int(width), mode),
+               "cola_fft_set_shape")
 
 
 def pm_fields(pos, n_mesh, box, delta=True, g=True, acc=True, ws=None):

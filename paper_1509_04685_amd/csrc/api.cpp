@@ -555,7 +555,7 @@ int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const c
 }
 
 int cola_fft_set_shape(int32_t n, const char* kind, int32_t values_per_thread, int32_t width, int32_t use_static) {
-    return set_fft_shape(n, kind, values_per_thread, width, use_static != 0);
+    return set_fft_shape(n, kind, values_per_thread, width, use_static);
 }
 
 namespace {

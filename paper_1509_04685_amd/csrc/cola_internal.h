@@ -97,7 +97,7 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
 
 // Pins the kernel shape of one pass kind ("z_r2c", "z_c2r", "cols_y", "cols_x", "x_green",
 // "y_split", "x_mult") at mesh size n for the rest of the process; a cola_status.
-int set_fft_shape(int n, const char* kind, int R, int width, bool stat);
+int set_fft_shape(int n, const char* kind, int R, int width, int stat);
 
 // ------------------------------------------------------------------ launchers (fft.hip)
 hipError_t launch_twiddles(float2* tw, int len, hipStream_t st);

@@ -121,11 +121,13 @@ static hipError_t dispatch_r(int R, F&& f) {
 // ------------------------------------------------------------------ kernel shapes and autotuning
 
 // Shape of one FFT kernel launch: R values per thread, `width` lines per block (z passes, y rows)
-// or columns per tile (x columns), and whether the compile-time plan of that shape is used.
+// or columns per tile (x columns), whether the compile-time plan of that shape is used, and (x
+// columns, static plans only) whether its exchanges are split into real and imaginary parts.
 struct FftShape {
     int R = 0;
     int width = 0;
     bool stat = false;
+    bool split = false;
 };
 
 enum FftKind { FK_Z_R2C = 0, FK_Z_C2R, FK_ROWS_Y, FK_COLS_X, FK_X_GREEN, FK_Y_SPLIT, FK_X_MULT, FK_NUM };
@@ -197,19 +199,24 @@ static hipError_t launch_static(const FftLaunch& L, int n) {
     }
 }
 
-static bool static_available(FftKind k, int n, int R, int width) {
+static bool is_cols(FftKind k) { return k == FK_COLS_X || k == FK_X_GREEN || k == FK_X_MULT; }
+
+static bool static_available(FftKind k, int n, int R, int width, bool split = false) {
+    if (split && !is_cols(k)) return false;
     FftLaunch L;
     L.op = op_of(k);
     L.n = line_len(k, n);
     L.R = R;
     L.width = width;
+    L.split = split;
     L.probe = true;
     return launch_static(L, n) == hipSuccess;
 }
 
 static size_t shape_lds(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
-    return is_z(k) ? (size_t)sh.width * (L + 1) * sizeof(float2) : (size_t)sh.width * L * sizeof(float2);
+    if (is_z(k)) return (size_t)sh.width * (L + 1) * sizeof(float2);
+    return (size_t)sh.width * L * (sh.split ? sizeof(float) : sizeof(float2));
 }
 
 static int log2_exact(int w) {  // log2 of a power of two, -1 otherwise
@@ -221,6 +228,7 @@ static int log2_exact(int w) {  // log2 of a power of two, -1 otherwise
 static bool shape_ok(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
     if (!plan_ok(L, sh.R) || sh.width < 1) return false;
+    if (sh.split && (!sh.stat || !is_cols(k))) return false;
     // z passes: a power-of-two number of lines of one x plane per block
     if (is_z(k) && (log2_exact(sh.width) < 0 || n % sh.width)) return false;
     long threads = (long)sh.width * (L / sh.R);
@@ -268,15 +276,16 @@ static FftShape shape_for(FftKind k, int n) {
 }
 
 // Pins the shape of one pass kind at mesh size n (what the autotuner would otherwise choose).
-int set_fft_shape(int n, const char* kind, int R, int width, bool stat) {
+int set_fft_shape(int n, const char* kind, int R, int width, int stat) {
     if (!kind || !fft_size_ok(n)) return COLA_ERR_INVALID_ARG;
     int k = -1;
     for (int i = 0; i < FK_NUM; ++i)
         if (std::string(kind) == kFftKindName[i]) k = i;
     if (k < 0) return COLA_ERR_INVALID_ARG;
-    const FftShape sh{R, width, stat};
+    if (stat < 0 || stat > 2) return COLA_ERR_INVALID_ARG;
+    const FftShape sh{R, width, stat != 0, stat == 2};
     if (!shape_ok((FftKind)k, n, sh)) return COLA_ERR_INVALID_ARG;
-    if (stat && !static_available((FftKind)k, n, R, width)) return COLA_ERR_INVALID_ARG;
+    if (sh.stat && !static_available((FftKind)k, n, R, width, sh.split)) return COLA_ERR_INVALID_ARG;
     ShapeCache& c = shape_cache();
     std::lock_guard<std::mutex> g(c.mu);
     c.tuned[{k, n}] = sh;
@@ -301,9 +310,11 @@ static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
     L.n = z ? mesh_n / 2 : mesh_n;
     L.R = sh.R;
     L.width = sh.width;
+    L.split = sh.split;
     if (sh.stat) {
         hipError_t e = launch_static(L, mesh_n);
-        if (e != hipErrorNotSupported) return e;
+        // a split exchange exists only in static plans (its LDS size is half the dynamic kernel's)
+        if (e != hipErrorNotSupported || sh.split) return e;
     }
     FftPlan pl = make_plan_r(L.n, sh.R, false);
     if (z) finish_plan(pl, 2);
@@ -338,7 +349,7 @@ static hipError_t run_rows_shape(FftOp op, float2* A, float2* S, long bstride, c
     FftLaunch L;
     L.op = op;
     L.nrows = (long)(g.m + 1) * g.n;
-    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.lds = shape_lds(FK_ROWS_Y, g.n, sh);
     L.grid = dim3((unsigned)((L.nrows + sh.width - 1) / sh.width), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
@@ -364,7 +375,7 @@ static hipError_t run_cols_shape(float2* data, long bstride, const Mesh3& g, con
     FftLaunch L;
     L.op = OP_COLS_FWD;
     L.cg = cols_x(g, sh.width);
-    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.lds = shape_lds(FK_COLS_X, g.n, sh);
     L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
@@ -446,7 +457,7 @@ static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstrid
     FftLaunch L;
     L.op = OP_X_GREEN;
     L.cg = cols_x(g, sh.width);
-    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.lds = shape_lds(FK_X_GREEN, g.n, sh);
     L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
@@ -467,7 +478,7 @@ static hipError_t run_x_mult_shape(const float2* spec, long spec_bstride, float2
     FftLaunch L;
     L.op = OP_X_MULT;
     L.cg = cols_x(g, sh.width);
-    L.lds = (size_t)sh.width * g.n * sizeof(float2);
+    L.lds = shape_lds(FK_X_MULT, g.n, sh);
     L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
     L.block = dim3(sh.width * (g.n / sh.R));
     L.st = st;
@@ -551,6 +562,7 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
                 if (threads < 64 && w < 64) continue;
                 cands.push_back(sh);
                 if (static_available(kind, n, R, w)) cands.push_back(FftShape{R, w, true});
+                if (static_available(kind, n, R, w, true)) cands.push_back(FftShape{R, w, true, true});
             }
         if (cands.empty()) continue;
         auto launch = [&](const FftShape& sh) -> hipError_t {
@@ -598,7 +610,8 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
         if (report) {
             char line[160];
             std::snprintf(line, sizeof(line), "n=%d %s: R=%d width=%d %s %.3f ms (%zu shapes)\n", n,
-                          kFftKindName[k], best_sh.R, best_sh.width, best_sh.stat ? "static" : "dynamic", best,
+                          kFftKindName[k], best_sh.R, best_sh.width,
+                          best_sh.split ? "static-split" : (best_sh.stat ? "static" : "dynamic"), best,
                           cands.size());
             *report += line;
         }

@@ -289,6 +289,7 @@ template <int R>
 struct DynLine {
     static constexpr int kR = R;
     static constexpr bool kStatic = false;
+    static constexpr bool kSplit = false;
     static constexpr int kN = 0;
     static constexpr int kTwN = 0;  // reads the table in global memory
     FftPlan p;
@@ -369,13 +370,17 @@ constexpr bool static_plan_ok(int n, int R) {
     return prod == n;
 }
 
-// N: line length; R: values per thread; LES: LDS element stride (float2); TWS: twiddle table
-// stride (the table holds exp(-2 pi i m / (N TWS))); REV: reversed radix order.
-template <int N, int R, int LES, int TWS, bool REV>
+// N: line length; R: values per thread; LES: LDS element stride (float2, or float with SPL);
+// TWS: twiddle table stride (the table holds exp(-2 pi i m / (N TWS))); REV: reversed radix order;
+// SPL: exchange the real and then the imaginary parts through a float buffer of N LES floats
+// (half the LDS of a float2 exchange, two more barriers per stage), which lets wide column tiles
+// keep more blocks resident.
+template <int N, int R, int LES, int TWS, bool REV, bool SPL = false>
 struct StatLine {
     static_assert(static_plan_ok(N, R), "no static plan for this line length and R");
     static constexpr int kR = R;
     static constexpr bool kStatic = true;
+    static constexpr bool kSplit = SPL;
     static constexpr int kN = N;
     static constexpr int kT = N / R;
     static constexpr Radices kRad = static_radices(N, R, REV);
@@ -424,21 +429,34 @@ struct StatLine {
             }
             if constexpr (ST + 1 < kRad.nst) {
                 constexpr int rn = kRad.r[ST + 1];
-                if (active) {
+                if constexpr (SPL) {
+                    // the real parts go out and come back in place before the imaginary parts
+                    // leave, so no temporaries are held
+                    float* lf = reinterpret_cast<float*>(lds);
+                    if (active) write_part<r, ns, 0>(v, lf, t);
+                    __syncthreads();
+                    if (active) read_part<rn, 0>(v, lf, t);
+                    __syncthreads();
+                    if (active) write_part<r, ns, 1>(v, lf, t);
+                    __syncthreads();
+                    if (active) read_part<rn, 1>(v, lf, t);
+                } else {
+                    if (active) {
 #pragma unroll
-                    for (int s = 0; s < R / r; ++s) {
-                        const int j = t + s * kT;
-                        const int base = (j / ns) * ns * (r - 1) + j;  // (j/ns) ns r + j%ns
+                        for (int s = 0; s < R / r; ++s) {
+                            const int j = t + s * kT;
+                            const int base = (j / ns) * ns * (r - 1) + j;  // (j/ns) ns r + j%ns
 #pragma unroll
-                        for (int i = 0; i < r; ++i) lds[(base + i * ns) * LES] = v[s * r + i];
+                            for (int i = 0; i < r; ++i) lds[(base + i * ns) * LES] = v[s * r + i];
+                        }
                     }
-                }
-                __syncthreads();
-                if (active) {
+                    __syncthreads();
+                    if (active) {
 #pragma unroll
-                    for (int s = 0; s < R / rn; ++s)
+                        for (int s = 0; s < R / rn; ++s)
 #pragma unroll
-                        for (int i = 0; i < rn; ++i) v[s * rn + i] = lds[(t + s * kT + i * (N / rn)) * LES];
+                            for (int i = 0; i < rn; ++i) v[s * rn + i] = lds[(t + s * kT + i * (N / rn)) * LES];
+                    }
                 }
                 __syncthreads();
                 stage<INV, ST + 1>(v, lds, t, tw, active);
@@ -448,6 +466,30 @@ struct StatLine {
     template <bool INV>
     __device__ __forceinline__ void run(float2 (&v)[R], float2* lds, int t, const float2* tw, bool active) const {
         stage<INV, 0>(v, lds, t, tw, active);
+    }
+
+    // Split exchange: one component (P = 0: real, 1: imaginary) of the stage's output written in
+    // the order the next stage reads, and read back.
+    template <int r, int ns, int P>
+    __device__ __forceinline__ static void write_part(const float2 (&v)[R], float* lf, int t) {
+#pragma unroll
+        for (int s = 0; s < R / r; ++s) {
+            const int j = t + s * kT;
+            const int base = (j / ns) * ns * (r - 1) + j;
+#pragma unroll
+            for (int i = 0; i < r; ++i) lf[(base + i * ns) * LES] = P == 0 ? v[s * r + i].x : v[s * r + i].y;
+        }
+    }
+    template <int rn, int P>
+    __device__ __forceinline__ static void read_part(float2 (&v)[R], const float* lf, int t) {
+#pragma unroll
+        for (int s = 0; s < R / rn; ++s)
+#pragma unroll
+            for (int i = 0; i < rn; ++i) {
+                const float x = lf[(t + s * kT + i * (N / rn)) * LES];
+                if constexpr (P == 0) v[s * rn + i].x = x;
+                else v[s * rn + i].y = x;
+            }
     }
 };
 

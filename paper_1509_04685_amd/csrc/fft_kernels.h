@@ -54,6 +54,14 @@ __device__ __forceinline__ bool col_setup(const ColGeom& cg, int& t, uint32_t& b
 
 __device__ __forceinline__ int signed_mode(int e, int n) { return e < n / 2 ? e : e - n; }
 
+// A column kernel's exchange base in LDS after TW staged twiddles: column ct of the tile at
+// element ct (float2, or float when the engine splits its exchanges into real and imaginary parts).
+template <class LE>
+__device__ __forceinline__ float2* col_lds(float2* lds, int tw_entries, int ct) {
+    if constexpr (LE::kSplit) return reinterpret_cast<float2*>(reinterpret_cast<float*>(lds + tw_entries) + ct);
+    else return lds + tw_entries + ct;
+}
+
 // ------------------------------------------------------------------ twiddles in LDS
 
 // Table entries a kernel stages at the front of its LDS (0: it reads the global table).  The z
@@ -294,7 +302,7 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, Co
     if (active) eng.first(t, [&](int q, int e) { v[q] = load_col<TK>(data + base + (uint32_t)e * es); });
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
-    eng.template run<false>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
+    eng.template run<false>(v, col_lds<LE>(lds, TW, threadIdx.x % (TK > 0 ? TK : cg.tk)), t, twl, active);
     if (!active) return;
     eng.last(t, [&](int q, int e) { store_col<TK>(data + base + (uint32_t)e * es, v[q]); });
 }
@@ -320,7 +328,7 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
     const uint32_t es = (uint32_t)cg.es;
     const int n = ef.n();
     const int my = signed_mode(c, n), mz = plane;
-    float2* L = lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk);
+    float2* L = col_lds<LF>(lds, TW, threadIdx.x % (TK > 0 ? TK : cg.tk));
     float2 v[R], h[R];
     if (active) ef.first(t, [&](int q, int e) { v[q] = load_col<TK>(S + base + (uint32_t)e * es); });
     const float2* twl = stage_twiddles<TW>(tw, lds);
@@ -387,7 +395,7 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
     }
     const float2* twl = stage_twiddles<TW>(tw, lds);
     if constexpr (TW > 0) __syncthreads();
-    eng.template run<true>(v, lds + TW + threadIdx.x % (TK > 0 ? TK : cg.tk), t, twl, active);
+    eng.template run<true>(v, col_lds<LE>(lds, TW, threadIdx.x % (TK > 0 ? TK : cg.tk)), t, twl, active);
     if (!active) return;
     eng.last(t, [&](int q, int e) { store_col<TK>(W + base + (uint32_t)e * es, v[q]); });
 }
@@ -408,6 +416,7 @@ struct FftLaunch {
     int n = 0;      // line length of the kernel's transform (n/2 for the z passes)
     int R = 0;      // values per thread
     int width = 0;  // lines per block (z, rows) or columns per tile (x)
+    bool split = false;  // x columns: exchanges split into real and imaginary parts (static plans)
     bool probe = false;  // static launchers: only report whether the shape exists
     dim3 grid, block;
     size_t lds = 0;
@@ -500,10 +509,10 @@ inline hipError_t go_x_mult(const FftLaunch& L, LE e) {
 
 // Static-plan launchers: x columns of line length N with R values per thread and TK columns per
 // tile, y rows of length N, z passes of line length M.
-template <int N, int R, int TK>
+template <int N, int R, int TK, bool SPL = false>
 inline hipError_t static_cols_ops(const FftLaunch& L) {
-    using F = StatLine<N, R, TK, 1, false>;
-    using I = StatLine<N, R, TK, 1, true>;
+    using F = StatLine<N, R, TK, 1, false, SPL>;
+    using I = StatLine<N, R, TK, 1, true, SPL>;
     if (L.probe) return hipSuccess;
     switch (L.op) {
         case OP_COLS_FWD: return go_cols<F, TK>(L, F{});

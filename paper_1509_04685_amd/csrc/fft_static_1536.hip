@@ -19,6 +19,10 @@ hipError_t fft_static_1536(const FftLaunch& L) {
         if (L.R == 12) return static_rows_ops<1536, 12>(L);
         return hipErrorNotSupported;
     }
+    if (L.split) {
+        if (L.R == 24 && L.width == 8) return static_cols_ops<1536, 24, 8, true>(L);
+        return hipErrorNotSupported;
+    }
     if (L.R == 24 && L.width == 8) return static_cols_ops<1536, 24, 8>(L);
     if (L.R == 24 && L.width == 4) return static_cols_ops<1536, 24, 4>(L);
     if (L.R == 12 && L.width == 4) return static_cols_ops<1536, 12, 4>(L);

@@ -19,6 +19,7 @@ hipError_t fft_static_256(const FftLaunch& L) {
         if (L.R == 8) return static_rows_ops<256, 8>(L);
         return hipErrorNotSupported;
     }
+    if (L.split) return hipErrorNotSupported;
     if (L.R == 16 && L.width == 8) return static_cols_ops<256, 16, 8>(L);
     if (L.R == 16 && L.width == 16) return static_cols_ops<256, 16, 16>(L);
     if (L.R == 8 && L.width == 8) return static_cols_ops<256, 8, 8>(L);

@@ -19,6 +19,7 @@ hipError_t fft_static_288(const FftLaunch& L) {
         if (L.R == 12) return static_rows_ops<288, 12>(L);
         return hipErrorNotSupported;
     }
+    if (L.split) return hipErrorNotSupported;
     if (L.R == 24 && L.width == 8) return static_cols_ops<288, 24, 8>(L);
     if (L.R == 24 && L.width == 16) return static_cols_ops<288, 24, 16>(L);
     if (L.R == 12 && L.width == 8) return static_cols_ops<288, 12, 8>(L);

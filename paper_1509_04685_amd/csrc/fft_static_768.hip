@@ -19,6 +19,11 @@ hipError_t fft_static_768(const FftLaunch& L) {
         if (L.R == 12) return static_rows_ops<768, 12>(L);
         return hipErrorNotSupported;
     }
+    if (L.split) {
+        if (L.R == 24 && L.width == 16) return static_cols_ops<768, 24, 16, true>(L);
+        if (L.R == 24 && L.width == 8) return static_cols_ops<768, 24, 8, true>(L);
+        return hipErrorNotSupported;
+    }
     if (L.R == 24 && L.width == 8) return static_cols_ops<768, 24, 8>(L);
     if (L.R == 24 && L.width == 16) return static_cols_ops<768, 24, 16>(L);
     if (L.R == 12 && L.width == 8) return static_cols_ops<768, 12, 8>(L);

@@ -228,3 +228,16 @@ def test_nonfinite_arguments_return_nonfinite():
     assert LIB.cola_step_lc(ctypes.byref(p1), ctypes.byref(COSMO), 0, 1, ctypes.byref(st), ctypes.byref(net), fake,
                             1 << 40, fake, 1 << 40, None) == -6
     assert LIB.cola_status_string(-6)
+
+
+def test_fft_set_shape_split_plans_host_checks():
+    """Split-exchange plans are offered for the x-column kinds where compiled, nowhere else (host
+    only: nothing is launched)."""
+    f = LIB.cola_fft_set_shape
+    assert f(768, b"x_green", 24, 16, 2) == 0
+    assert f(1536, b"x_green", 24, 8, 2) == 0
+    assert f(768, b"rows_y", 24, 8, 2) == -1
+    assert f(512, b"x_green", 16, 8, 2) == -1
+    assert f(768, b"x_green", 24, 16, 3) == -1
+    assert f(768, b"x_green", 24, 8, 1) == 0  # restore a plain static plan
+    assert f(768, b"x_green", 24, 16, 1) == 0
