@@ -264,6 +264,80 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
     }
 }
 
+// The first layer of a density-only network (the force channels' input scales are zero): the
+// only input channel is the BF16 density d0 [V], so K = 27 taps (padded to 32) instead of 27 taps
+// x 8 channels -- one MFMA K step per output block instead of seven, six of which would multiply
+// zeros.  Lane (m, kb) takes taps 8 kb .. 8 kb + 7 of voxel m's row; the weights are channel 0 of
+// the packed [16 NB][27][8] layer-1 weights, staged as [16 NB][32] (taps 27..31 zero).  Tiles,
+// halo and epilogue (A1 = silu(Z1)) as in k_conv3_mfma.
+template <int NB>
+__global__ void __launch_bounds__(256, 3) k_conv3_dens(const uint16_t* __restrict__ d0, const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias, uint16_t* out, int n, int tiles) {
+    constexpr int COP = 16 * NB;
+    extern __shared__ uint4 smem[];
+    uint4* sw = smem;                                          // [COP][32] BF16: COP * 4 vectors
+    uint16_t* sh = reinterpret_cast<uint16_t*>(smem + COP * 4);  // halo densities, HVOX BF16
+    uint16_t* swh = reinterpret_cast<uint16_t*>(sw);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < COP * 32; i += 256) {
+        const int co = i >> 5, tap = i & 31;
+        swh[i] = tap < 27 ? w[(co * 27 + tap) * 8] : (uint16_t)0;
+    }
+    const int nty = n / TY, ntz = n / TZ;
+    const int m = lane & 15, kb = lane >> 4;
+    // halo offsets of this lane's eight taps relative to the voxel's own halo position (negative
+    // for the lower neighbours); taps 27..31 are padding and read nothing
+    int toff[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int tap = kb * 8 + j;
+        const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
+        toff[j] = (dx * HY + dy) * HZ + dz;
+    }
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        __syncthreads();  // the previous tile's readers are done with the halo (and the weights are staged)
+        for (int hv = tid; hv < HVOX; hv += 256) {
+            const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
+            const int gx = wrap_halo(x0 + hx - 1, n), gy = wrap_halo(y0 + hy - 1, n), gz = wrap_halo(z0 + hz - 1, n);
+            sh[hv] = d0[((long)gx * n + gy) * n + gz];
+        }
+        __syncthreads();
+        Frag8 bf[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bf[b].u = sw[(b * 16 + m) * 4 + kb];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int hv0 = ((wave + 1) * HY + (r + 1)) * HZ + (m + 1);
+            Frag8 af;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) af.h[j] = kb * 8 + j < 27 ? sh[hv0 + toff[j]] : (uint16_t)0;
+            const long vrow = ((long)(x0 + wave) * n + (y0 + r)) * n + z0 + 4 * kb;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, bf[b].v, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                          0, 0, 0);
+                const int co = b * 16 + m;
+                const float bb = bias[co];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) out[(vrow + q) * COP + co] = (uint16_t)f2bf(silu_f(acc[q] + bb));
+            }
+        }
+    }
+}
+
+template <int NB>
+static hipError_t run_conv_dens(const uint16_t* d0, const uint16_t* w, const float* bias, uint16_t* out, int n,
+                                hipStream_t st) {
+    const long tiles = (long)(n / TX) * (n / TY) * (n / TZ);
+    const size_t lds = (size_t)16 * NB * 32 * 2 + (size_t)HVOX * 2;
+    ProfScope ps(PROF_LC_CONV, st);
+    hipLaunchKernelGGL(k_conv3_dens<NB>, dim3((unsigned)std::min<long>(tiles, 4096)), dim3(256), lds, st, d0, w, bias,
+                       out, n, (int)tiles);
+    return hipGetLastError();
+}
+
 static long conv_tiles(int n) { return (long)(n / TX) * (n / TY) * (n / TZ); }
 
 template <int CINP, int NB, int EPI, bool FIELDS = false>
@@ -857,7 +931,9 @@ static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16
                                    hipStream_t st) {
     constexpr int NB = C / 16;
     FieldSrc fs{d0, {g[0], g[1], g[2]}, row, {in_scale[1], in_scale[2], in_scale[3]}};
-    hipError_t e = run_conv<8, NB, EPI_A, true>(nullptr, P.wb1, P.b1, a1, nullptr, nullptr, n, st, fs);
+    const bool dens_only = in_scale[1] == 0.0f && in_scale[2] == 0.0f && in_scale[3] == 0.0f;
+    hipError_t e = dens_only ? run_conv_dens<NB>(d0, P.wb1, P.b1, a1, n, st)
+                             : run_conv<8, NB, EPI_A, true>(nullptr, P.wb1, P.b1, a1, nullptr, nullptr, n, st, fs);
     if (e != hipSuccess) return e;
     if (band != 0.0f) {  // dF stored in t, then added to the force meshes through the band-pass weight
         const long V = (long)n * n * n;
