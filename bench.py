@@ -512,7 +512,8 @@ def large_bench(cola, torch):
     return res
 
 
-def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps, halo3=None):
+def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_plain3, reps, halo3=None,
+                  holdout_seeds=()):
     """The learned-correction form: 256^3 particles on the 256^3 (PM_grid = 1) mesh with the trained
     network, against the plain 3x realization timed above (same seed, same outputs) and the plain
     1x run without the network."""
@@ -587,6 +588,19 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
         res["plain_3x"]["halo_counts"] = [int(v) for v in halo3["counts"]]
         res["halo_bins_log10_mass"] = [round(float(v), 3) for v in halo3["log10_edges"]]
     res["speedup_vs_plain_3x"] = round(ms_plain3 / res["learned_1x"]["ms_per_realization"], 3)
+    if holdout_seeds:
+        # seeds never used for training, calibration or any choice of the method
+        prob3 = cola.make_problem(c["box"], c["n_part"], 3, c["z_init"], c["n_steps"])
+        worst = {}
+        for s in holdout_seeds:
+            ref = L.run_spectra(prob3, cosmo, s, sorted(a_outs), n_pk, n_bins)
+            got = L.run_spectra(prob, cosmo, s, sorted(a_outs), n_pk, n_bins, net=net)
+            worst[str(s)] = round(max(L.max_error(k, pl, p3) for (k, p3), (_, pl) in zip(ref, got)), 4)
+        vals = sorted(worst.values())
+        res["holdout"] = {"seeds": list(holdout_seeds), "max_pk_error_k_lt_1": worst,
+                          "worst": vals[-1], "median": vals[len(vals) // 2],
+                          "seeds_within_1pct": sum(v <= 0.01 for v in vals),
+                          "what": "per seed: max over 0<k<1 h/Mpc and over the outputs of |P_learned1x / P_plain3x - 1|"}
     rec = doc.get("recipe", {})
     seeds = rec.get("calib_seeds", (3001, 3002))
     inputs = "density and force" if rec.get("force_input", True) else "density only"
@@ -598,6 +612,10 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
                       f"{net.out_scale_slope:+.2f} in (1 - a)"
                       + (f", schedule {[round(v, 3) for v in net.schedule[1]]} at a = {[round(v, 3) for v in net.schedule[0]]}"
                          if net.schedule else "")
+                      + (f"; Green's-function transfer T(|k|/k_N, a): cubic in |k|/k_N on {len(net.green_filter[0])} "
+                         f"knots, rows at the schedule's knots, calibrated with the schedule at trajectory level on "
+                         f"training seeds {doc['green_filter']['passes'][0]['seeds']} "
+                         f"({doc['green_filter']['passes'][0]['n_part']}^3 particles)" if net.green_filter else "")
                       + f"; evaluation seed {c['seeds'][0]} held out")
     res["workload"] = (f"{lname}: {c['n_part']}^3 particles, {c['n_part']}^3 mesh (PM_grid 1), box {c['box']:g}, "
                        f"40 nodes from z=19, seed {c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = "
@@ -795,7 +813,7 @@ def main():
     if not args.no_learned:
         print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
         result["learned"] = learned_bench(cola, torch, args.workload, [o[1].cpu().numpy()[0] for o in outs], a_outs, n_pk,
-                                          n_bins, ms_per_step, reps=2, halo3=halo3)
+                                          n_bins, ms_per_step, reps=2, halo3=halo3, holdout_seeds=(31, 32, 33, 34, 35))
         print(f"[bench] learned: {json.dumps(result['learned'])}", file=sys.stderr, flush=True)
     if not args.no_ensemble:
         del st, ws, outs

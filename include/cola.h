@@ -217,6 +217,17 @@ typedef struct {
                             a calibration set the correction's strength per epoch              */
     float knot_a[8];
     float knot_v[8];
+    int32_t n_gknots;    /* 0, or 2..10: the corrected force of cola_step_lc and cola_pm_force_lc
+                            computes its mesh force with the Green's function times a radial
+                            transfer T(u, a), u = |k| / k_N (k_N = pi n / L, the mesh's Nyquist
+                            wavenumber): in u the cubic Hermite interpolant of (gknot_u[j],
+                            gknot_t[i][j]) with slope 0 at the first knot, centred-difference
+                            slopes inside and the one-sided slope at the last knot (gknot_u
+                            increasing; constant beyond the end knots); in a piecewise linear
+                            over the schedule's knot_a (row i; row 0 alone when n_knots = 0).
+                            The network's dF is added unfiltered.  0: T = 1                      */
+    float gknot_u[10];
+    float gknot_t[8][10];
     float* params;       /* device, cola_lc_param_count(C) floats, flat in the order
                             w1 (C,4,27) b1 (C) w2 (C,C,27) b2 (C) w3 (3,C) b3 (3), C order       */
     float* grads;        /* device, same size: cola_lc_backward adds into it, cola_lc_adam

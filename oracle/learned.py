@@ -24,11 +24,19 @@ particle-level relative residual against the fine-mesh force on the same positio
   L = sum_p |g1_p + G[dF]_p - g3_p|^2 / sum_p |g3_p - g1_p|^2,
 
 G the CIC gather (L = 1 without the network).
+
+Optional radial transfer of the Green's function (calibrated at trajectory level, not trained):
+the mesh force becomes g_k = i k T(u) delta_k / k^2, u = |m| / (n/2) for the signed mode integers
+m (|k| over the mesh's Nyquist wavenumber), T the cubic Hermite interpolant of knots (u_j, t_j)
+with slope 0 at the first knot, centred-difference slopes inside and the one-sided slope at the
+last knot, constant beyond the end knots; the network's input g is that filtered force and dF is
+added unfiltered.
 """
 
 import numpy as np
+from scipy import fft as sfft
 
-from . import pm
+from . import lpt, pm
 
 TAPS = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)]
 
@@ -162,10 +170,39 @@ def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def corrected_accel(net, pos, n_mesh, box):
-    """Mesh force plus the network's correction, interpolated to the particles (3, N)."""
+def hermite_transfer(u, u_knots, t_knots):
+    """The transfer at u (any array): cubic Hermite on the knots, slope 0 at the first knot,
+    (t_{j+1} - t_{j-1}) / (u_{j+1} - u_{j-1}) inside, one-sided at the last knot; t_0 below the
+    first knot and t_last beyond the last (scipy's CubicHermiteSpline for the pieces)."""
+    from scipy.interpolate import CubicHermiteSpline
+    uk = np.asarray(u_knots, np.float64)
+    tk = np.asarray(t_knots, np.float64)
+    m = np.zeros_like(tk)
+    m[1:-1] = (tk[2:] - tk[:-2]) / (uk[2:] - uk[:-2])
+    m[-1] = (tk[-1] - tk[-2]) / (uk[-1] - uk[-2])
+    u = np.asarray(u, np.float64)
+    out = CubicHermiteSpline(uk, tk, m)(np.clip(u, uk[0], uk[-1]))
+    return np.where(u <= uk[0], tk[0], np.where(u >= uk[-1], tk[-1], out))
+
+
+def green_transfer(n, u_knots, t_knots):
+    """T(u) on the rfftn grid of an n^3 mesh, u = |m| / (n/2) (hermite_transfer)."""
+    mx, my, mz = lpt.mode_integers(n)
+    u = np.sqrt((mx ** 2 + my ** 2 + mz ** 2).astype(np.float64)) / (n / 2.0)
+    return hermite_transfer(u, u_knots, t_knots)
+
+
+def corrected_accel(net, pos, n_mesh, box, transfer=None):
+    """Mesh force plus the network's correction, interpolated to the particles (3, N).  transfer:
+    (u_knots, t_knots) of the Green's function's radial transfer, or None for T = 1.  The transfer
+    multiplies delta_k before the plain force operator (pm.force_mesh), which is the same as
+    multiplying its Green's function."""
     delta = pm.density_contrast(pos, n_mesh, box)
-    g = pm.force_mesh(delta, box)
+    if transfer is None:
+        g = pm.force_mesh(delta, box)
+    else:
+        dk = sfft.rfftn(delta) * green_transfer(n_mesh, *transfer)
+        g = pm.force_mesh(sfft.irfftn(dk, s=delta.shape), box)
     df, _ = forward(net, delta, g)
     return pm.cic_gather(g + df, pos, box)
 

@@ -420,6 +420,32 @@ class LcNet:
             self.c.knot_a[i] = float(a)
             self.c.knot_v[i] = float(v)
 
+    def set_green_filter(self, u=None, rows=None):
+        """Radial transfer T(u, a) of the corrected step's Green's function (see cola_lc_net): u the
+        knots in |k| / k_Nyquist, rows[i][j] = T at the schedule's knot_a[i] and u[j] (one row without
+        a schedule).  None: no filter."""
+        if u is None:
+            self.c.n_gknots = 0
+            return
+        if not 2 <= len(u) <= 10 or not 1 <= len(rows) <= 8 or any(len(r) != len(u) for r in rows):
+            raise ValueError("2 to 10 knots in u and 1 to 8 rows of as many values")
+        self.c.n_gknots = len(u)
+        for j, v in enumerate(u):
+            self.c.gknot_u[j] = float(v)
+        for i in range(8):
+            src = rows[min(i, len(rows) - 1)]
+            for j in range(10):
+                self.c.gknot_t[i][j] = float(src[j]) if j < len(u) else 0.0
+
+    @property
+    def green_filter(self):
+        n = int(self.c.n_gknots)
+        if not n:
+            return None
+        nr = max(1, int(self.c.n_knots))
+        return ([float(self.c.gknot_u[j]) for j in range(n)],
+                [[float(self.c.gknot_t[i][j]) for j in range(n)] for i in range(nr)])
+
     @property
     def schedule(self):
         n = int(self.c.n_knots)

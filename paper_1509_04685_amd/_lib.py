@@ -74,6 +74,7 @@ class LcNet(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int32), ("in_scale", ctypes.c_float * 4), ("out_scale", ctypes.c_float),
                 ("out_scale_slope", ctypes.c_float), ("out_band", ctypes.c_float),
                 ("n_knots", ctypes.c_int32), ("knot_a", ctypes.c_float * 8), ("knot_v", ctypes.c_float * 8),
+                ("n_gknots", ctypes.c_int32), ("gknot_u", ctypes.c_float * 10), ("gknot_t", (ctypes.c_float * 10) * 8),
                 ("params", ctypes.c_void_p), ("grads", ctypes.c_void_p), ("adam_m", ctypes.c_void_p),
                 ("adam_v", ctypes.c_void_p), ("packed", ctypes.c_void_p)]
 

@@ -215,6 +215,32 @@ struct LcHook {
     float out_band;
     int n_knots;
     float knot_a[8], knot_v[8];
+    int n_gknots;
+    float gknot_u[10], gknot_t[8][10];
+    // The Green's-function filter at a: each knot's T interpolated over the schedule's knot_a
+    // (row 0 alone without a schedule); false without a filter.
+    bool filter_at(double a, GreenFilter& gf) const {
+        if (n_gknots < 2) return false;
+        gf.n = n_gknots;
+        int i = 0;
+        double t = 0.0;
+        if (n_knots >= 2 && a > knot_a[0]) {
+            if (a >= knot_a[n_knots - 1]) {
+                i = n_knots - 1;
+            } else {
+                while (i + 2 < n_knots && a >= knot_a[i + 1]) ++i;
+                t = (a - knot_a[i]) / ((double)knot_a[i + 1] - knot_a[i]);
+            }
+        }
+        for (int j = 0; j < n_gknots; ++j) {
+            gf.u[j] = gknot_u[j];
+            const double v0 = gknot_t[i][j];
+            const double v1 = t > 0.0 ? gknot_t[i + 1][j] : v0;
+            gf.t[j] = (float)(v0 + t * (v1 - v0));
+        }
+        green_slopes(gf);
+        return true;
+    }
     // out_scale (1 + slope (1 - a)), times the knot schedule at a when there is one
     float scale_at(double a) const {
         double s = out_scale * (1.0 + out_scale_slope * (1.0 - a));
@@ -259,8 +285,10 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
     e = fft_zy_forward(reinterpret_cast<const float*>(w.S), row, bs, w.A, L.cstride, L.g, w.twg, p.n_real, 1.0f,
                        0.0f, st);
     if (e != hipSuccess) return e;
+    GreenFilter gf;
+    const bool filt = lc && lc->filter_at(a_node, gf);
     e = pm_force_from_spectrum(w.A, w.B, w.S, w.C, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real,
-                               st);
+                               st, filt ? &gf : nullptr);
     if (e != hipSuccess || !lc) return e;
     for (int r = 0; r < p.n_real; ++r) {
         float* f[3] = {reinterpret_cast<float*>(w.C) + r * bs, reinterpret_cast<float*>(w.B) + r * bs,
@@ -515,6 +543,11 @@ int make_hook(const cola_problem* prob, const cola_lc_net* net, void* lc_ws, siz
     for (int i = 0; i < 8; ++i) {
         h.knot_a[i] = net->knot_a[i];
         h.knot_v[i] = net->knot_v[i];
+    }
+    h.n_gknots = net->n_gknots;
+    for (int j = 0; j < 10; ++j) {
+        h.gknot_u[j] = net->gknot_u[j];
+        for (int i = 0; i < 8; ++i) h.gknot_t[i][j] = net->gknot_t[i][j];
     }
     return COLA_OK;
 }

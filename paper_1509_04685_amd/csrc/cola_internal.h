@@ -108,14 +108,35 @@ hipError_t launch_twiddles(float2* tw, int len, hipStream_t st);
 hipError_t fft3d_r2c(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                      const Mesh3& g, const float2* tw, int n_real, float pa, float pb, hipStream_t st);
 
+// Radial transfer of the Green's function (the learned form's filter): T(u) the cubic Hermite
+// interpolant of the n knots (u[j], t[j]) with slopes m[j] (green_slopes), u = |m| / (N/2) for the
+// signed mode integers m of an N^3 mesh, constant beyond the end knots.
+struct GreenFilter {
+    int n = 0;
+    float u[10] = {};
+    float t[10] = {};
+    float m[10] = {};
+};
+// The knot slopes of the transfer: 0 at the first knot, centred differences inside, one-sided at
+// the last.
+inline void green_slopes(GreenFilter& gf) {
+    for (int j = 0; j < gf.n; ++j) {
+        if (j == 0) gf.m[j] = 0.0f;
+        else if (j == gf.n - 1) gf.m[j] = (gf.t[j] - gf.t[j - 1]) / (gf.u[j] - gf.u[j - 1]);
+        else gf.m[j] = (gf.t[j + 1] - gf.t[j - 1]) / (gf.u[j + 1] - gf.u[j - 1]);
+    }
+}
+
 // PM force from the y-transformed spectrum in P (z and y forward passes done), with Q, R, T free
 // buffers of the same size (all distinct):
 //   fused x (forward, Green 1/(k^2 n^3), inverse) -> P = G P, Q = i k_x G P;
 //   y inverse: P -> P (times i k_y), R (plain);  Q -> Q;
 //   z c2r (out of place): Q -> T = F_x, P -> Q = F_y, R (times i k_z) -> P = F_z.
 // Real force rows of 2 nzp floats, with the ghost values of z = 0, 1 at z = n, n + 1.
+// gf (optional): the Green's function is multiplied by gf's T.
 hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
-                                  const float2* tw, float kf, int n_real, hipStream_t st);
+                                  const float2* tw, float kf, int n_real, hipStream_t st,
+                                  const GreenFilter* gf = nullptr);
 // z r2c + y forward only (first half of the PM force transform), out of place
 hipError_t fft_zy_forward(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                           const Mesh3& g, const float2* tw, int n_real, float pa, float pb,

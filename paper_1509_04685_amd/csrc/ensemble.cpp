@@ -66,6 +66,9 @@ std::string make_key(int n_classes, const cola_ensemble_class* cls, const cola_c
                 put(key, e.net->knot_a[i]);
                 put(key, e.net->knot_v[i]);
             }
+            put(key, e.net->n_gknots);
+            put(key, e.net->gknot_u);
+            put(key, e.net->gknot_t);
         }
     }
     return key;

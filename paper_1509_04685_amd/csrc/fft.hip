@@ -337,6 +337,11 @@ static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
                 err = go_x_green<D, D, 0>(L, e, ei);
                 break;
             }
+            case OP_X_GREEN_FILT: {
+                D ei{make_plan_r(L.n, R, true), les};
+                err = go_x_green<D, D, 0, true>(L, e, ei);
+                break;
+            }
             case OP_X_MULT: err = go_x_mult<D, 0>(L, e); break;
         }
     });
@@ -453,9 +458,11 @@ static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long 
 }
 
 static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstride, const Mesh3& g,
-                                    const float2* tw, float kf, int n_real, const FftShape& sh, hipStream_t st) {
+                                    const float2* tw, float kf, int n_real, const FftShape& sh, hipStream_t st,
+                                    const GreenFilter* gf = nullptr) {
     FftLaunch L;
-    L.op = OP_X_GREEN;
+    L.op = gf && gf->n > 0 ? OP_X_GREEN_FILT : OP_X_GREEN;
+    if (gf) L.gf = *gf;
     L.cg = cols_x(g, sh.width);
     L.lds = shape_lds(FK_X_GREEN, g.n, sh);
     L.grid = dim3((unsigned)((long)(g.m + 1) * L.cg.tiles), n_real);
@@ -512,8 +519,8 @@ hipError_t fft3d_r2c(const float* in, long in_row, long in_bstride, float2* out,
 }
 
 hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
-                                  const float2* tw, float kf, int n_real, hipStream_t st) {
-    hipError_t e = run_x_green_shape(P, P, Q, bstride, g, tw, kf, n_real, shape_for(FK_X_GREEN, g.n), st);
+                                  const float2* tw, float kf, int n_real, hipStream_t st, const GreenFilter* gf) {
+    hipError_t e = run_x_green_shape(P, P, Q, bstride, g, tw, kf, n_real, shape_for(FK_X_GREEN, g.n), st, gf);
     if (e != hipSuccess) return e;
     e = run_rows(OP_ROWS_SPLIT, P, R, bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;

@@ -307,14 +307,32 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, Co
     eng.last(t, [&](int q, int e) { store_col<TK>(data + base + (uint32_t)e * es, v[q]); });
 }
 
+// T(u) of a Green's-function filter: the cubic Hermite interpolant of its knots (u_j, t_j) with
+// slopes m_0 = 0, m_j = (t_{j+1} - t_{j-1}) / (u_{j+1} - u_{j-1}) inside and the one-sided slope at
+// the last knot; t_0 below the first knot, t_{n-1} beyond the last.  The slopes come with the
+// filter (green_slopes, on the host).
+__device__ __forceinline__ float green_transfer(const GreenFilter& gf, float u) {
+    if (u <= gf.u[0]) return gf.t[0];
+    float t = gf.t[gf.n - 1];
+#pragma unroll
+    for (int j = 1; j < 10; ++j)
+        if (j < gf.n && u <= gf.u[j] && u > gf.u[j - 1]) {
+            const float h = gf.u[j] - gf.u[j - 1];
+            const float s = (u - gf.u[j - 1]) / h, s2 = s * s, s3 = s2 * s;
+            t = (2.0f * s3 - 3.0f * s2 + 1.0f) * gf.t[j - 1] + (s3 - 2.0f * s2 + s) * h * gf.m[j - 1] +
+                (3.0f * s2 - 2.0f * s3) * gf.t[j] + (s3 - s2) * h * gf.m[j];
+        }
+    return t;
+}
+
 // Fused x pass of the particle-mesh force on the (kz, y) columns: forward x FFT,
 // V = S / (k^2 n^3) (k = 0 -> 0), then A = IFFT_x[V] and B = IFFT_x[i k_x V] (the k_x Nyquist plane
 // of B set to 0).  ef: forward engine; ei: the same radices reversed, so the inverse starts from
 // the forward's output pattern without an LDS round trip.
-template <class LF, class LI, int TK>
+template <class LF, class LI, int TK, bool FILT = false>
 __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A, float2* B, long bstride,
                                                      ColGeom cg, LF ef, LI ei, const float2* tw, float kf,
-                                                     float gscale) {
+                                                     float gscale, GreenFilter gf) {
     constexpr int R = LF::kR;
     constexpr int TW = pair_tw_entries<LF, LI>();
     extern __shared__ float2 lds[];
@@ -340,6 +358,7 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
         int mx = signed_mode(e, n);
         float m2 = (float)(mx * mx) + kyz2;
         float gk = (m2 > 0.0f) ? g0 * __builtin_amdgcn_rcpf(m2) : 0.0f;  // hardware reciprocal, 1 ulp
+        if constexpr (FILT) gk *= green_transfer(gf, sqrtf(m2) * (2.0f / (float)n));
         v[q] = cscale(v[q], gk);
         float kx = (2 * mx == -n) ? 0.0f : kf * (float)mx;
         h[q] = make_float2(-kx * v[q].y, kx * v[q].x);  // i k_x V
@@ -405,7 +424,8 @@ __global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spe
 enum FftOp {
     OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ,          // z passes (line length n/2)
     OP_ROWS_FWD, OP_ROWS_INV, OP_ROWS_SPLIT,       // y rows
-    OP_COLS_FWD, OP_X_GREEN, OP_X_MULT             // x columns
+    OP_COLS_FWD, OP_X_GREEN, OP_X_MULT,            // x columns
+    OP_X_GREEN_FILT                                // x_green with a Green's-function filter
 };
 inline bool is_z_op(FftOp op) { return op <= OP_Z_C2R_IKZ; }
 inline bool is_rows_op(FftOp op) { return op >= OP_ROWS_FWD && op <= OP_ROWS_SPLIT; }
@@ -438,6 +458,7 @@ struct FftLaunch {
     float2* d1 = nullptr;
     long b0 = 0, b1 = 0;
     ColGeom cg{};
+    GreenFilter gf{};
     const float2* tw = nullptr;
     float kf = 0.0f, scale = 1.0f;
     int mtype = 0, ax_a = 0, ax_b = 0;
@@ -488,12 +509,13 @@ inline hipError_t go_cols(const FftLaunch& L, LE e) {
     return hipGetLastError();
 }
 
-template <class LF, class LI, int TK>
+template <class LF, class LI, int TK, bool FILT = false>
 inline hipError_t go_x_green(const FftLaunch& L, LF f, LI i) {
-    auto kern = k_fft_x_green<LF, LI, TK>;
+    auto kern = k_fft_x_green<LF, LI, TK, FILT>;
     const size_t lds = L.lds + tw_lds_bytes(pair_tw_entries<LF, LI>());
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
-    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.c0, L.d0, L.d1, L.b0, L.cg, f, i, L.tw, L.kf, L.scale);
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.c0, L.d0, L.d1, L.b0, L.cg, f, i, L.tw, L.kf, L.scale,
+                       L.gf);
     return hipGetLastError();
 }
 
@@ -517,6 +539,7 @@ inline hipError_t static_cols_ops(const FftLaunch& L) {
     switch (L.op) {
         case OP_COLS_FWD: return go_cols<F, TK>(L, F{});
         case OP_X_GREEN: return go_x_green<F, I, TK>(L, F{}, I{});
+        case OP_X_GREEN_FILT: return go_x_green<F, I, TK, true>(L, F{}, I{});
         case OP_X_MULT: return go_x_mult<F, TK>(L, F{});
         default: return hipErrorNotSupported;
     }

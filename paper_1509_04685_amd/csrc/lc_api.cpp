@@ -61,6 +61,14 @@ int lc_check_net(const cola_lc_net* net, bool training) {
         if (!std::isfinite(net->knot_a[i]) || !std::isfinite(net->knot_v[i])) return COLA_ERR_NONFINITE;
         if (i > 0 && !(net->knot_a[i] > net->knot_a[i - 1])) return COLA_ERR_INVALID_ARG;
     }
+    if (net->n_gknots != 0 && (net->n_gknots < 2 || net->n_gknots > 10)) return COLA_ERR_INVALID_ARG;
+    const int rows = net->n_knots >= 2 ? net->n_knots : 1;
+    for (int j = 0; j < net->n_gknots; ++j) {
+        if (!std::isfinite(net->gknot_u[j])) return COLA_ERR_NONFINITE;
+        if (j > 0 && !(net->gknot_u[j] > net->gknot_u[j - 1])) return COLA_ERR_INVALID_ARG;
+        for (int i = 0; i < rows; ++i)
+            if (!std::isfinite(net->gknot_t[i][j])) return COLA_ERR_NONFINITE;
+    }
     if (training && (!net->grads || !net->adam_m || !net->adam_v)) return COLA_ERR_INVALID_ARG;
     return COLA_OK;
 }

@@ -161,6 +161,9 @@ def load_net(path, training=False):
     net.set_scales(net.in_scale, net.out_scale, doc.get("out_scale_slope", 0.0), doc.get("out_band", 0.0))
     sched = doc.get("schedule")
     net.set_schedule(*(sched if sched else (None, None)))
+    gfil = doc.get("green_filter")
+    if gfil:
+        net.set_green_filter(gfil["u"], gfil["t"])
     return net, doc
 
 
@@ -250,3 +253,111 @@ def calibrate_schedule(net, cosmo, box, n_part, z_init, n_steps, seeds, knot_a, 
             break
     net.set_schedule(knot_a, vals)
     return vals, best, moves
+
+
+def calibrate_green_filter(net, cosmo, box, n_part, z_init, n_steps, seeds, u_knots, a_outs=(1.0,), n_pk=None,
+                           k_max=1.0, p_norms=(2, 2, 4, 4, 4, 6, 6, 6), h=0.04, smooth=0.1, n_fixed=1,
+                           seed_mean=False, log=None):
+    """Trajectory-level calibration of the corrected step's Green's-function transfer T(u, a)
+    together with the output-scale schedule, on training realizations.  Parameters: T at every
+    (schedule knot a_i, u_j) beyond the first n_fixed knots and the schedule's knot values; T = 1 at
+    the first n_fixed knots (the first one is u = 0): the long-wavelength force, and with it the
+    linear growth, stays the PM force's; residuals: P / P_3x - 1 in every bin
+    with 0 < k < k_max at every output of every seed.  One Levenberg-Marquardt step per entry of
+    p_norms on the p-norm of the residuals (iteratively reweighted least squares, weights
+    (|r| / max |r|)^(p - 2): least squares first, then larger p, which approaches the worst case
+    that the target bounds), with a forward-difference Jacobian (step h) and a second-difference
+    penalty in u and in a (weight `smooth`) that keeps T smooth.  A step is taken when it lowers
+    that p-norm; the parameters with the smallest worst |P / P_3x - 1| seen are kept.  seed_mean:
+    the residuals are the errors averaged over the seeds bin by bin (the systematic part, which a
+    transfer can remove; each realization adds its own scatter of a few per mille near k_max).  Sets the filter and schedule on the network and returns (u_knots, rows, knot_v,
+    worst error, history)."""
+    n_pk = n_pk or n_part * 3
+    n_bins = n_pk // 2
+    prob1 = make_problem(box, n_part, 1, z_init, n_steps)
+    prob3 = make_problem(box, n_part, 3, z_init, n_steps)
+    refs = [run_spectra(prob3, cosmo, s, a_outs, n_pk, n_bins) for s in seeds]
+    sched = net.schedule
+    if sched is None:
+        raise ValueError("the network needs an output-scale schedule (its knots carry T's rows)")
+    knot_a, knot_v = [float(v) for v in sched[0]], [float(v) for v in sched[1]]
+    if float(u_knots[0]) != 0.0:
+        raise ValueError("the first knot of the transfer is u = 0")
+    na, nu = len(knot_a), len(u_knots) - n_fixed  # free values per row
+    theta = np.concatenate([np.ones(na * nu), np.asarray(knot_v)])
+    start = net.green_filter
+    if start is not None and list(start[0]) == [float(np.float32(u)) for u in u_knots]:
+        theta[:na * nu] = np.asarray([r[n_fixed:] for r in start[1][:na]]).ravel()
+
+    def rows_of(th):
+        return [[1.0] * n_fixed + list(th[i * nu:(i + 1) * nu]) for i in range(na)]
+
+    def apply(th):
+        net.set_green_filter(list(u_knots), rows_of(th))
+        net.set_schedule(knot_a, list(th[na * nu:]))
+
+    def resid(th):
+        apply(th)
+        out = []
+        for s, ref in zip(seeds, refs):
+            got = run_spectra(prob1, cosmo, s, a_outs, n_pk, n_bins, net=net)
+            for (k, p3), (_, pl) in zip(ref, got):
+                sel = (k > 0) & (k < k_max) & (p3 > 0)
+                out.append(pl[sel] / p3[sel] - 1.0)
+        if seed_mean:
+            return np.mean(np.asarray(out).reshape(len(seeds), len(a_outs), -1), axis=0).ravel()
+        return np.concatenate(out)
+
+    def pnorm(r, p):
+        m = np.abs(r).max()
+        return float(m * np.mean((np.abs(r) / m) ** p) ** (1.0 / p))
+
+    # second differences of T along u (within each row) and along a (within each column)
+    rows_d = []
+    for i in range(na):
+        for j in range(1, nu - 1):
+            e = np.zeros(theta.size)
+            e[i * nu + j - 1], e[i * nu + j], e[i * nu + j + 1] = 1.0, -2.0, 1.0
+            rows_d.append(e)
+    for j in range(nu):
+        for i in range(1, na - 1):
+            e = np.zeros(theta.size)
+            e[(i - 1) * nu + j], e[i * nu + j], e[(i + 1) * nu + j] = 1.0, -2.0, 1.0
+            rows_d.append(e)
+    D = np.asarray(rows_d)
+    r = resid(theta)
+    best_theta, best = theta.copy(), float(np.abs(r).max())
+    history = [(0, best)]
+    if log:
+        log(f"[green] start: worst {best:.4f}, rms {np.sqrt(np.mean(r ** 2)):.4f}")
+    for it, p_norm in enumerate(p_norms):
+        J = np.empty((r.size, theta.size))
+        for q in range(theta.size):
+            tp = theta.copy()
+            tp[q] += h
+            J[:, q] = (resid(tp) - r) / h
+        w = (np.abs(r) / np.abs(r).max()) ** (p_norm - 2.0)
+        w = w / float(np.mean(w))  # mean weight 1: the penalty keeps its weight across p
+        JW = J * w[:, None]
+        JtJ = JW.T @ J
+        lm = float(np.mean(np.diag(JtJ)))
+        taken = False
+        for mu in (1e-3, 1e-2, 1e-1, 1.0):
+            A = JtJ + smooth * (D.T @ D) + mu * lm * np.eye(theta.size)
+            step = np.linalg.solve(A, -(JW.T @ r + smooth * (D.T @ (D @ theta))))
+            trial = theta + step
+            rt = resid(trial)
+            wt = float(np.abs(rt).max())
+            if log:
+                log(f"[green] step {it} (p = {p_norm}) damping {mu:g}: worst {wt:.4f}, "
+                    f"rms {np.sqrt(np.mean(rt ** 2)):.4f}")
+            if pnorm(rt, p_norm) < pnorm(r, p_norm):
+                theta, r, taken = trial, rt, True
+                if wt < best:
+                    best_theta, best = trial.copy(), wt
+                history.append((it + 1, wt))
+                break
+        if not taken and p_norm == p_norms[-1]:
+            break
+    apply(best_theta)
+    return list(u_knots), rows_of(best_theta), list(best_theta[na * nu:]), best, history

@@ -17,6 +17,13 @@ coarse form on the training seeds, the positions it visits get fine-mesh targets
 fine-tuned on the old and new samples together and calibrated again.  The weights file holds the flat
 FP32 parameters in the library's order, the input and output scales (fitted and calibrated), the
 validation loss before and after training, the calibration table and the recipe.
+
+    python paper_1509_04685_amd/train_lc.py --calibrate-filter paper_1509_04685_amd/lc_weights_c16.json
+
+calibrates, for an existing weights file, a radial transfer T(|k| / k_Nyquist, a) of the corrected
+step's Green's function together with the schedule (damped Gauss-Newton on the p-norm, p = 8, of
+the errors of every P(k) bin with k < 1 h/Mpc of the training seeds 3001-3004 at every output) and
+writes it into the file.
 """
 
 import argparse
@@ -38,6 +45,12 @@ RECIPE = dict(box=384.0, n_part=128, pm_fine=3, n_steps=40, z_init=19.0,
               onpolicy_rounds=0, onpolicy_iters=1500, onpolicy_lr=1e-3,
               onpolicy_factors=tuple(round(0.9 + 0.05 * i, 2) for i in range(13)),
               onpolicy_slopes=tuple(round(-0.2 + 0.2 * i, 1) for i in range(6)))
+
+
+# knots of the Green's-function transfer in |k| / k_Nyquist of the coarse mesh (the last one covers
+# the mesh corners)
+FILTER_U = (0.0, 0.12, 0.25, 0.38, 0.5, 0.62, 0.74, 0.86, 0.98, 1.3)
+FILTER_FIXED = 1  # T = 1 (with zero slope) at u = 0: the large-scale force stays the PM force
 
 
 def train(channels, recipe=RECIPE, log=print):
@@ -93,6 +106,38 @@ def train(channels, recipe=RECIPE, log=print):
     return net, v0, v1, fitted, table
 
 
+def calibrate_filter_file(path, recipe=RECIPE, log=print, n_part=None, seeds=None, p_norms=None, seed_mean=False):
+    """The Green's-function transfer of the corrected step (T at the schedule's knots in a and at
+    FILTER_U in |k| / k_Nyquist), calibrated with the schedule by damped Gauss-Newton on the
+    training seeds' trajectories (every output a), written into the weights file."""
+    import paper_1509_04685_amd as cola
+    from paper_1509_04685_amd import learned as L, workloads as W
+    r = recipe
+    cosmo = cola.make_cosmology(**W.COSMOLOGY)
+    net, doc = L.load_net(path)
+    t0 = time.time()
+    # the same 3 h^-1 Mpc cells as the training pairs, in a box scaled with the particle count
+    n_part = n_part or r["n_part"]
+    box = r["box"] * n_part / r["n_part"]
+    seeds = tuple(seeds or r["calib_seeds"])
+    extra = {} if p_norms is None else {"p_norms": tuple(p_norms)}
+    u, rows, knot_v, worst, hist = L.calibrate_green_filter(
+        net, cosmo, box, n_part, r["z_init"], r["n_steps"], seeds, FILTER_U,
+        a_outs=r["calib_a"], n_fixed=FILTER_FIXED, seed_mean=seed_mean, log=log, **extra)
+    log(f"[train_lc] Green's-function transfer calibrated: worst training-seed error {worst:.4f} "
+        f"({time.time() - t0:.1f} s)")
+    prev = doc.get("green_filter") or {}
+    passes = prev.get("passes", []) if list(prev.get("u", [])) == list(u) else []
+    passes.append({"seeds": list(seeds), "n_part": n_part, "box": box, "seed_mean": seed_mean,
+                   "worst_training_error": worst, "history": hist})
+    doc["green_filter"] = {"u": u, "t": rows, "worst_training_error": worst, "a_outs": list(r["calib_a"]),
+                           "passes": passes}
+    doc["schedule"] = [net.schedule[0], knot_v]
+    with open(path, "w") as fh:
+        json.dump(doc, fh)
+    log(f"[train_lc] wrote {path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--channels", type=int, default=16)
@@ -100,7 +145,22 @@ def main():
     ap.add_argument("--iters", type=int, default=RECIPE["iters"])
     ap.add_argument("--onpolicy-rounds", type=int, default=RECIPE["onpolicy_rounds"])
     ap.add_argument("--force-input", action="store_true", help="the network also sees the three force components")
+    ap.add_argument("--calibrate-filter", metavar="WEIGHTS", default=None,
+                    help="calibrate the Green's-function transfer (and the schedule) of an existing weights "
+                         "file on the training seeds and write it back (no training)")
+    ap.add_argument("--calib-n-part", type=int, default=None,
+                    help="particles per side of the filter calibration runs (box scaled to keep 3 h^-1 Mpc cells)")
+    ap.add_argument("--calib-seeds", type=int, nargs="*", default=None,
+                    help="training seeds of the filter calibration (default: the recipe's calibration seeds)")
+    ap.add_argument("--calib-p", type=float, nargs="*", default=None,
+                    help="p of the p-norm of each calibration step (default 2 2 4 4 4 6 6 6)")
+    ap.add_argument("--calib-seed-mean", action="store_true",
+                    help="fit the errors averaged over the calibration seeds (their systematic part)")
     args = ap.parse_args()
+    if args.calibrate_filter:
+        calibrate_filter_file(args.calibrate_filter, log=lambda m: print(m, flush=True), n_part=args.calib_n_part,
+                              seeds=args.calib_seeds, p_norms=args.calib_p, seed_mean=args.calib_seed_mean)
+        return
     out = args.out or os.path.join(HERE, f"lc_weights_c{args.channels}.json")
     recipe = dict(RECIPE, iters=args.iters, onpolicy_rounds=args.onpolicy_rounds,
                   force_input=args.force_input)

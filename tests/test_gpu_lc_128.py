@@ -107,3 +107,51 @@ def test_random_network_with_force_inputs_128(cola):
     olc.set_flat_params(onet, flat.astype(np.float64))
     net = cola.LcNet(16, params=flat, in_scale=onet.in_scale, out_scale=onet.out_scale, training=False)
     check(cola, net, onet, seed=1290, n_real=2)
+
+
+def test_green_filter_128(cola):
+    """The Green's-function transfer T(u, a) of the corrected step: rows at the schedule's knots,
+    evaluated between two knots (a = 0.6), against the oracle's corrected force with the same T
+    interpolated in a by numpy and the schedule's output scale at a.  Bound: |got - ref| RMS <=
+    1e-5 of the force plus 1.5e-2 of the network's part; the transfer moves the force by >1 %."""
+    from paper_1509_04685_amd import learned as L
+    path = os.path.join(ROOT, "paper_1509_04685_amd", "lc_weights_c16.json")
+    if not os.path.exists(path):
+        pytest.skip("no trained weights")
+    say("corrected force with a Green's-function transfer, trained network, 128^3, a = 0.6")
+    net, doc = L.load_net(path)
+    knot_a = [0.05, 0.2, 0.35, 0.5, 0.65, 0.8, 1.0]
+    knot_v = [0.9, 1.1, 1.0, 0.8, 1.2, 1.05, 1.0]
+    u = [0.0, 0.2, 0.45, 0.7, 0.95, 1.3]
+    rows = [[1.0 + 0.05 * i * np.sin(3.0 * uj + i) for uj in u] for i in range(len(knot_a))]
+    net.set_scales(net.in_scale, net.out_scale, 0.0, 0.0)
+    net.set_schedule(knot_a, knot_v)
+    net.set_green_filter(u, rows)
+    a = 0.6
+    t_at = [float(np.interp(a, knot_a, [r[j] for r in rows])) for j in range(len(u))]
+    scale = net.out_scale * float(np.interp(a, knot_a, knot_v))
+    params = np.asarray(doc["params"], dtype=np.float32).astype(np.float64)
+    onet = olc.Net(channels=net.channels, in_scale=net.in_scale, out_scale=scale)
+    olc.set_flat_params(onet, params)
+    onet0 = olc.Net(channels=net.channels, in_scale=net.in_scale, out_scale=0.0)
+    olc.set_flat_params(onet0, params)
+    prob = cola.make_problem(BOX, N_PART, 1, 19.0, 40)
+    disp = W.random_displacements(N_PART, 2.0, seed=1301).astype(np.float32)
+    st = cola.ParticleState(prob)
+    st.x.copy_(torch.as_tensor(disp, device="cuda"))
+    ws = cola.Workspace(prob)
+    lws = cola.lc_workspace(N_PART, net.channels, 1)
+    got = cola.pm_force_lc(prob, st, net, lws, ws, a=a).cpu().numpy().astype(np.float64)
+    op = ocola.Problem(BOX, N_PART, 1, 19.0, 40)
+    pos = ocola.positions(ocola.State(disp.astype(np.float64), None, None, None), op)
+    say("  oracle corrected force with the transfer")
+    ref = olc.corrected_accel(onet, pos, N_PART, BOX, transfer=(u, t_at))
+    mesh_ref = olc.corrected_accel(onet0, pos, N_PART, BOX, transfer=(u, t_at))
+    plain_ref = opm.pm_accel(pos, N_PART, BOX)
+    rms = lambda x: float(np.sqrt(np.mean(x ** 2)))  # noqa: E731
+    err = rms(got - ref)
+    bound = 1e-5 * rms(ref) + 1.5e-2 * rms(ref - mesh_ref)
+    effect = rms(mesh_ref - plain_ref) / rms(plain_ref)
+    say(f"  |got - ref| {err:.3e} (bound {bound:.3e}); the transfer moves the mesh force by {effect:.3f}")
+    assert effect > 1e-2
+    assert err < bound

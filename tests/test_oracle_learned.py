@@ -158,3 +158,33 @@ def test_flat_params_roundtrip_and_order():
     L.set_flat_params(other, flat)
     for a, b in zip(net.params(), other.params()):
         assert np.array_equal(a, b)
+
+
+def test_green_transfer_values_and_reductions():
+    """T(u), u = |m| / (n/2): the cubic Hermite interpolant with slopes 0, centred, one-sided, worked
+    by hand on knots (0, 1), (0.5, 2), (1, 0): slopes m = (0, -1, -4); at the midpoint of a piece
+    T = (t_j + t_j+1) / 2 + h (m_j - m_j+1) / 8, at s = 3/4 of the first piece
+    T = h00 t0 + h01 t1 + h h11 m1 with h00 = 5/32, h01 = 27/32, h11 = -9/64; constant beyond the
+    end knots.  T = 1 gives the plain corrected force and a constant T = c scales the mesh force by
+    c (network output switched off)."""
+    n = 16
+    T = L.green_transfer(n, [0.0, 0.5, 1.0], [1.0, 2.0, 0.0])
+    assert T[0, 0, 0] == 1.0
+    assert T[0, 4, 0] == pytest.approx(2.0)                               # u = 1/2, a knot
+    assert T[0, 2, 0] == pytest.approx(1.5 + 0.5 * (0.0 + 1.0) / 8)        # u = 1/4, midpoint
+    assert T[0, 0, 6] == pytest.approx(1.0 + 0.5 * (-1.0 + 4.0) / 8)       # u = 3/4, midpoint
+    assert T[3, 0, 0] == pytest.approx(5 / 32 + 27 / 32 * 2.0 + 0.5 * (-9 / 64) * (-1.0))  # u = 3/8
+    assert T[8, 8, 8] == 0.0                                               # u = sqrt(3): beyond
+    assert T[n - 3, 0, 0] == T[3, 0, 0]                                    # m = -3
+    rng = np.random.default_rng(17)
+    box = 20.0
+    pos = rng.uniform(0, box, size=(3, 400))
+    net = L.Net(channels=4, seed=5, out_scale=0.5)
+    base = L.corrected_accel(net, pos, n, box)
+    same = L.corrected_accel(net, pos, n, box, transfer=([0.0, 1.0], [1.0, 1.0]))
+    assert np.allclose(same, base, rtol=0, atol=1e-12)
+    net.w3[:] = 0.0
+    net.b3[:] = 0.0
+    plain = L.corrected_accel(net, pos, n, box)
+    scaled = L.corrected_accel(net, pos, n, box, transfer=([0.2, 0.9], [0.7, 0.7]))
+    assert np.allclose(scaled, 0.7 * plain, rtol=1e-12, atol=1e-14)
