@@ -731,7 +731,7 @@ def main():
             (name, tag), (ms, cnt) = dom
             b = algorithmic_bytes(name, tag, n_g, n_part)
             achieved = b / (ms / cnt / 1e3) / 1e9
-            traffic = read_traffic(name, tag)
+            traffic = read_traffic(name, tag or n_g)
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": traffic, "kernel": name, "mesh": tag or n_g, "bytes_per_launch": b,
@@ -749,7 +749,7 @@ def main():
                     "ms_per_launch": round(kms / kcnt, 4), "bytes_per_launch": kb,
                     "achieved": round(kach, 1) if kach else None,
                     "frac": round(kach / HBM_PEAK_GBS, 4) if kach else None,
-                    "traffic": read_traffic(kname, ktag)})
+                    "traffic": read_traffic(kname, ktag or n_g)})
 
     result = {
         "metric": METRIC,

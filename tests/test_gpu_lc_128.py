@@ -91,6 +91,7 @@ def test_trained_network_128(cola):
     net, doc = L.load_net(path)
     net.set_scales(net.in_scale, net.out_scale, 0.0, 0.0)
     net.set_schedule(None)  # output scale = out_scale, as in the oracle
+    net.set_green_filter(None)  # the plain Green's function, as in the oracle's default
     onet = olc.Net(channels=net.channels, in_scale=net.in_scale, out_scale=net.out_scale)
     olc.set_flat_params(onet, np.asarray(doc["params"], dtype=np.float32).astype(np.float64))
     check(cola, net, onet, seed=1281)
