@@ -116,15 +116,23 @@ struct GreenFilter {
     float u[10] = {};
     float t[10] = {};
     float m[10] = {};
+    float u_last = 0.0f, t_last = 1.0f;
 };
 // The knot slopes of the transfer: 0 at the first knot, centred differences inside, one-sided at
-// the last.
+// the last; knots past the n-th padded with u = 3e38 (never reached), the last knot copied out.
 inline void green_slopes(GreenFilter& gf) {
     for (int j = 0; j < gf.n; ++j) {
         if (j == 0) gf.m[j] = 0.0f;
         else if (j == gf.n - 1) gf.m[j] = (gf.t[j] - gf.t[j - 1]) / (gf.u[j] - gf.u[j - 1]);
         else gf.m[j] = (gf.t[j + 1] - gf.t[j - 1]) / (gf.u[j + 1] - gf.u[j - 1]);
     }
+    for (int j = gf.n; j < 10; ++j) {
+        gf.u[j] = 3.0e38f;
+        gf.t[j] = gf.t[gf.n - 1];
+        gf.m[j] = 0.0f;
+    }
+    gf.u_last = gf.u[gf.n - 1];
+    gf.t_last = gf.t[gf.n - 1];
 }
 
 // PM force from the y-transformed spectrum in P (z and y forward passes done), with Q, R, T free

@@ -311,18 +311,27 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, Co
 // slopes m_0 = 0, m_j = (t_{j+1} - t_{j-1}) / (u_{j+1} - u_{j-1}) inside and the one-sided slope at
 // the last knot; t_0 below the first knot, t_{n-1} beyond the last.  The slopes come with the
 // filter (green_slopes, on the host).
+// The piece is found by selects over the knots at fixed indices (the knots past the n-th are padded
+// with u = 3e38 by green_slopes), so that the filter stays in scalar registers: indexing it with a
+// lane value would copy it to scratch memory.
 __device__ __forceinline__ float green_transfer(const GreenFilter& gf, float u) {
     if (u <= gf.u[0]) return gf.t[0];
-    float t = gf.t[gf.n - 1];
+    if (u >= gf.u_last) return gf.t_last;
+    float ua = gf.u[0], ub = gf.u[1], ta = gf.t[0], tb = gf.t[1], ma = gf.m[0], mb = gf.m[1];
 #pragma unroll
-    for (int j = 1; j < 10; ++j)
-        if (j < gf.n && u <= gf.u[j] && u > gf.u[j - 1]) {
-            const float h = gf.u[j] - gf.u[j - 1];
-            const float s = (u - gf.u[j - 1]) / h, s2 = s * s, s3 = s2 * s;
-            t = (2.0f * s3 - 3.0f * s2 + 1.0f) * gf.t[j - 1] + (s3 - 2.0f * s2 + s) * h * gf.m[j - 1] +
-                (3.0f * s2 - 2.0f * s3) * gf.t[j] + (s3 - s2) * h * gf.m[j];
-        }
-    return t;
+    for (int j = 2; j < 10; ++j) {
+        const bool past = u > gf.u[j - 1];
+        ua = past ? gf.u[j - 1] : ua;
+        ub = past ? gf.u[j] : ub;
+        ta = past ? gf.t[j - 1] : ta;
+        tb = past ? gf.t[j] : tb;
+        ma = past ? gf.m[j - 1] : ma;
+        mb = past ? gf.m[j] : mb;
+    }
+    const float h = ub - ua;
+    const float s = (u - ua) / h, s2 = s * s, s3 = s2 * s;
+    return (2.0f * s3 - 3.0f * s2 + 1.0f) * ta + (s3 - 2.0f * s2 + s) * h * ma + (3.0f * s2 - 2.0f * s3) * tb +
+           (s3 - s2) * h * mb;
 }
 
 // Fused x pass of the particle-mesh force on the (kz, y) columns: forward x FFT,
