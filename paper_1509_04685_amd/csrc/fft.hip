@@ -232,7 +232,8 @@ static bool shape_ok(FftKind k, int n, const FftShape& sh) {
     // z passes: a power-of-two number of lines of one x plane per block
     if (is_z(k) && (log2_exact(sh.width) < 0 || n % sh.width)) return false;
     long threads = (long)sh.width * (L / sh.R);
-    if (threads > 512 || threads < 1) return false;
+    // 1024-thread blocks only for the static x-column plans with split exchanges (compiled for them)
+    if (threads > (sh.split ? 1024 : 512) || threads < 1) return false;
     return shape_lds(k, n, sh) <= 128 * 1024;
 }
 
@@ -563,13 +564,14 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
         std::vector<FftShape> cands;
         for (int R : valid_rs(L))
             for (int w : {1, 2, 4, 8, 16, 32, 64}) {
+                const long threads = (long)w * (L / R);
+                if (threads < 64 && w < 64) continue;
+                const FftShape sp{R, w, true, true};
+                if (shape_ok(kind, n, sp) && static_available(kind, n, R, w, true)) cands.push_back(sp);
                 FftShape sh{R, w, false};
                 if (!shape_ok(kind, n, sh)) continue;
-                long threads = (long)w * (L / R);
-                if (threads < 64 && w < 64) continue;
                 cands.push_back(sh);
                 if (static_available(kind, n, R, w)) cands.push_back(FftShape{R, w, true});
-                if (static_available(kind, n, R, w, true)) cands.push_back(FftShape{R, w, true, true});
             }
         if (cands.empty()) continue;
         auto launch = [&](const FftShape& sh) -> hipError_t {

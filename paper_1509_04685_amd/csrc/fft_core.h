@@ -290,6 +290,7 @@ struct DynLine {
     static constexpr int kR = R;
     static constexpr bool kStatic = false;
     static constexpr bool kSplit = false;
+    static constexpr int kT = 0;  // threads per line: known at run time only
     static constexpr int kN = 0;
     static constexpr int kTwN = 0;  // reads the table in global memory
     FftPlan p;

@@ -62,6 +62,13 @@ __device__ __forceinline__ float2* col_lds(float2* lds, int tw_entries, int ct) 
     else return lds + tw_entries + ct;
 }
 
+// Launch bound of a column kernel: 512 threads, or 1024 for a compile-time plan whose tile needs
+// them (wide tiles of many-thread lines, affordable with the split exchange's half-size LDS).
+template <class LE, int TK>
+constexpr int col_bound() {
+    return (LE::kStatic && TK > 0 && TK * LE::kT > 512) ? 1024 : 512;
+}
+
 // ------------------------------------------------------------------ twiddles in LDS
 
 // Table entries a kernel stages at the front of its LDS (0: it reads the global table).  The z
@@ -289,7 +296,7 @@ __global__ void __launch_bounds__(512) k_fft_rows(float2* A, float2* S, long bst
 
 // Forward x transform of every (kz, y) column.
 template <class LE, int TK>
-__global__ void __launch_bounds__(512) k_fft_cols(float2* data, long bstride, ColGeom cg, LE eng, const float2* tw) {
+__global__ void __launch_bounds__((col_bound<LE, TK>())) k_fft_cols(float2* data, long bstride, ColGeom cg, LE eng, const float2* tw) {
     constexpr int R = LE::kR;
     constexpr int TW = LE::kTwN;
     extern __shared__ float2 lds[];
@@ -339,7 +346,7 @@ __device__ __forceinline__ float green_transfer(const GreenFilter& gf, float u) 
 // of B set to 0).  ef: forward engine; ei: the same radices reversed, so the inverse starts from
 // the forward's output pattern without an LDS round trip.
 template <class LF, class LI, int TK, bool FILT = false>
-__global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A, float2* B, long bstride,
+__global__ void __launch_bounds__((col_bound<LF, TK>())) k_fft_x_green(const float2* S, float2* A, float2* B, long bstride,
                                                      ColGeom cg, LF ef, LI ei, const float2* tw, float kf,
                                                      float gscale, GreenFilter gf) {
     constexpr int R = LF::kR;
@@ -383,7 +390,7 @@ __global__ void __launch_bounds__(512) k_fft_x_green(const float2* S, float2* A,
 //   MUL_SCALE: M = scale;  MUL_IK: M = i k_a / k^2 * scale;  MUL_KK: M = k_a k_b / k^2 * scale.
 // A factor k_d is zeroed on the Nyquist plane of axis d when it appears to an odd power.
 template <class LE, int TK>
-__global__ void __launch_bounds__(512) k_fft_x_mult(const float2* spec, long spec_bstride, float2* W,
+__global__ void __launch_bounds__((col_bound<LE, TK>())) k_fft_x_mult(const float2* spec, long spec_bstride, float2* W,
                                                     long w_bstride, ColGeom cg, LE eng, const float2* tw,
                                                     int mtype, int ax_a, int ax_b, float kf, float scale) {
     constexpr int R = LE::kR;

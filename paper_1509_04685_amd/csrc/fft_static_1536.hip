@@ -21,6 +21,7 @@ hipError_t fft_static_1536(const FftLaunch& L) {
     }
     if (L.split) {
         if (L.R == 24 && L.width == 8) return static_cols_ops<1536, 24, 8, true>(L);
+        if (L.R == 12 && L.width == 8) return static_cols_ops<1536, 12, 8, true>(L);  // 1024 threads
         return hipErrorNotSupported;
     }
     if (L.R == 24 && L.width == 8) return static_cols_ops<1536, 24, 8>(L);

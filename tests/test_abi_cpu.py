@@ -236,8 +236,11 @@ def test_fft_set_shape_split_plans_host_checks():
     f = LIB.cola_fft_set_shape
     assert f(768, b"x_green", 24, 16, 2) == 0
     assert f(1536, b"x_green", 24, 8, 2) == 0
+    assert f(1536, b"x_green", 12, 8, 2) == 0   # 1024-thread blocks: split plans only
+    assert f(1536, b"x_green", 12, 8, 1) == -1
     assert f(768, b"rows_y", 24, 8, 2) == -1
     assert f(512, b"x_green", 16, 8, 2) == -1
     assert f(768, b"x_green", 24, 16, 3) == -1
     assert f(768, b"x_green", 24, 8, 1) == 0  # restore a plain static plan
     assert f(768, b"x_green", 24, 16, 1) == 0
+    assert f(1536, b"x_green", 24, 4, 1) == 0
