@@ -613,9 +613,10 @@ def learned_bench(cola, torch, cfg_name, pk_plain3, a_outs, n_pk, n_bins, ms_pla
                       + (f", schedule {[round(v, 3) for v in net.schedule[1]]} at a = {[round(v, 3) for v in net.schedule[0]]}"
                          if net.schedule else "")
                       + (f"; Green's-function transfer T(|k|/k_N, a): cubic in |k|/k_N on {len(net.green_filter[0])} "
-                         f"knots, rows at the schedule's knots, calibrated with the schedule at trajectory level on "
-                         f"training seeds {doc['green_filter']['passes'][0]['seeds']} "
-                         f"({doc['green_filter']['passes'][0]['n_part']}^3 particles)" if net.green_filter else "")
+                         f"knots, rows at the schedule's knots, calibrated with the schedule at trajectory level in "
+                         f"{len(doc['green_filter']['passes'])} passes on training seeds "
+                         + ", ".join(f"{p['seeds'][0]}-{p['seeds'][-1]}" for p in doc['green_filter']['passes'])
+                         + f" ({doc['green_filter']['passes'][-1]['n_part']}^3 particles)" if net.green_filter else "")
                       + f"; evaluation seed {c['seeds'][0]} held out")
     res["workload"] = (f"{lname}: {c['n_part']}^3 particles, {c['n_part']}^3 mesh (PM_grid 1), box {c['box']:g}, "
                        f"40 nodes from z=19, seed {c['seeds'][0]}, P(k) on {n_pk}^3 at the same outputs; error = "
@@ -813,7 +814,7 @@ def main():
     if not args.no_learned:
         print("[bench] learned correction: 256^3 on the 256^3 mesh vs the plain runs", file=sys.stderr, flush=True)
         result["learned"] = learned_bench(cola, torch, args.workload, [o[1].cpu().numpy()[0] for o in outs], a_outs, n_pk,
-                                          n_bins, ms_per_step, reps=2, halo3=halo3, holdout_seeds=(31, 32, 33, 34, 35))
+                                          n_bins, ms_per_step, reps=2, halo3=halo3, holdout_seeds=(41, 42, 43, 44, 45))
         print(f"[bench] learned: {json.dumps(result['learned'])}", file=sys.stderr, flush=True)
     if not args.no_ensemble:
         del st, ws, outs

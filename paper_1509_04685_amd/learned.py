@@ -257,7 +257,7 @@ def calibrate_schedule(net, cosmo, box, n_part, z_init, n_steps, seeds, knot_a, 
 
 def calibrate_green_filter(net, cosmo, box, n_part, z_init, n_steps, seeds, u_knots, a_outs=(1.0,), n_pk=None,
                            k_max=1.0, p_norms=(2, 2, 4, 4, 4, 6, 6, 6), h=0.04, smooth=0.1, n_fixed=1,
-                           seed_mean=False, log=None):
+                           seed_mean=False, mean_weight=0.0, log=None):
     """Trajectory-level calibration of the corrected step's Green's-function transfer T(u, a)
     together with the output-scale schedule, on training realizations.  Parameters: T at every
     (schedule knot a_i, u_j) beyond the first n_fixed knots and the schedule's knot values; T = 1 at
@@ -270,7 +270,8 @@ def calibrate_green_filter(net, cosmo, box, n_part, z_init, n_steps, seeds, u_kn
     penalty in u and in a (weight `smooth`) that keeps T smooth.  A step is taken when it lowers
     that p-norm; the parameters with the smallest worst |P / P_3x - 1| seen are kept.  seed_mean:
     the residuals are the errors averaged over the seeds bin by bin (the systematic part, which a
-    transfer can remove; each realization adds its own scatter of a few per mille near k_max).  Sets the filter and schedule on the network and returns (u_knots, rows, knot_v,
+    transfer can remove; each realization adds its own scatter of a few per mille near k_max);
+    mean_weight > 0: every seed's residuals and, appended with that weight, the seed-averaged ones.  Sets the filter and schedule on the network and returns (u_knots, rows, knot_v,
     worst error, history)."""
     n_pk = n_pk or n_part * 3
     n_bins = n_pk // 2
@@ -304,9 +305,12 @@ def calibrate_green_filter(net, cosmo, box, n_part, z_init, n_steps, seeds, u_kn
             for (k, p3), (_, pl) in zip(ref, got):
                 sel = (k > 0) & (k < k_max) & (p3 > 0)
                 out.append(pl[sel] / p3[sel] - 1.0)
+        per_seed = np.asarray(out).reshape(len(seeds), len(a_outs), -1)
         if seed_mean:
-            return np.mean(np.asarray(out).reshape(len(seeds), len(a_outs), -1), axis=0).ravel()
-        return np.concatenate(out)
+            return per_seed.mean(axis=0).ravel()
+        if mean_weight > 0.0:
+            return np.concatenate([per_seed.ravel(), mean_weight * per_seed.mean(axis=0).ravel()])
+        return per_seed.ravel()
 
     def pnorm(r, p):
         m = np.abs(r).max()
@@ -325,8 +329,16 @@ def calibrate_green_filter(net, cosmo, box, n_part, z_init, n_steps, seeds, u_kn
             e[(i - 1) * nu + j], e[i * nu + j], e[(i + 1) * nu + j] = 1.0, -2.0, 1.0
             rows_d.append(e)
     D = np.asarray(rows_d)
+    n_seed_res = None
+
+    def worst_of(rv):
+        # the worst error of the realizations themselves (not of the appended weighted means)
+        return float(np.abs(rv[:n_seed_res]).max()) if n_seed_res else float(np.abs(rv).max())
+
     r = resid(theta)
-    best_theta, best = theta.copy(), float(np.abs(r).max())
+    if mean_weight > 0.0 and not seed_mean:
+        n_seed_res = r.size * len(seeds) // (len(seeds) + 1)
+    best_theta, best = theta.copy(), worst_of(r)
     history = [(0, best)]
     if log:
         log(f"[green] start: worst {best:.4f}, rms {np.sqrt(np.mean(r ** 2)):.4f}")
@@ -347,7 +359,7 @@ def calibrate_green_filter(net, cosmo, box, n_part, z_init, n_steps, seeds, u_kn
             step = np.linalg.solve(A, -(JW.T @ r + smooth * (D.T @ (D @ theta))))
             trial = theta + step
             rt = resid(trial)
-            wt = float(np.abs(rt).max())
+            wt = worst_of(rt)
             if log:
                 log(f"[green] step {it} (p = {p_norm}) damping {mu:g}: worst {wt:.4f}, "
                     f"rms {np.sqrt(np.mean(rt ** 2)):.4f}")

@@ -106,7 +106,8 @@ def train(channels, recipe=RECIPE, log=print):
     return net, v0, v1, fitted, table
 
 
-def calibrate_filter_file(path, recipe=RECIPE, log=print, n_part=None, seeds=None, p_norms=None, seed_mean=False):
+def calibrate_filter_file(path, recipe=RECIPE, log=print, n_part=None, seeds=None, p_norms=None, seed_mean=False,
+                          mean_weight=0.0):
     """The Green's-function transfer of the corrected step (T at the schedule's knots in a and at
     FILTER_U in |k| / k_Nyquist), calibrated with the schedule by damped Gauss-Newton on the
     training seeds' trajectories (every output a), written into the weights file."""
@@ -123,12 +124,13 @@ def calibrate_filter_file(path, recipe=RECIPE, log=print, n_part=None, seeds=Non
     extra = {} if p_norms is None else {"p_norms": tuple(p_norms)}
     u, rows, knot_v, worst, hist = L.calibrate_green_filter(
         net, cosmo, box, n_part, r["z_init"], r["n_steps"], seeds, FILTER_U,
-        a_outs=r["calib_a"], n_fixed=FILTER_FIXED, seed_mean=seed_mean, log=log, **extra)
+        a_outs=r["calib_a"], n_fixed=FILTER_FIXED, seed_mean=seed_mean, mean_weight=mean_weight, log=log, **extra)
     log(f"[train_lc] Green's-function transfer calibrated: worst training-seed error {worst:.4f} "
         f"({time.time() - t0:.1f} s)")
     prev = doc.get("green_filter") or {}
     passes = prev.get("passes", []) if list(prev.get("u", [])) == list(u) else []
     passes.append({"seeds": list(seeds), "n_part": n_part, "box": box, "seed_mean": seed_mean,
+                   "mean_weight": mean_weight,
                    "worst_training_error": worst, "history": hist})
     doc["green_filter"] = {"u": u, "t": rows, "worst_training_error": worst, "a_outs": list(r["calib_a"]),
                            "passes": passes}
@@ -156,10 +158,13 @@ def main():
                     help="p of the p-norm of each calibration step (default 2 2 4 4 4 6 6 6)")
     ap.add_argument("--calib-seed-mean", action="store_true",
                     help="fit the errors averaged over the calibration seeds (their systematic part)")
+    ap.add_argument("--calib-mean-weight", type=float, default=0.0,
+                    help="also fit the seed-averaged errors, with this weight, beside every seed's")
     args = ap.parse_args()
     if args.calibrate_filter:
         calibrate_filter_file(args.calibrate_filter, log=lambda m: print(m, flush=True), n_part=args.calib_n_part,
-                              seeds=args.calib_seeds, p_norms=args.calib_p, seed_mean=args.calib_seed_mean)
+                              seeds=args.calib_seeds, p_norms=args.calib_p, seed_mean=args.calib_seed_mean,
+                              mean_weight=args.calib_mean_weight)
         return
     out = args.out or os.path.join(HERE, f"lc_weights_c{args.channels}.json")
     recipe = dict(RECIPE, iters=args.iters, onpolicy_rounds=args.onpolicy_rounds,
