@@ -141,7 +141,8 @@ __global__ void k_pk_bin_ell(const float2* spec, long bstride, int n, long plane
         int b = isqrt_floor(m2);
         if (b >= n_bins) continue;
         float2 d = spec[(long)kz * plane + rr];
-        float w1 = sinc_pi(mx * inv_n) * sinc_pi(my * inv_n) * sinc_pi(kz * inv_n);
+        // same product order as k_pk_bin (x and z first), so the real-space monopole is P(k)
+        float w1 = (sinc_pi(mx * inv_n) * sinc_pi(kz * inv_n)) * sinc_pi(my * inv_n);
         float w2 = w1 * w1;
         const double pw = (double)((d.x * d.x + d.y * d.y) / (w2 * w2));
         const int ml = los == 0 ? mx : (los == 1 ? my : kz);
