@@ -77,7 +77,9 @@ def algorithmic_bytes(kind, tag, n_g, n_part):
         "fft_y_split": 8 * C + 16 * C,          # one in, two out
         "fft_y_inverse": 16 * C,
         "fft_z_c2r": 8 * C + 4 * G,
-        "gather_kick_drift": 12 * G + 92 * N,   # 3 force meshes; x,p,psi1,psi2 in; x,p out; key +
+        "fft_z_c2r3": 24 * C + 12 * G,          # the three force spectra in; (F_x, F_y, F_z) out,
+                                                # interleaved (ghost cells and row padding not counted)
+        "gather_kick_drift": 12 * G + 92 * N,   # the force mesh; x,p,psi1,psi2 in; x,p out; key +
                                                 # record of the next deposit out (binning fused in)
         "gather_kick": 12 * G + 60 * N,
         "pk_deposit": 12 * G + 68 * N,          # binning with the partial drift: x, p, psi1, psi2 and
@@ -123,8 +125,10 @@ def node_index(table, a_out):
 
 KERNEL_SOURCES = {"fft": ("fft.hip", "fft_core.h", "fft_kernels.h", "fft_static_1536.hip", "fft_static_768.hip",
                           "fft_static_512.hip", "fft_static_384.hip", "fft_static_288.hip", "fft_static_256.hip"), "cic": ("deposit_sorted.hip",),
-                  "pk_deposit": ("deposit_sorted.hip",), "gather_kick_drift": ("deposit_sorted.hip", "pm_kernels.hip"),
-                  "gather": ("pm_kernels.hip",), "lc": ("lc_kernels.hip",), "pk_alias": ("pk_kernels.hip",)}
+                  "pk_deposit": ("deposit_sorted.hip", "force_gather.h"),
+                  "gather_kick_drift": ("deposit_sorted.hip", "pm_kernels.hip", "force_gather.h"),
+                  "gather": ("pm_kernels.hip", "force_gather.h"), "lc": ("lc_kernels.hip",),
+                  "pk_alias": ("pk_kernels.hip",)}
 
 
 def source_hash(kind):

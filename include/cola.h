@@ -325,7 +325,8 @@ int cola_autotune(const cola_problem* prob, int32_t n_pk, void* ws, size_t ws_by
 
 /* Pins the kernel shape of one FFT pass kind at mesh side n for the rest of the process, as the
  * autotuner would: kind one of "z_r2c", "z_c2r", "rows_y", "cols_x", "x_green", "y_split",
- * "x_mult"; values_per_thread and width (lines per block for the z passes and the y rows, a power
+ * "x_mult", "z_c2r3" (the step's z pass writing the three force components interleaved);
+ * values_per_thread and width (lines per block for the z passes and the y rows, a power
  * of two dividing n for the z passes; columns per tile for the x passes) must form an admissible
  * shape; use_static: 0 the plan built at run time, 1 the compile-time plan of that shape, 2 (x-column
  * kinds) the compile-time plan whose LDS exchanges move the real and then the imaginary parts
@@ -354,10 +355,10 @@ int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const c
 
 /* cola_pm_force for callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): the same passes and the same result, with
- * the workspace taken from a fixed 64 MiB device array that the library holds on each GPU until
+ * the workspace taken from a fixed 96 MiB device array that the library holds on each GPU until
  * the process ends, instead of a caller buffer.  The caller still passes the state and acc.
- * Problems whose cola_workspace_bytes(prob, 0) exceeds 64 MiB (for example 128^3 particles on a
- * 128^3 mesh; 64^3 particles on a 128^3 mesh need 49 MiB) return COLA_ERR_WORKSPACE_TOO_SMALL before
+ * Problems whose cola_workspace_bytes(prob, 0) exceeds 96 MiB (for example 128^3 particles on a
+ * 128^3 mesh, 128 MiB; 64^3 particles on a 128^3 mesh need 65 MiB) return COLA_ERR_WORKSPACE_TOO_SMALL before
  * any launch.  Every call on
  * one GPU shares that GPU's array: calls that overlap on one GPU (other streams, other threads)
  * race, and a state's cached force is never kept in it.  No hipMalloc, hipFree or other

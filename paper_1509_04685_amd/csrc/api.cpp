@@ -73,18 +73,21 @@ constexpr int kMaxMesh = 1536;  // keeps per-realization mesh offsets below 2^31
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace: four mesh buffers S, A, B, C (real fields or transposed spectra; the z passes are
-// out of place), two P(k) buffers K (the deposit) and K2 (its spectrum), the deposit's sort
-// buffers and the twiddle tables.  After a force evaluation F_x, F_y, F_z are in C, B, A.
+// Workspace: three mesh buffers S, A, B (real fields or transposed spectra; the z passes are
+// out of place), the interleaved force mesh F, two P(k) buffers K (the deposit) and K2 (its
+// spectrum), the deposit's sort buffers and the twiddle tables.  After a force evaluation F holds
+// (F_x, F_y, F_z) of every cell, interleaved (pm_force_interleaved).
 struct Layout {
     Mesh3 g;   // force mesh, N_g
     Mesh3 gp;  // Lagrangian lattice, N_p
     Mesh3 gk;  // P(k) mesh (n = 0 when absent)
-    long cstride = 0;  // float2 per realization in S, A, B, C
+    long cstride = 0;  // float2 per realization in S, A, B
+    long frow = 0;     // floats per row of F
+    long fstride = 0;  // floats per realization in F
     long kstride = 0;  // float2 per realization in K, K2
     TileGeom tg;  // force-mesh tiles of the deposit
     TileGeom tk;  // P(k)-mesh tiles
-    size_t off_s = 0, off_a = 0, off_b = 0, off_c = 0, off_k = 0, off_k2 = 0, off_twg = 0, off_twp = 0,
+    size_t off_s = 0, off_a = 0, off_b = 0, off_f = 0, off_k = 0, off_k2 = 0, off_twg = 0, off_twp = 0,
            off_twk = 0, off_sort = 0;
     size_t total = 0;
 };
@@ -99,7 +102,9 @@ Layout layout_of(const cola_problem& p, int n_pk) {
     L.off_s = off; off += cb;
     L.off_a = off; off += cb;
     L.off_b = off; off += cb;
-    L.off_c = off; off += cb;
+    L.frow = force_row3(L.g.n);
+    L.fstride = (long)L.g.n * L.g.n * L.frow;
+    L.off_f = off; off += align256((size_t)L.fstride * sizeof(float) * p.n_real);
     if (n_pk > 0) {
         L.gk = make_mesh(n_pk);
         L.kstride = L.gk.total_c();
@@ -171,7 +176,8 @@ ParticlePtrs ptrs_of(const cola_particles* P) {
 }
 
 struct Ws {
-    float2 *S, *A, *B, *C, *K, *K2, *twg, *twp, *twk;
+    float2 *S, *A, *B, *K, *K2, *twg, *twp, *twk;
+    float* F;
     void* sort;
 };
 
@@ -181,7 +187,7 @@ Ws carve(void* ws, const Layout& L) {
     w.S = reinterpret_cast<float2*>(b + L.off_s);
     w.A = reinterpret_cast<float2*>(b + L.off_a);
     w.B = reinterpret_cast<float2*>(b + L.off_b);
-    w.C = reinterpret_cast<float2*>(b + L.off_c);
+    w.F = reinterpret_cast<float*>(b + L.off_f);
     w.K = L.kstride ? reinterpret_cast<float2*>(b + L.off_k) : nullptr;
     w.K2 = L.kstride ? reinterpret_cast<float2*>(b + L.off_k2) : nullptr;
     w.twg = reinterpret_cast<float2*>(b + L.off_twg);
@@ -191,12 +197,20 @@ Ws carve(void* ws, const Layout& L) {
     return w;
 }
 
+// The force mesh's cells relative to the lattice, with the rows of the interleaved force mesh F
+// (force_geom) or of the density mesh in S (dens_geom).
 LatticeGeom force_geom(const cola_problem& p, const Layout& L) {
     LatticeGeom g;
     g.n_part = p.n_part;
     g.n_mesh = L.g.n;
     g.inv_h = (float)(L.g.n / p.box);
     g.qoff = 0.5f;
+    g.row = L.frow;
+    g.mesh_bstride = L.fstride;
+    return g;
+}
+LatticeGeom dens_geom(const cola_problem& p, const Layout& L) {
+    LatticeGeom g = force_geom(p, L);
     g.row = 2L * L.g.nzp;
     g.mesh_bstride = 2L * L.cstride;
     return g;
@@ -260,21 +274,21 @@ struct LcHook {
     }
 };
 
-// Density, forward transform and force meshes for the current positions.  Force meshes end up
-// as real rows in C (x), B (y), A (z); with a network hook, dF is added to them.  binned: the
-// particles were already binned for this deposit (gather_kick_drift_bin).
+// Density, forward transform and force mesh for the current positions: F ends up holding the
+// interleaved (F_x, F_y, F_z) rows; with a network hook, dF is added to it.  binned: the particles
+// were already binned for this deposit (gather_kick_drift_bin).
 hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, const ParticlePtrs& P,
                          hipStream_t st, const LcHook* lc = nullptr, double a_node = 1.0, bool binned = false) {
     const long npr = (long)p.n_part * p.n_part * p.n_part;
-    LatticeGeom fg = force_geom(p, L);
+    LatticeGeom dg = dens_geom(p, L);
     const double cells = (double)L.g.n * L.g.n * L.g.n;
     SortBufs sb = carve_sort(w.sort, npr, L.tg, p.n_real);
     KickDrift none{};
     float* dens = reinterpret_cast<float*>(w.S);
     const float dscale = (float)(cells / (double)npr);
-    hipError_t e = binned ? sorted_deposit_binned(npr, p.n_real, fg, L.tg, sb, dens, dscale, -1.0f, st)
-                          : sorted_deposit(P, npr, p.n_real, fg, false, fg, nullptr, nullptr, nullptr, none, L.tg, sb,
-                                           dens, dscale, -1.0f, st);
+    hipError_t e = binned ? sorted_deposit_binned(npr, p.n_real, dg, L.tg, sb, dens, dscale, -1.0f, st)
+                          : sorted_deposit(P, npr, p.n_real, dg, false, dg, nullptr, none, L.tg, sb, dens, dscale,
+                                           -1.0f, st);
     if (e != hipSuccess) return e;
     const long row = 2L * L.g.nzp, bs = 2L * L.cstride;
     if (lc)
@@ -287,26 +301,14 @@ hipError_t compute_force(const cola_problem& p, const Layout& L, const Ws& w, co
     if (e != hipSuccess) return e;
     GreenFilter gf;
     const bool filt = lc && lc->filter_at(a_node, gf);
-    e = pm_force_from_spectrum(w.A, w.B, w.S, w.C, L.cstride, L.g, w.twg, (float)(2.0 * M_PI / p.box), p.n_real,
-                               st, filt ? &gf : nullptr);
+    e = pm_force_interleaved(w.A, w.B, w.S, w.F, L.frow, L.fstride, L.cstride, L.g, w.twg,
+                             (float)(2.0 * M_PI / p.box), p.n_real, st, filt ? &gf : nullptr);
     if (e != hipSuccess || !lc) return e;
-    for (int r = 0; r < p.n_real; ++r) {
-        float* f[3] = {reinterpret_cast<float*>(w.C) + r * bs, reinterpret_cast<float*>(w.B) + r * bs,
-                       reinterpret_cast<float*>(w.A) + r * bs};
-        if ((e = lc_forward_fields(lc->P, lc->A.a1, lc->A.x0 + r * lc->x0_stride, f, row, L.g.n, lc->in_scale,
-                                   lc->scale_at(a_node), lc->out_band, lc->A.t, st)) != hipSuccess)
+    for (int r = 0; r < p.n_real; ++r)
+        if ((e = lc_forward_fields(lc->P, lc->A.a1, lc->A.x0 + r * lc->x0_stride, w.F + r * L.fstride, L.frow, L.g.n,
+                                   lc->in_scale, lc->scale_at(a_node), lc->out_band, lc->A.t, st)) != hipSuccess)
             return e;
-    }
-    float* f[3] = {reinterpret_cast<float*>(w.C), reinterpret_cast<float*>(w.B), reinterpret_cast<float*>(w.A)};
-    return mesh_ghosts(f, row, L.g.n, bs, p.n_real, st);  // the gathers read z pairs through the ghosts
-}
-
-struct ForceMeshes {
-    const float *fx, *fy, *fz;
-};
-ForceMeshes force_meshes(const Ws& w) {
-    return {reinterpret_cast<const float*>(w.C), reinterpret_cast<const float*>(w.B),
-            reinterpret_cast<const float*>(w.A)};
+    return mesh_ghosts(w.F, L.frow, L.g.n, L.fstride, p.n_real, st);  // the gathers read z pairs through the ghosts
 }
 
 // With the LPT frame switched off (PM only) the kick uses g alone and the drift p alone: the
@@ -338,8 +340,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     Schedule sc = make_schedule(p, *cosmo);
     const double c32 = 1.5 * sc.omega_m;
     const long npr = (long)p.n_part * p.n_part * p.n_part;
-    LatticeGeom fg = force_geom(p, L);
-    ForceMeshes f = force_meshes(w);
+    LatticeGeom fg = force_geom(p, L), dg = dens_geom(p, L);
 
     const void* net_id = lc ? lc->id : nullptr;
     (void)hipGetLastError();
@@ -362,7 +363,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
         kd.drift = (float)sc.drift[j];
         kd.dd1 = (float)(sc.d1[j + 1] - sc.d1[j]);
         kd.dd2 = (float)(sc.d2[j + 1] - sc.d2[j]);
-        COLA_TRY(gather_kick_drift_bin(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, frame_terms(kd, p), L.tg,
+        COLA_TRY(gather_kick_drift_bin(P, npr, p.n_real, fg, w.F, dg, frame_terms(kd, p), L.tg,
                                        carve_sort(w.sort, npr, L.tg, p.n_real), st));
         COLA_TRY(compute_force(p, L, w, P, st, lc, sc.a[j + 1], true));
         pending = sc.k_in[j];
@@ -371,7 +372,7 @@ int step_impl(const cola_problem* prob, const cola_cosmology* cosmo, int32_t j_b
     kd.kick = (float)(c32 * pending);
     kd.d1 = (float)sc.d1[j_end];
     kd.d2m = (float)(sc.d2[j_end] - sc.d1[j_end] * sc.d1[j_end]);
-    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, f.fx, f.fy, f.fz, frame_terms(kd, p), st));
+    COLA_TRY(gather_kick_drift(P, npr, p.n_real, fg, w.F, frame_terms(kd, p), st));
     io->node = j_end;
     io->force_node = j_end;
     io->force_ws = ws;
@@ -507,9 +508,8 @@ int cola_pm_force(const cola_problem* prob, const cola_particles* in, float* acc
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     COLA_TRY(compute_force(*prob, L, w, P, st));
-    ForceMeshes f = force_meshes(w);
     const long npr = (long)prob->n_part * prob->n_part * prob->n_part;
-    COLA_TRY(gather_force(P, npr, prob->n_real, force_geom(*prob, L), f.fx, f.fy, f.fz, acc, st));
+    COLA_TRY(gather_force(P, npr, prob->n_real, force_geom(*prob, L), w.F, acc, st));
     return COLA_OK;
 }
 
@@ -581,9 +581,8 @@ int cola_pm_force_lc(const cola_problem* prob, const cola_particles* in, const c
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
     COLA_TRY(compute_force(*prob, L, w, P, st, &h, a));
-    ForceMeshes f = force_meshes(w);
     const long npr = (long)prob->n_part * prob->n_part * prob->n_part;
-    COLA_TRY(gather_force(P, npr, prob->n_real, force_geom(*prob, L), f.fx, f.fy, f.fz, acc, st));
+    COLA_TRY(gather_force(P, npr, prob->n_real, force_geom(*prob, L), w.F, acc, st));
     return COLA_OK;
 }
 
@@ -620,7 +619,6 @@ int power_spectrum_impl(const cola_problem* prob, const cola_cosmology* cosmo, c
     ParticlePtrs P = ptrs_of(in);
     const long npr = (long)p.n_part * p.n_part * p.n_part;
     LatticeGeom fg = force_geom(p, L);
-    ForceMeshes f = force_meshes(w);
     KickDrift kd{};
     (void)hipGetLastError();
     COLA_TRY(launch_twiddles(w.twg, L.g.n, st));
@@ -654,8 +652,8 @@ int power_spectrum_impl(const cola_problem* prob, const cola_cosmology* cosmo, c
     dg.mesh_bstride = 2L * L.kstride;
     double cells = (double)n_pk * n_pk * n_pk;
     SortBufs sb = carve_sort(w.sort, npr, L.tk, p.n_real);
-    COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, !on_node, fg, f.fx, f.fy, f.fz, kd, L.tk, sb,
-                            reinterpret_cast<float*>(w.K), (float)(cells / (double)npr), -1.0f, st));
+    COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, !on_node, fg, w.F, kd, L.tk, sb, reinterpret_cast<float*>(w.K),
+                            (float)(cells / (double)npr), -1.0f, st));
     COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K2, L.kstride, gk, w.twk,
                        p.n_real, 1.0f, 0.0f, st));
     const long nb = (long)n_bins * p.n_real;
@@ -718,7 +716,6 @@ int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo,
     ParticlePtrs P = ptrs_of(in);
     const long npr = (long)p.n_part * p.n_part * p.n_part;
     LatticeGeom fg = force_geom(p, L);
-    ForceMeshes f = force_meshes(w);
     // Eq. 5, plane-parallel: s = x + v_los / (a H) along axis los, v = a dx/dt the peculiar
     // velocity.  With p = a^2 dx/dt (H0 = 1) the shift is p_los / (a^2 E(a)); in the COLA frame
     // p = p_res + a^3 E (dD1/da Psi1 + dD2/da Psi2), which adds a (dD1/da Psi1 + dD2/da Psi2).
@@ -743,7 +740,7 @@ int cola_power_multipoles(const cola_problem* prob, const cola_cosmology* cosmo,
     dg.mesh_bstride = 2L * L.kstride;
     double cells = (double)n_pk * n_pk * n_pk;
     SortBufs sb = carve_sort(w.sort, npr, L.tk, p.n_real);
-    COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, redshift_space != 0, fg, f.fx, f.fy, f.fz, kd, L.tk, sb,
+    COLA_TRY(sorted_deposit(P, npr, p.n_real, dg, redshift_space != 0, fg, w.F, kd, L.tk, sb,
                             reinterpret_cast<float*>(w.K), (float)(cells / (double)npr), -1.0f, st));
     COLA_TRY(fft3d_r2c(reinterpret_cast<const float*>(w.K), 2L * gk.nzp, 2L * L.kstride, w.K2, L.kstride, gk, w.twk,
                        p.n_real, 1.0f, 0.0f, st));

@@ -29,7 +29,7 @@ enum ProfKind {
     PROF_FILL = 0, PROF_DEPOSIT, PROF_Z_R2C, PROF_Y_FWD, PROF_X_FWD, PROF_X_GREEN, PROF_Y_SPLIT,
     PROF_Y_INV, PROF_Z_C2R, PROF_GKD, PROF_GATHER, PROF_IC, PROF_X_INV_MULT, PROF_PK, PROF_COPY,
     PROF_OTHER, PROF_KICK, PROF_PK_DEPOSIT, PROF_DEP_SORT, PROF_DEP_TILE, PROF_LC_CONV, PROF_LC_WGRAD, PROF_LC_MISC,
-    PROF_FOF, PROF_PK_ALIAS,
+    PROF_FOF, PROF_PK_ALIAS, PROF_Z_C2R3,
     PROF_NUM_KINDS
 };
 // Brackets one kernel launch with an event pair when the profiler is enabled.  tag: a size label
@@ -145,6 +145,14 @@ inline void green_slopes(GreenFilter& gf) {
 hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
                                   const float2* tw, float kf, int n_real, hipStream_t st,
                                   const GreenFilter* gf = nullptr);
+// The same passes, with the three z c2r passes fused into one that writes the force components
+// interleaved: F[(x n + y) frow + 3 z + c], c = 0, 1, 2 for x, y, z, z = 0 .. n + 1 (the ghost cells
+// z = n, n + 1 repeat z = 0, 1), frow = force_row3(n) floats per row, fstride floats between
+// realizations.  P, Q, R are overwritten; F must not overlap them.
+long force_row3(int n);
+hipError_t pm_force_interleaved(float2* P, float2* Q, float2* R, float* F, long frow, long fstride, long bstride,
+                                const Mesh3& g, const float2* tw, float kf, int n_real, hipStream_t st,
+                                const GreenFilter* gf = nullptr);
 // z r2c + y forward only (first half of the PM force transform), out of place
 hipError_t fft_zy_forward(const float* in, long in_row, long in_bstride, float2* out, long out_bstride,
                           const Mesh3& g, const float2* tw, int n_real, float pa, float pb,
@@ -177,7 +185,7 @@ struct LatticeGeom {
     int n_mesh;     // cells per side of this mesh
     float inv_h;    // n_mesh / L
     float qoff;     // lattice offset in this mesh's cells (0.5 * n_mesh / N_g)
-    long row;       // floats per mesh row
+    long row;       // floats per mesh row (force meshes: per row of interleaved (x, y, z) cells)
     long mesh_bstride;  // floats between realizations
 };
 
@@ -196,12 +204,12 @@ hipError_t launch_fill_d(double* p, long n, double v, hipStream_t st);
 hipError_t cic_deposit_absolute(const float* const pos[3], long n, int n_mesh, float inv_h, long row,
                                 float* mesh, hipStream_t st);
 hipError_t density_finish(float* mesh, long row, int n_mesh, float scale, float offset, hipStream_t st);
-hipError_t gather_kick_drift(const ParticlePtrs& P, long n_per_real, int n_real,
-                             const LatticeGeom& fgeom, const float* fx, const float* fy,
-                             const float* fz, const KickDrift& kd, hipStream_t st);
+// The gathers read the interleaved force mesh F of pm_force_interleaved (fgeom.row floats per
+// row, fgeom.mesh_bstride between realizations).
+hipError_t gather_kick_drift(const ParticlePtrs& P, long n_per_real, int n_real, const LatticeGeom& fgeom,
+                             const float* F, const KickDrift& kd, hipStream_t st);
 hipError_t gather_force(const ParticlePtrs& P, long n_per_real, int n_real, const LatticeGeom& fgeom,
-                        const float* fx, const float* fy, const float* fz, float* const acc[3],
-                        hipStream_t st);
+                        const float* F, float* const acc[3], hipStream_t st);
 
 // Exclusive scan of nkeys counts: start[k] = sum of count[0..k), start[nkeys] = total (the sum,
 // known to the caller), cursor = start.  block_sums holds ceil(nkeys / 1024) entries.
@@ -232,23 +240,24 @@ TileGeom make_tiles(int n, long n_particles);
 size_t sort_bytes(long n_particles_per_real, const TileGeom& tg, int n_real);
 SortBufs carve_sort(void* base, long npr, const TileGeom& tg, int n_real);
 // CIC deposit of every particle (drifted on the fly when `drift`, with the force gathered from
-// fgeom's meshes) onto a mesh of dg's geometry, written as delta = rho * scale + offset.
+// the interleaved force mesh F of geometry fg) onto a mesh of dg's geometry, written as
+// delta = rho * scale + offset.
 hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg, bool drift,
-                          const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
-                          const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
-                          float scale, float offset, hipStream_t st);
+                          const LatticeGeom& fg, const float* F, const KickDrift& kd, const TileGeom& tg,
+                          const SortBufs& sb, float* mesh, float scale, float offset, hipStream_t st);
 
 // The step's gather, kick and drift (as gather_kick_drift with a drift) fused with the binning of
 // the moved particles onto fg's mesh for the next force evaluation; sorted_deposit_binned then
-// finishes that deposit (sort and tile passes).  The force meshes' rows carry the ghost values.
-hipError_t gather_kick_drift_bin(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
-                                 const float* fy, const float* fz, const KickDrift& kd, const TileGeom& tg,
-                                 const SortBufs& sb, hipStream_t st);
+// finishes that deposit (sort and tile passes).  F: the interleaved force mesh, with the ghost
+// cells; dg: the geometry of the density mesh the particles are binned for.
+hipError_t gather_kick_drift_bin(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* F,
+                                 const LatticeGeom& dg, const KickDrift& kd, const TileGeom& tg, const SortBufs& sb,
+                                 hipStream_t st);
 hipError_t sorted_deposit_binned(long npr, int n_real, const LatticeGeom& dg, const TileGeom& tg, const SortBufs& sb,
                                  float* mesh, float scale, float offset, hipStream_t st);
-// Rewrites the ghost values (z = 0, 1 again at z = n, n + 1) of n_real batches of force meshes with
+// Rewrites the ghost cells (z = 0, 1 again at z = n, n + 1) of n_real interleaved force meshes with
 // `row` floats per row, after something other than the z c2r pass changed the meshes.
-hipError_t mesh_ghosts(float* const f[3], long row, int n, long bstride, int n_real, hipStream_t st);
+hipError_t mesh_ghosts(float* F, long row, int n, long bstride, int n_real, hipStream_t st);
 
 // The same deposit for absolute positions pos[3] (n floats each, wrapped into the mesh), one
 // realization, onto a mesh of n_mesh cells per side with rows of `row` floats.

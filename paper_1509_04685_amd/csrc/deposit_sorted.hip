@@ -16,6 +16,7 @@
 // fractions exactly as computed from the lattice index and displacement.
 
 #include "cola_internal.h"
+#include "force_gather.h"
 #include "wave_ops.h"
 
 namespace cola {
@@ -77,8 +78,6 @@ __device__ __forceinline__ void lagr_idx(uint32_t p, int n_part, int& i, int& j,
     l = (int)(r - jj * np);
 }
 
-__device__ __forceinline__ int wrapn(int m, int n) { return m + 1 == n ? 0 : m + 1; }
-
 // The per-particle key and record arrays are written once and read once, in particle order:
 // non-temporal, so that they do not evict mesh and count lines from L2 (the tile pass also
 // stores the mesh this way).
@@ -97,43 +96,6 @@ __device__ __forceinline__ float4 load_rec_stream(const float4* p) {
     return v;
 }
 
-// The two z corners of a mesh row as one 8-byte load: the force meshes' rows carry the values of
-// z = 0, 1 again at z = n, n + 1, so the pair (m, m + 1) never wraps.
-__device__ __forceinline__ float2 load_pair(const float* p) {
-    float2 v;
-    __builtin_memcpy(&v, p, sizeof(float2));
-    return v;
-}
-
-// CIC gather of three force meshes (rows with the ghost values) at one particle.
-__device__ __forceinline__ void gather3c(const float* fx, const float* fy, const float* fz, long row, int n,
-                                         const CellC* c, float g[3]) {
-    const int xs[2] = {c[0].m, wrapn(c[0].m, n)}, ys[2] = {c[1].m, wrapn(c[1].m, n)};
-    const float wx[2] = {1.0f - c[0].f, c[0].f}, wy[2] = {1.0f - c[1].f, c[1].f}, wz[2] = {1.0f - c[2].f, c[2].f};
-    float2 vx[4], vy[4], vz[4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {  // the twelve loads are issued together
-            const long r = ((long)xs[a] * n + ys[b]) * row + c[2].m;
-            vx[2 * a + b] = load_pair(fx + r);
-            vy[2 * a + b] = load_pair(fy + r);
-            vz[2 * a + b] = load_pair(fz + r);
-        }
-    g[0] = g[1] = g[2] = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const float wab = wx[a] * wy[b];
-            const float w0 = wab * wz[0], w1 = wab * wz[1];
-            const int q = 2 * a + b;
-            g[0] += w0 * vx[q].x + w1 * vx[q].y;
-            g[1] += w0 * vy[q].x + w1 * vy[q].y;
-            g[2] += w0 * vz[q].x + w1 * vz[q].y;
-        }
-}
-
 // Binning of the particles onto the mesh of dg (key and cell record per particle, counts per
 // key).  MODE 0: at their positions; 1: drifted on the fly (kick with the force gathered from fg's
 // meshes, then the drift of kd) without changing the state -- outputs between nodes and the
@@ -141,8 +103,7 @@ __device__ __forceinline__ void gather3c(const float* fx, const float* fy, const
 // binned at the new positions for the next force evaluation (dg = fg).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_dep_bin(ParticlePtrs P, long npr, LatticeGeom dg, TileGeom tg,
-                                                 LatticeGeom fg, const float* fx, const float* fy, const float* fz,
-                                                 KickDrift kd, SortBufs sb) {
+                                                 LatticeGeom fg, const float* F, KickDrift kd, SortBufs sb) {
     constexpr bool DRIFT = MODE != 0;
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -156,12 +117,17 @@ __global__ void __launch_bounds__(256) k_dep_bin(ParticlePtrs P, long npr, Latti
         float x[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) x[d] = __builtin_nontemporal_load(P.x[d] + gid);
+        // x is issued first: loads complete in order, so the gather, whose addresses need only x,
+        // waits for these three and not for the nine below
+        __builtin_amdgcn_sched_barrier(0);
         if (DRIFT) {
-            // the particle arrays are read before the force gather, so both are in flight together
-            float s1[3] = {0.0f, 0.0f, 0.0f}, s2[3] = {0.0f, 0.0f, 0.0f}, pv[3] = {0.0f, 0.0f, 0.0f};
+            // The particle arrays are read before the force gather, so both are in flight together.
+            // All nine are loaded without a branch: loads guarded per axis (by the line of sight)
+            // made the compiler wait for each axis's loads before issuing the next, which added a
+            // memory round trip to every wave.
+            float s1[3], s2[3], pv[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                if (kd.los >= 0 && d != kd.los) continue;
                 s1[d] = __builtin_nontemporal_load(P.psi1[d] + gid);
                 s2[d] = __builtin_nontemporal_load(P.psi2[d] + gid);
                 pv[d] = __builtin_nontemporal_load(P.p[d] + gid);
@@ -171,8 +137,8 @@ __global__ void __launch_bounds__(256) k_dep_bin(ParticlePtrs P, long npr, Latti
                 CellC c[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) c[d] = cell_c(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
-                const long mo = (long)r * fg.mesh_bstride;
-                gather3c(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c, g);
+                gather_interleaved(F + (long)r * fg.mesh_bstride, fg.row, fg.n_mesh, c[0].m, c[1].m, c[2].m, c[0].f,
+                                   c[1].f, c[2].f, g);
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -525,34 +491,33 @@ hipError_t sorted_deposit_absolute(const float* const pos[3], long n, int n_mesh
 }
 
 hipError_t sorted_deposit(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& dg, bool drift,
-                          const LatticeGeom& fg, const float* fx, const float* fy, const float* fz,
-                          const KickDrift& kd, const TileGeom& tg, const SortBufs& sb, float* mesh,
-                          float scale, float offset, hipStream_t st) {
+                          const LatticeGeom& fg, const float* F, const KickDrift& kd, const TileGeom& tg,
+                          const SortBufs& sb, float* mesh, float scale, float offset, hipStream_t st) {
     const dim3 pgrid((unsigned)((npr + 255) / 256), n_real);
     hipError_t e = launch_fill(reinterpret_cast<float*>(sb.count), sb.kstride * n_real, 0.0f, st);
     if (e != hipSuccess) return e;
     {
         ProfScope ps(drift ? PROF_PK_DEPOSIT : PROF_DEPOSIT, st);
         if (drift)
-            hipLaunchKernelGGL(k_dep_bin<1>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
+            hipLaunchKernelGGL(k_dep_bin<1>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, F, kd, sb);
         else
-            hipLaunchKernelGGL(k_dep_bin<0>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, fx, fy, fz, kd, sb);
+            hipLaunchKernelGGL(k_dep_bin<0>, pgrid, dim3(256), 0, st, P, npr, dg, tg, fg, F, kd, sb);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return sort_and_tile(npr, n_real, tg, sb, mesh, dg.row, dg.mesh_bstride, scale, offset, st);
 }
 
-hipError_t gather_kick_drift_bin(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
-                                 const float* fy, const float* fz, const KickDrift& kd, const TileGeom& tg,
-                                 const SortBufs& sb, hipStream_t st) {
+hipError_t gather_kick_drift_bin(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* F,
+                                 const LatticeGeom& dg, const KickDrift& kd, const TileGeom& tg, const SortBufs& sb,
+                                 hipStream_t st) {
     hipError_t e = launch_fill(reinterpret_cast<float*>(sb.count), sb.kstride * n_real, 0.0f, st);
     if (e != hipSuccess) return e;
     KickDrift k = kd;
     k.los = -1;
     ProfScope ps(PROF_GKD, st);
-    hipLaunchKernelGGL(k_dep_bin<2>, dim3((unsigned)((npr + 255) / 256), n_real), dim3(256), 0, st, P, npr, fg, tg,
-                       fg, fx, fy, fz, k, sb);
+    hipLaunchKernelGGL(k_dep_bin<2>, dim3((unsigned)((npr + 255) / 256), n_real), dim3(256), 0, st, P, npr, dg, tg,
+                       fg, F, k, sb);
     return hipGetLastError();
 }
 

@@ -130,9 +130,9 @@ struct FftShape {
     bool split = false;
 };
 
-enum FftKind { FK_Z_R2C = 0, FK_Z_C2R, FK_ROWS_Y, FK_COLS_X, FK_X_GREEN, FK_Y_SPLIT, FK_X_MULT, FK_NUM };
+enum FftKind { FK_Z_R2C = 0, FK_Z_C2R, FK_ROWS_Y, FK_COLS_X, FK_X_GREEN, FK_Y_SPLIT, FK_X_MULT, FK_Z_C2R3, FK_NUM };
 static const char* const kFftKindName[FK_NUM] = {"z_r2c", "z_c2r", "rows_y", "cols_x", "x_green",
-                                                 "y_split", "x_mult"};
+                                                 "y_split", "x_mult", "z_c2r3"};
 
 static bool plan_ok(int n, int R) {
     if (R < 2 || n % R) return false;
@@ -168,7 +168,7 @@ static std::vector<int> valid_rs(int n) {
     return out;
 }
 
-static bool is_z(FftKind k) { return k == FK_Z_R2C || k == FK_Z_C2R; }
+static bool is_z(FftKind k) { return k == FK_Z_R2C || k == FK_Z_C2R || k == FK_Z_C2R3; }
 static bool is_rows(FftKind k) { return k == FK_ROWS_Y || k == FK_Y_SPLIT; }
 
 // Line length the kernel transforms: n/2 for the z passes, n otherwise.
@@ -178,6 +178,7 @@ static FftOp op_of(FftKind k) {
     switch (k) {
         case FK_Z_R2C: return OP_Z_R2C;
         case FK_Z_C2R: return OP_Z_C2R;
+        case FK_Z_C2R3: return OP_Z_C2R3;
         case FK_ROWS_Y: return OP_ROWS_FWD;
         case FK_COLS_X: return OP_COLS_FWD;
         case FK_X_GREEN: return OP_X_GREEN;
@@ -213,9 +214,14 @@ static bool static_available(FftKind k, int n, int R, int width, bool split = fa
     return launch_static(L, n) == hipSuccess;
 }
 
+// Threads per block: z_c2r3 runs one group of lines per force component.
+static long shape_threads(FftKind k, int n, const FftShape& sh) {
+    return (long)sh.width * (line_len(k, n) / sh.R) * (k == FK_Z_C2R3 ? 3 : 1);
+}
+
 static size_t shape_lds(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
-    if (is_z(k)) return (size_t)sh.width * (L + 1) * sizeof(float2);
+    if (is_z(k)) return (size_t)sh.width * (L + 1) * sizeof(float2) * (k == FK_Z_C2R3 ? 3 : 1);
     return (size_t)sh.width * L * (sh.split ? sizeof(float) : sizeof(float2));
 }
 
@@ -231,10 +237,12 @@ static bool shape_ok(FftKind k, int n, const FftShape& sh) {
     if (sh.split && (!sh.stat || !is_cols(k))) return false;
     // z passes: a power-of-two number of lines of one x plane per block
     if (is_z(k) && (log2_exact(sh.width) < 0 || n % sh.width)) return false;
-    long threads = (long)sh.width * (L / sh.R);
-    // 1024-thread blocks only for the static x-column plans with split exchanges (compiled for them)
-    if (threads > (sh.split ? 1024 : 512) || threads < 1) return false;
-    return shape_lds(k, n, sh) <= 128 * 1024;
+    long threads = shape_threads(k, n, sh);
+    // 1024-thread blocks only for the kernels compiled for them: the static x-column plans with
+    // split exchanges and z_c2r3
+    if (threads > ((sh.split || k == FK_Z_C2R3) ? 1024 : 512) || threads < 1) return false;
+    // z_c2r3 may take up to 150 KB: with 16 lines of 768 points its three groups need 148 KB
+    return shape_lds(k, n, sh) <= (k == FK_Z_C2R3 ? 150 : 128) * 1024;
 }
 
 static FftShape default_shape(FftKind k, int n) {
@@ -249,6 +257,7 @@ static FftShape default_shape(FftKind k, int n) {
             int w = 1;  // the largest power of two <= width that divides n
             while (w * 2 <= sh.width && n % (w * 2) == 0) w *= 2;
             sh.width = w;
+            while (sh.width > 1 && !shape_ok(k, n, sh)) sh.width /= 2;  // z_c2r3: three groups
         }
     } else {
         sh.width = pick_tk(n, pl.T);
@@ -329,6 +338,7 @@ static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
             case OP_Z_R2C: err = go_z_r2c<D>(L, e); break;
             case OP_Z_C2R: err = go_z_c2r<D, false>(L, e); break;
             case OP_Z_C2R_IKZ: err = go_z_c2r<D, true>(L, e); break;
+            case OP_Z_C2R3: err = go_z_c2r3<D>(L, e); break;
             case OP_ROWS_FWD: err = go_rows<D, 0>(L, e); break;
             case OP_ROWS_INV: err = go_rows<D, 1>(L, e); break;
             case OP_ROWS_SPLIT: err = go_rows<D, 2>(L, e); break;
@@ -458,6 +468,36 @@ static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long 
                                 shape_for(FK_Z_C2R, g.n), st);
 }
 
+// The three force components into one interleaved mesh (k_fft_z_c2r3); `lines` rows (x, y) from
+// the first (all n^2 of them in the step; fewer when the autotuner times it on a scratch buffer).
+static hipError_t run_z_c2r3_shape(const float2* fx, const float2* fy, const float2* fz, long in_bstride, float* out,
+                                   long out_row, long out_bstride, const Mesh3& g, const float2* tw, int n_real,
+                                   float kf, const FftShape& sh, hipStream_t st, long lines = -1) {
+    FftLaunch L;
+    L.op = OP_Z_C2R3;
+    const int lpb = sh.width;
+    if (lines < 0) lines = (long)g.n * g.n;
+    L.lds = shape_lds(FK_Z_C2R3, g.n, sh);
+    L.grid = dim3((unsigned)(lines / lpb), n_real);
+    L.block = dim3((unsigned)shape_threads(FK_Z_C2R3, g.n, sh));
+    L.st = st;
+    L.cin = fx;
+    L.cin1 = fy;
+    L.cin2 = fz;
+    L.in_bstride = in_bstride;
+    L.rout = out;
+    L.out_row = out_row;
+    L.out_bstride = out_bstride;
+    L.mesh_n = g.n;
+    L.plane = g.plane;
+    L.lw = log2_exact(lpb);
+    L.tw = tw;
+    L.kf = kf;
+    L.scale = 1.0f;
+    ProfScope ps(PROF_Z_C2R3, st, g.n);
+    return launch_shape(L, g.n, sh);
+}
+
 static hipError_t run_x_green_shape(float2* S, float2* A, float2* B, long bstride, const Mesh3& g,
                                     const float2* tw, float kf, int n_real, const FftShape& sh, hipStream_t st,
                                     const GreenFilter* gf = nullptr) {
@@ -519,13 +559,30 @@ hipError_t fft3d_r2c(const float* in, long in_row, long in_bstride, float2* out,
     return run_cols_shape(out, out_bstride, g, tw, n_real, shape_for(FK_COLS_X, g.n), st);
 }
 
-hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
-                                  const float2* tw, float kf, int n_real, hipStream_t st, const GreenFilter* gf) {
+// x and y passes of the force: x_green (P -> P, Q), y split (P -> P: i k_y, R: plain), y inverse
+// of Q; left in the transposed spectrum: F_x in Q, F_y in P, F_z (before i k_z) in R.
+static hipError_t force_xy_passes(float2* P, float2* Q, float2* R, long bstride, const Mesh3& g, const float2* tw,
+                                  float kf, int n_real, hipStream_t st, const GreenFilter* gf) {
     hipError_t e = run_x_green_shape(P, P, Q, bstride, g, tw, kf, n_real, shape_for(FK_X_GREEN, g.n), st, gf);
     if (e != hipSuccess) return e;
     e = run_rows(OP_ROWS_SPLIT, P, R, bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;
-    e = run_rows(OP_ROWS_INV, Q, nullptr, bstride, g, tw, kf, n_real, st);
+    return run_rows(OP_ROWS_INV, Q, nullptr, bstride, g, tw, kf, n_real, st);
+}
+
+long force_row3(int n) { return (3L * (n + 2) + 31) / 32 * 32; }
+
+hipError_t pm_force_interleaved(float2* P, float2* Q, float2* R, float* F, long frow, long fstride, long bstride,
+                                const Mesh3& g, const float2* tw, float kf, int n_real, hipStream_t st,
+                                const GreenFilter* gf) {
+    hipError_t e = force_xy_passes(P, Q, R, bstride, g, tw, kf, n_real, st, gf);
+    if (e != hipSuccess) return e;
+    return run_z_c2r3_shape(Q, P, R, bstride, F, frow, fstride, g, tw, n_real, kf, shape_for(FK_Z_C2R3, g.n), st);
+}
+
+hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
+                                  const float2* tw, float kf, int n_real, hipStream_t st, const GreenFilter* gf) {
+    hipError_t e = force_xy_passes(P, Q, R, bstride, g, tw, kf, n_real, st, gf);
     if (e != hipSuccess) return e;
     const long rowf = 2L * g.nzp;
     e = run_z_c2r<false>(Q, bstride, reinterpret_cast<float*>(T), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
@@ -561,11 +618,16 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
     for (int k = 0; k < FK_NUM && status == hipSuccess; ++k) {
         FftKind kind = (FftKind)k;
         int L = line_len(kind, n);
+        // z_c2r3 is timed on as many rows as its interleaved output fits in one scratch buffer
+        auto z3_rows = [&](int w) {
+            return std::min((long)n * n, 2L * g.total_c() / force_row3(n)) / w * w;
+        };
         std::vector<FftShape> cands;
         for (int R : valid_rs(L))
             for (int w : {1, 2, 4, 8, 16, 32, 64}) {
                 const long threads = (long)w * (L / R);
                 if (threads < 64 && w < 64) continue;
+                if (kind == FK_Z_C2R3 && z3_rows(w) < w) continue;
                 const FftShape sp{R, w, true, true};
                 if (shape_ok(kind, n, sp) && static_available(kind, n, R, w, true)) cands.push_back(sp);
                 FftShape sh{R, w, false};
@@ -587,6 +649,9 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
                 case FK_X_GREEN: return run_x_green_shape(S, S, A, 0, g, tw, kf, 1, sh, st);
                 case FK_Y_SPLIT: return run_rows_shape(OP_ROWS_SPLIT, A, S, 0, g, tw, kf, 1, sh, st);
                 case FK_X_MULT: return run_x_mult_shape(S, 0, A, 0, g, tw, 1, MUL_IK, 0, 0, kf, 1.0f, sh, st);
+                case FK_Z_C2R3:
+                    return run_z_c2r3_shape(S, S, S, 0, reinterpret_cast<float*>(A), force_row3(n), 0, g, tw, 1, kf,
+                                            sh, st, z3_rows(sh.width));
                 default: return hipErrorInvalidValue;
             }
         };

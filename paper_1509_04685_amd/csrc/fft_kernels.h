@@ -245,6 +245,92 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bst
     });
 }
 
+// The three force components in one pass, written interleaved: the block's threads form three
+// groups of W lines each; group c inverts, as the kernel above does for one spectrum, the spectrum
+// of F_x (c = 0: in0), F_y (in1) or F_z (in2, multiplied by i k_z) of the rows (x, y0 .. y0 + W - 1),
+// each group in its own LDS area.  Those areas together hold W rows of 3 (n + 2) floats, so after
+// the transforms the same LDS is the staging area of the interleaved rows
+//   out[(x n + y) out_row + 3 z + c],  z = 0 .. n + 1 (z = n, n + 1 repeat z = 0, 1),
+// which the whole block then writes with contiguous stores.  A CIC gather finds the three
+// components of a cell pair (z, z + 1) in 24 contiguous bytes instead of three lines of separate
+// meshes.
+template <class LE>
+__global__ void __launch_bounds__(1024) k_fft_z_c2r3(const float2* in0, const float2* in1, const float2* in2,
+                                                     long in_bstride, float* out, long out_row, long out_bstride,
+                                                     int n, long plane, int lw, LE eng, const float2* tw, float kf,
+                                                     float scale) {
+    constexpr int R = LE::kR;
+    constexpr int TW = z_tw_entries<LE>();
+    extern __shared__ float2 lds[];
+    const int T = eng.T(), M = eng.n();
+    const int W = 1 << lw;
+    const int gs = W * T;  // threads per group
+    const int comp = threadIdx.x / gs, lt = threadIdx.x - comp * gs;
+    const int line = lt / T, t = lt % T;
+    // blocks of neighbouring lines meet in one XCD's L2: with W < 16 they share the 128-byte lines
+    // of every kz plane
+    const long first = (long)xcd_block() * W;
+    const int x = (int)(first / n), y0 = (int)(first - (long)x * n);
+    float2* const Lb = lds + TW;
+    float2* const Lg = Lb + (long)comp * W * (M + 1);  // this group's lines
+    const float2* twl = stage_twiddles<TW>(tw, lds);  // visible after the barrier below
+    {
+        const float2* src = (comp == 0 ? in0 : (comp == 1 ? in1 : in2)) + (long)blockIdx.y * in_bstride +
+                            (long)x * n + y0;
+        const uint32_t pl = (uint32_t)plane;
+        float2 xv[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {  // k plane + j < (n/2 + 1) plane < 2^31
+            const uint32_t o = lt + u * gs;
+            xv[u] = load_stream(src + ((o >> lw) * pl + (o & (W - 1))));
+        }
+        const float2 xm = lt < W ? load_stream(src + (long)M * plane + lt) : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int o = lt + u * gs;
+            const int k = o >> lw, j = o & (W - 1);
+            float2 y = xv[u];
+            if (comp == 2) {
+                const float kz = kf * (float)k;
+                y = make_float2(-kz * y.y, kz * y.x);
+            }
+            Lg[j * (M + 1) + k] = cscale(y, scale);
+        }
+        if (lt < W)  // kz Nyquist plane (0 for the i k_z component)
+            Lg[lt * (M + 1) + M] = comp == 2 ? make_float2(0.0f, 0.0f) : cscale(xm, scale);
+    }
+    __syncthreads();
+    float2* L = Lg + line * (M + 1);
+    float2 v[R];
+    eng.first(t, [&](int q, int k) {
+        float2 xk = L[k];
+        float2 xc = cconj(L[M - k]);
+        float2 d = cmul(cconj(twl[k]), csub(xk, xc));
+        v[q] = make_float2(xk.x + xc.x - d.y, xk.y + xc.y + d.x);  // (xk + xc) + i d
+    });
+    __syncthreads();
+    eng.template run<true>(v, L, t, twl, true);
+    __syncthreads();  // every group's transform is done: the LDS becomes the staging rows
+    const int rs = 3 * (2 * M + 2);  // floats per staged row: n + 2 cells of three components
+    float* const S = reinterpret_cast<float*>(Lb);
+    float* const Sl = S + line * rs + comp;
+    eng.last(t, [&](int q, int e) {  // v[q]: cells 2e and 2e + 1 of this component
+        Sl[6 * e] = v[q].x;
+        Sl[6 * e + 3] = v[q].y;
+        if (e == 0) {
+            Sl[6 * M] = v[q].x;
+            Sl[6 * M + 3] = v[q].y;
+        }
+    });
+    __syncthreads();
+    float* dst = out + (long)blockIdx.y * out_bstride + first * out_row;
+    const int half = rs / 2;  // float2 per staged row (rs is even)
+    for (int i = threadIdx.x; i < W * half; i += blockDim.x) {
+        const int j = i / half, h = i - j * half;
+        store_stream(reinterpret_cast<float2*>(dst + j * out_row) + h, reinterpret_cast<const float2*>(S + j * rs)[h]);
+    }
+}
+
 // ------------------------------------------------------------------ y rows
 
 // Complex rows of n contiguous values (the rows (kz, x) of the transposed spectrum), transformed
@@ -438,12 +524,12 @@ __global__ void __launch_bounds__((col_bound<LE, TK>())) k_fft_x_mult(const floa
 // ------------------------------------------------------------------ launches
 
 enum FftOp {
-    OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ,          // z passes (line length n/2)
-    OP_ROWS_FWD, OP_ROWS_INV, OP_ROWS_SPLIT,       // y rows
-    OP_COLS_FWD, OP_X_GREEN, OP_X_MULT,            // x columns
-    OP_X_GREEN_FILT                                // x_green with a Green's-function filter
+    OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ, OP_Z_C2R3,  // z passes (line length n/2)
+    OP_ROWS_FWD, OP_ROWS_INV, OP_ROWS_SPLIT,          // y rows
+    OP_COLS_FWD, OP_X_GREEN, OP_X_MULT,               // x columns
+    OP_X_GREEN_FILT                                   // x_green with a Green's-function filter
 };
-inline bool is_z_op(FftOp op) { return op <= OP_Z_C2R_IKZ; }
+inline bool is_z_op(FftOp op) { return op <= OP_Z_C2R3; }
 inline bool is_rows_op(FftOp op) { return op >= OP_ROWS_FWD && op <= OP_ROWS_SPLIT; }
 
 // Everything one pass launch needs; each op reads its own subset.
@@ -461,6 +547,8 @@ struct FftLaunch {
     const float* rin = nullptr;
     float* rout = nullptr;
     const float2* cin = nullptr;
+    const float2* cin1 = nullptr;  // z_c2r3: the F_y and F_z spectra (cin: F_x)
+    const float2* cin2 = nullptr;
     float2* cout = nullptr;
     long in_row = 0, in_bstride = 0, out_row = 0, out_bstride = 0;
     long plane = 0;  // kz-plane stride of the transposed spectrum (z passes, y rows)
@@ -504,6 +592,16 @@ inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
     hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.in_bstride, L.rout, L.out_row, L.out_bstride,
                        L.mesh_n, L.plane, L.lw, L.ghost, e, L.tw, L.kf, L.scale);
+    return hipGetLastError();
+}
+
+template <class LE>
+inline hipError_t go_z_c2r3(const FftLaunch& L, LE e) {
+    auto kern = k_fft_z_c2r3<LE>;
+    const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
+    if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.cin1, L.cin2, L.in_bstride, L.rout, L.out_row,
+                       L.out_bstride, L.mesh_n, L.plane, L.lw, e, L.tw, L.kf, L.scale);
     return hipGetLastError();
 }
 
@@ -581,6 +679,7 @@ inline hipError_t static_z_ops(const FftLaunch& L) {
         case OP_Z_R2C: return go_z_r2c<E>(L, E{});
         case OP_Z_C2R: return go_z_c2r<E, false>(L, E{});
         case OP_Z_C2R_IKZ: return go_z_c2r<E, true>(L, E{});
+        case OP_Z_C2R3: return go_z_c2r3<E>(L, E{});
         default: return hipErrorNotSupported;
     }
 }

@@ -62,11 +62,12 @@ hipError_t lc_pack_weights(const float* w1, const float* w2, int C, uint16_t* wb
 hipError_t lc_pack(const float* delta, const float* const g[3], long row, int n, const float in_scale[4],
                    uint16_t* x0, hipStream_t st);
 // The step's input path: delta * s0 saved as compact BF16 (d0, n^3 values) before the transform
-// overwrites the density; later the network reads d0 and the force meshes directly and adds dF
-// to the force meshes (a1: [n^3][C] BF16 scratch).
+// overwrites the density; later the network reads d0 and the force mesh directly and adds dF to
+// it.  F: the step's interleaved force mesh (component c of cell z of a row at 3 z + c, `row`
+// floats per row); a1: [n^3][C] BF16 scratch.
 hipError_t lc_pack_delta(const float* delta, long row, int n, float s0, uint16_t* d0, hipStream_t st);
 // band != 0: dF goes through t ([3][n^3] scratch) and the band-pass weight (lc_band).
-hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row, int n,
+hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* F, long row, int n,
                              const float in_scale[4], float out_scale, float band, float* t, hipStream_t st);
 // dF (times out_scale, then through the band-pass weight) written to, or added into, three meshes
 // with `row` floats per row.  keep_z stores z1, z2 for the backward pass.
@@ -76,9 +77,10 @@ hipError_t lc_forward(const LcParams& P, const LcActs& A, int n, float out_scale
 hipError_t lc_backward(const LcParams& P, const LcActs& A, LcGrads& G, int n, float out_scale, float band,
                        const float* ddf, hipStream_t st);
 // out[c] (+)= T[c] + beta (K T[c] - K K T[c]), K the periodic [1, 2, 1] / 4 smoothing per axis;
-// T dense [3][n^3] (n a multiple of 16), out with `row` floats per row; T and out must not overlap.
+// T dense [3][n^3] (n a multiple of 16), out with `row` floats per row and cell z of a row at zs z;
+// T and out must not overlap.
 hipError_t lc_band(const float* T, int n, float beta, float* const out[3], long row, int accumulate,
-                   hipStream_t st);
+                   hipStream_t st, int zs = 1);
 // Particle loss (stats[0] = L, stats[1] = denominator; zeroed here) and d_df = dL/d(dF) (overwritten).
 hipError_t lc_loss(const float* const pos[3], long np, int n, double box, const float* const df[3],
                    const float* const g1[3], const float* const g3[3], double* stats, float* ddf,

@@ -94,21 +94,24 @@ __device__ __forceinline__ int wrap_halo(int i, int n) { return i < 0 ? i + n : 
 enum { EPI_ZA = 0, EPI_A = 1, EPI_DSILU = 2, EPI_OUT = 3, EPI_OUT_STORE = 4 };
 
 // Inputs of the first layer taken straight from the step's fields (instead of a packed X0):
-// delta as BF16 (already scaled) and the three force meshes with `row` floats per row.
+// delta as BF16 (already scaled) and the three force meshes with `row` floats per row and cell z
+// of a row at zs z (zs = 3 for the interleaved force mesh, whose g[c] point at component c).
 struct FieldSrc {
     const uint16_t* d0;
     const float* g[3];
     long row;
     float s[3];
+    int zs = 1;
 };
 // The output layer fused into the second convolution: dF = (W3 silu(Z2) + b3) * scale added to
-// three meshes with `row` floats per row.
+// three meshes with `row` floats per row and cell z at zs z.
 struct OutDst {
     float* f[3];
     long row;
     const float* w3;
     const float* b3;
     float scale;
+    int zs = 1;
 };
 
 // out[v][co] = sum_tap sum_ci W[co][tap][ci] in[v + d_tap][ci] + bias[co], then
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
                 if constexpr (FIELDS) {
                     static_assert(C8 == 1, "field input has 4 channels (padded to 8)");
                     const long v = ((long)gx * n + gy) * n + gz;
-                    const long o = ((long)gx * n + gy) * fs.row + gz;
+                    const long o = ((long)gx * n + gy) * fs.row + (long)gz * fs.zs;
                     // a channel with a zero input scale is not read (a density-only network)
                     const float g0 = fs.s[0] != 0.0f ? fs.g[0][o] * fs.s[0] : 0.0f;
                     const float g1 = fs.s[1] != 0.0f ? fs.g[1][o] * fs.s[1] : 0.0f;
@@ -227,7 +230,7 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
                 y2 += od.w3[2 * COP + co] * a;
             }
             const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
-            const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + z0 + lz;
+            const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + (long)(z0 + lz) * od.zs;
             if constexpr (EPI == EPI_OUT_STORE) {
                 od.f[0][o] = y0 * od.scale;
                 od.f[1][o] = y1 * od.scale;
@@ -357,7 +360,8 @@ static hipError_t run_conv(const uint16_t* in, const uint16_t* w, const float* b
 // ------------------------------------------------------------------ band-pass output weight
 
 // out[c] (+)= T[c] + beta (K T[c] - K K T[c]), K the periodic [1, 2, 1] / 4 smoothing along each
-// axis; T dense [3][n^3], out with `row` floats per (x, y) row.  One block per 8 x 8 x 16 tile:
+// axis; T dense [3][n^3], out with `row` floats per (x, y) row and cell z at zs z.  One block per
+// 8 x 8 x 16 tile:
 // T with a halo of two cells goes to LDS, K is applied as three axis passes (giving K T on the
 // tile plus one cell), then three more (K K T on the tile); the passes ping-pong between two
 // LDS buffers.
@@ -367,7 +371,7 @@ constexpr int BH = (BX + 4) * (BY + 4) * (BZ + 4);
 __device__ __forceinline__ float k121(float a, float b, float c) { return 0.25f * a + 0.5f * b + 0.25f * c; }
 
 __global__ void __launch_bounds__(256) k_lc_band(const float* __restrict__ T, int n, float beta, float* o0, float* o1,
-                                                 float* o2, long row, int accumulate) {
+                                                 float* o2, long row, int zs, int accumulate) {
     __shared__ float bufa[BH], bufb[BH];
     const int tid = threadIdx.x;
     const int ntz = n / BZ, nty = n / BY;
@@ -441,7 +445,7 @@ __global__ void __launch_bounds__(256) k_lc_band(const float* __restrict__ T, in
             const float* h = bufb + (lx * BY + ly) * BZ + lz;
             const float kkt = k121(h[0], h[BY * BZ], h[2 * BY * BZ]);
             const float val = tc[j] + beta * (kt[j] - kkt);
-            const long o = ((long)(x0 + lx) * n + (y0 + ly)) * row + z0 + lz;
+            const long o = ((long)(x0 + lx) * n + (y0 + ly)) * row + (long)(z0 + lz) * zs;
             if (accumulate) dst[o] += val;
             else dst[o] = val;
         }
@@ -450,11 +454,11 @@ __global__ void __launch_bounds__(256) k_lc_band(const float* __restrict__ T, in
 }
 
 hipError_t lc_band(const float* T, int n, float beta, float* const out[3], long row, int accumulate,
-                   hipStream_t st) {
+                   hipStream_t st, int zs) {
     ProfScope ps(PROF_LC_MISC, st);
     const long tiles = (long)(n / BX) * (n / BY) * (n / BZ);
     hipLaunchKernelGGL(k_lc_band, dim3((unsigned)tiles), dim3(256), 0, st, T, n, beta, out[0], out[1], out[2], row,
-                       accumulate);
+                       zs, accumulate);
     return hipGetLastError();
 }
 
@@ -926,11 +930,11 @@ static hipError_t forward_c(const LcParams& P, const LcActs& A, int n, float out
 }
 
 template <int C>
-static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row,
-                                   int n, const float in_scale[4], float out_scale, float band, float* t,
-                                   hipStream_t st) {
+static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* F, long row, int n,
+                                   const float in_scale[4], float out_scale, float band, float* t, hipStream_t st) {
     constexpr int NB = C / 16;
-    FieldSrc fs{d0, {g[0], g[1], g[2]}, row, {in_scale[1], in_scale[2], in_scale[3]}};
+    float* const g[3] = {F, F + 1, F + 2};  // the interleaved force mesh: component c at 3 z + c
+    FieldSrc fs{d0, {g[0], g[1], g[2]}, row, {in_scale[1], in_scale[2], in_scale[3]}, 3};
     const bool dens_only = in_scale[1] == 0.0f && in_scale[2] == 0.0f && in_scale[3] == 0.0f;
     hipError_t e = dens_only ? run_conv_dens<NB>(d0, P.wb1, P.b1, a1, n, st)
                              : run_conv<8, NB, EPI_A, true>(nullptr, P.wb1, P.b1, a1, nullptr, nullptr, n, st, fs);
@@ -940,16 +944,16 @@ static hipError_t forward_fields_c(const LcParams& P, uint16_t* a1, const uint16
         OutDst od{{t, t + V, t + 2 * V}, (long)n, P.w3, P.b3, out_scale};
         e = run_conv<C, NB, EPI_OUT_STORE>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
         if (e != hipSuccess) return e;
-        return lc_band(t, n, band, g, row, 1, st);
+        return lc_band(t, n, band, g, row, 1, st, 3);
     }
-    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale};
+    OutDst od{{g[0], g[1], g[2]}, row, P.w3, P.b3, out_scale, 3};
     return run_conv<C, NB, EPI_OUT>(a1, P.wb2, P.b2, nullptr, nullptr, nullptr, n, st, FieldSrc{}, od);
 }
 
-hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* const g[3], long row, int n,
+hipError_t lc_forward_fields(const LcParams& P, uint16_t* a1, const uint16_t* d0, float* F, long row, int n,
                              const float in_scale[4], float out_scale, float band, float* t, hipStream_t st) {
-    if (P.C == 16) return forward_fields_c<16>(P, a1, d0, g, row, n, in_scale, out_scale, band, t, st);
-    if (P.C == 32) return forward_fields_c<32>(P, a1, d0, g, row, n, in_scale, out_scale, band, t, st);
+    if (P.C == 16) return forward_fields_c<16>(P, a1, d0, F, row, n, in_scale, out_scale, band, t, st);
+    if (P.C == 32) return forward_fields_c<32>(P, a1, d0, F, row, n, in_scale, out_scale, band, t, st);
     return hipErrorInvalidValue;
 }
 

@@ -1,8 +1,8 @@
 // cola_pm_force without a caller workspace, for callers that cannot allocate device memory
 // (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).
 //
-// The workspace of cola_pm_force -- the three padded spectra, the deposit's sort buffers and the
-// twiddle tables -- lives in a fixed device array of kNoAllocBytes per GPU, defined here.  Host
+// The workspace of cola_pm_force -- the three padded spectra, the interleaved force mesh, the
+// deposit's sort buffers and the twiddle tables -- lives in a fixed device array of kNoAllocBytes per GPU, defined here.  Host
 // code never passes the array's name to a kernel (on the host it is only a stand-in symbol): the
 // first call on a device looks up that device's address of the array with hipGetSymbolAddress,
 // with the device current, and every later call on that device passes the looked-up pointer as
@@ -14,7 +14,7 @@
 
 namespace {
 
-constexpr size_t kNoAllocBytes = size_t(64) << 20;  // 64 MiB per GPU, held until the process ends
+constexpr size_t kNoAllocBytes = size_t(96) << 20;  // 96 MiB per GPU, held until the process ends
 constexpr int kMaxDevices = 64;
 
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];

@@ -10,6 +10,7 @@
 // meshes where an absolute float coordinate would only resolve 1e-4 cell.
 
 #include "cola_internal.h"
+#include "force_gather.h"
 
 namespace cola {
 
@@ -42,43 +43,6 @@ __device__ __forceinline__ void lagr_index(uint32_t p, int n_part, int& i, int& 
     i = (int)ii;
     j = (int)jj;
     l = (int)(r - jj * np);
-}
-
-// The two z corners of a mesh row as one 8-byte load: the force meshes' rows carry the values of
-// z = 0, 1 again at z = n, n + 1, so the pair (m, m + 1) never wraps.
-__device__ __forceinline__ float2 load_pair(const float* p) {
-    float2 v;
-    __builtin_memcpy(&v, p, sizeof(float2));
-    return v;
-}
-
-// CIC gather of three force meshes (rows with the ghost values) at one particle.
-__device__ __forceinline__ void gather3(const float* fx, const float* fy, const float* fz, long row, int n,
-                                        const Cell& cx, const Cell& cy, const Cell& cz, float g[3]) {
-    const int xs[2] = {cx.m, wrap1(cx.m, n)}, ys[2] = {cy.m, wrap1(cy.m, n)};
-    const float wx[2] = {1.0f - cx.f, cx.f}, wy[2] = {1.0f - cy.f, cy.f}, wz[2] = {1.0f - cz.f, cz.f};
-    float2 vx[4], vy[4], vz[4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {  // the twelve loads are issued together
-            const long r = ((long)xs[a] * n + ys[b]) * row + cz.m;
-            vx[2 * a + b] = load_pair(fx + r);
-            vy[2 * a + b] = load_pair(fy + r);
-            vz[2 * a + b] = load_pair(fz + r);
-        }
-    g[0] = g[1] = g[2] = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const float wab = wx[a] * wy[b];
-            const float w0 = wab * wz[0], w1 = wab * wz[1];
-            const int q = 2 * a + b;
-            g[0] += w0 * vx[q].x + w1 * vx[q].y;
-            g[1] += w0 * vy[q].x + w1 * vy[q].y;
-            g[2] += w0 * vz[q].x + w1 * vz[q].y;
-        }
 }
 
 __device__ __forceinline__ void deposit8(float* mesh, long row, int n, const Cell& cx, const Cell& cy,
@@ -184,23 +148,19 @@ __global__ void k_density_finish(float* mesh, long row, int n, float scale, floa
     }
 }
 
-// z = 0, 1 copied to z = n, n + 1 in every row of the three meshes.
-__global__ void k_mesh_ghosts(float* fx, float* fy, float* fz, long row, int n, long bstride) {
+// Cells z = 0, 1 (six floats) copied to z = n, n + 1 in every row of an interleaved force mesh.
+__global__ void k_mesh_ghosts(float* F, long row, int n, long bstride) {
     const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;  // row index
     if (r >= (long)n * n) return;
-    const long o = (long)blockIdx.y * bstride + r * row;
-    float* f[3] = {fx, fy, fz};
+    float* f = F + (long)blockIdx.y * bstride + r * row;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        f[d][o + n] = f[d][o];
-        f[d][o + n + 1] = f[d][o + 1];
-    }
+    for (int k = 0; k < 6; ++k) f[3L * n + k] = f[k];
 }
 
-hipError_t mesh_ghosts(float* const f[3], long row, int n, long bstride, int n_real, hipStream_t st) {
+hipError_t mesh_ghosts(float* F, long row, int n, long bstride, int n_real, hipStream_t st) {
     ProfScope ps(PROF_OTHER, st);
-    hipLaunchKernelGGL(k_mesh_ghosts, dim3((unsigned)(((long)n * n + 255) / 256), n_real), dim3(256), 0, st, f[0], f[1],
-                       f[2], row, n, bstride);
+    hipLaunchKernelGGL(k_mesh_ghosts, dim3((unsigned)(((long)n * n + 255) / 256), n_real), dim3(256), 0, st, F, row,
+                       n, bstride);
     return hipGetLastError();
 }
 
@@ -225,16 +185,19 @@ __device__ __forceinline__ float bracket(float g, float d1, float d2m, float s1,
 // particle streams are non-temporal, leaving L2 to the force-mesh lines that neighbouring
 // particles share.
 __global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint32_t npr, LatticeGeom fg,
-                                                           const float* fx, const float* fy, const float* fz,
-                                                           KickDrift kd) {
+                                                           const float* F, KickDrift kd) {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npr) return;
     const int r = blockIdx.y;
     const long gid = (long)r * npr + p;
     float x[3], pv[3], s1[3], s2[3];
 #pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = __builtin_nontemporal_load(P.x[d] + gid);
+    // x first: loads complete in order, so the gather, whose addresses need only x, does not wait
+    // for the nine loads below
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        x[d] = __builtin_nontemporal_load(P.x[d] + gid);
         pv[d] = __builtin_nontemporal_load(P.p[d] + gid);
         s1[d] = __builtin_nontemporal_load(P.psi1[d] + gid);
         s2[d] = __builtin_nontemporal_load(P.psi2[d] + gid);
@@ -245,8 +208,8 @@ __global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint3
 #pragma unroll
     for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], x[d], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
     float g[3];
-    const long mo = r * fg.mesh_bstride;
-    gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
+    gather_interleaved(F + r * fg.mesh_bstride, fg.row, fg.n_mesh, c[0].m, c[1].m, c[2].m, c[0].f, c[1].f, c[2].f,
+                       g);
     const bool move = kd.drift != 0.0f || kd.dd1 != 0.0f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -256,17 +219,16 @@ __global__ void __launch_bounds__(256) k_gather_kick_drift(ParticlePtrs P, uint3
     }
 }
 
-hipError_t gather_kick_drift(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg,
-                             const float* fx, const float* fy, const float* fz, const KickDrift& kd,
-                             hipStream_t st) {
+hipError_t gather_kick_drift(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* F,
+                             const KickDrift& kd, hipStream_t st) {
     ProfScope ps((kd.drift != 0.0f || kd.dd1 != 0.0f) ? PROF_GKD : PROF_KICK, st);
     hipLaunchKernelGGL(k_gather_kick_drift, dim3((unsigned)((npr + 255) / 256), n_real), dim3(256), 0, st, P,
-                       (uint32_t)npr, fg, fx, fy, fz, kd);
+                       (uint32_t)npr, fg, F, kd);
     return hipGetLastError();
 }
 
-__global__ void k_gather_force(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* fx,
-                               const float* fy, const float* fz, float* ax, float* ay, float* az) {
+__global__ void k_gather_force(ParticlePtrs P, long npr, int n_real, LatticeGeom fg, const float* F, float* ax,
+                               float* ay, float* az) {
     long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= npr * n_real) return;
     long r = gid / npr, p = gid - r * npr;
@@ -276,19 +238,19 @@ __global__ void k_gather_force(ParticlePtrs P, long npr, int n_real, LatticeGeom
 #pragma unroll
     for (int d = 0; d < 3; ++d) c[d] = cell_of(idx[d], P.x[d][gid], fg.n_part, fg.n_mesh, fg.inv_h, fg.qoff);
     float g[3];
-    long mo = r * fg.mesh_bstride;
-    gather3(fx + mo, fy + mo, fz + mo, fg.row, fg.n_mesh, c[0], c[1], c[2], g);
+    gather_interleaved(F + r * fg.mesh_bstride, fg.row, fg.n_mesh, c[0].m, c[1].m, c[2].m, c[0].f, c[1].f, c[2].f,
+                       g);
     ax[gid] = g[0];
     ay[gid] = g[1];
     az[gid] = g[2];
 }
 
-hipError_t gather_force(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* fx,
-                        const float* fy, const float* fz, float* const acc[3], hipStream_t st) {
+hipError_t gather_force(const ParticlePtrs& P, long npr, int n_real, const LatticeGeom& fg, const float* F,
+                        float* const acc[3], hipStream_t st) {
     long n = npr * n_real;
     ProfScope ps(PROF_GATHER, st);
     hipLaunchKernelGGL(k_gather_force, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, npr, n_real,
-                       fg, fx, fy, fz, acc[0], acc[1], acc[2]);
+                       fg, F, acc[0], acc[1], acc[2]);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ const char* const kKindNames[PROF_NUM_KINDS] = {
     "fill", "cic_deposit", "fft_z_r2c", "fft_y_forward", "fft_x_forward", "fft_x_green",
     "fft_y_split", "fft_y_inverse", "fft_z_c2r", "gather_kick_drift", "gather_force",
     "ic_kernels", "fft_x_inverse_mult", "pk_bin", "copy", "other", "gather_kick", "pk_deposit", "cic_sort", "cic_tile",
-    "lc_conv3", "lc_conv3_wgrad", "lc_other", "fof", "pk_alias"};
+    "lc_conv3", "lc_conv3_wgrad", "lc_other", "fof", "pk_alias", "fft_z_c2r3"};
 
 struct Record {
     int kind;

@@ -3,7 +3,7 @@ array of the library), called through the C ABI and compared with cola_pm_force 
 workspace.  Both run the same kernels on the same inputs with a deterministic deposit (fixed-point
 sums) and FFT, so the accelerations must agree bit for bit.  Two calls in a row, the second on a
 smaller problem, show that nothing left in the shared array from the first call leaks into the
-second; a problem beyond the array's 64 MiB is rejected before any launch.
+second; a problem beyond the array's 96 MiB is rejected before any launch.
 """
 
 import ctypes
@@ -43,7 +43,7 @@ def noalloc_force(cola, prob, st):
 
 def test_noalloc_matches_workspace_form(cola):
     cosmo = cola.make_cosmology(**W.COSMOLOGY)
-    # first 64^3 particles on a 128^3 mesh (39 MiB of workspace), then a smaller batch of two
+    # first 64^3 particles on a 128^3 mesh (65 MiB of workspace), then a smaller batch of two
     # 24^3 / 72^3 realizations
     for box, n_part, pm, n_real, seeds in ((256.0, 64, 2, 1, [3]), (96.0, 24, 3, 2, [4, 5])):
         say(f"noalloc force: {n_real} x {n_part}^3 particles, {n_part * pm}^3 mesh")
@@ -61,7 +61,7 @@ def test_noalloc_matches_workspace_form(cola):
 
 def test_noalloc_rejects_beyond_its_array(cola):
     from paper_1509_04685_amd import _lib
-    prob = cola.make_problem(256.0, 128, 1, 19.0, 10)  # 102 MiB of workspace
+    prob = cola.make_problem(256.0, 128, 1, 19.0, 10)  # 128 MiB of workspace
     assert cola.workspace_bytes(prob) > 64 << 20
     st = cola.ParticleState(prob)
     ptrs = (ctypes.c_void_p * 3)(*[st.p[d].data_ptr() for d in range(3)])
