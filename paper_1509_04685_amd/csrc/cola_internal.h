@@ -147,8 +147,9 @@ hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, lo
                                   const GreenFilter* gf = nullptr);
 // The same passes, with the three z c2r passes fused into one that writes the force components
 // interleaved: F[(x n + y) frow + 3 z + c], c = 0, 1, 2 for x, y, z, z = 0 .. n + 1 (the ghost cells
-// z = n, n + 1 repeat z = 0, 1), frow = force_row3(n) floats per row, fstride floats between
-// realizations.  P, Q, R are overwritten; F must not overlap them.
+// z = n, n + 1 repeat z = 0, 1), frow = force_row3(n) floats per row (3 (n + 2) rounded up to
+// whole 128-byte lines), fstride floats between realizations.  P, Q, R are overwritten; F must
+// not overlap them.
 long force_row3(int n);
 hipError_t pm_force_interleaved(float2* P, float2* Q, float2* R, float* F, long frow, long fstride, long bstride,
                                 const Mesh3& g, const float2* tw, float kf, int n_real, hipStream_t st,

@@ -473,6 +473,7 @@ static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long 
 static hipError_t run_z_c2r3_shape(const float2* fx, const float2* fy, const float2* fz, long in_bstride, float* out,
                                    long out_row, long out_bstride, const Mesh3& g, const float2* tw, int n_real,
                                    float kf, const FftShape& sh, hipStream_t st, long lines = -1) {
+    if (out_row < 3L * (g.n + 2)) return hipErrorInvalidValue;
     FftLaunch L;
     L.op = OP_Z_C2R3;
     const int lpb = sh.width;
@@ -570,7 +571,7 @@ static hipError_t force_xy_passes(float2* P, float2* Q, float2* R, long bstride,
     return run_rows(OP_ROWS_INV, Q, nullptr, bstride, g, tw, kf, n_real, st);
 }
 
-long force_row3(int n) { return (3L * (n + 2) + 31) / 32 * 32; }
+long force_row3(int n) { return (3L * (n + 2) + 31) / 32 * 32; }  // rows start on 128-byte lines
 
 hipError_t pm_force_interleaved(float2* P, float2* Q, float2* R, float* F, long frow, long fstride, long bstride,
                                 const Mesh3& g, const float2* tw, float kf, int n_real, hipStream_t st,

@@ -325,10 +325,9 @@ __global__ void __launch_bounds__(1024) k_fft_z_c2r3(const float2* in0, const fl
     __syncthreads();
     float* dst = out + (long)blockIdx.y * out_bstride + first * out_row;
     const int half = rs / 2;  // float2 per staged row (rs is even)
-    for (int i = threadIdx.x; i < W * half; i += blockDim.x) {
-        const int j = i / half, h = i - j * half;
-        store_stream(reinterpret_cast<float2*>(dst + j * out_row) + h, reinterpret_cast<const float2*>(S + j * rs)[h]);
-    }
+    for (int j = 0; j < W; ++j)
+        for (int h = threadIdx.x; h < half; h += blockDim.x)
+            store_stream(reinterpret_cast<float2*>(dst + j * out_row) + h, reinterpret_cast<const float2*>(S + j * rs)[h]);
 }
 
 // ------------------------------------------------------------------ y rows
