@@ -230,6 +230,21 @@ def test_nonfinite_arguments_return_nonfinite():
     assert LIB.cola_status_string(-6)
 
 
+def test_fft_set_shape_fused_force_pass_host_checks():
+    """The fused z pass of the force (z_c2r3: three thread groups per block, one per force
+    component, sharing one LDS area) is admitted up to 1024 threads and 150 KB of LDS per block
+    (host only: nothing is launched)."""
+    f = LIB.cola_fft_set_shape
+    assert f(768, b"z_c2r3", 24, 16, 1) == 0    # 3 x 16 x 16 threads, 3 x 16 x 385 x 8 B = 148 KB
+    assert f(768, b"z_c2r3", 24, 32, 1) == -1   # 296 KB of LDS
+    assert f(768, b"z_c2r3", 12, 16, 1) == -1   # 1536 threads
+    assert f(1536, b"z_c2r3", 24, 8, 1) == 0
+    assert f(1536, b"z_c2r3", 24, 16, 1) == -1
+    assert f(768, b"z_c2r3", 24, 16, 2) == -1   # no split-exchange plan for z passes
+    assert f(768, b"z_c2r", 12, 32, 0) == -1    # the single z pass keeps its 512-thread bound
+    assert f(768, b"z_c2r3", 12, 8, 1) == 0     # restore the usual shape
+
+
 def test_fft_set_shape_split_plans_host_checks():
     """Split-exchange plans are offered for the x-column kinds where compiled, nowhere else (host
     only: nothing is launched)."""
