@@ -114,6 +114,27 @@ struct OutDst {
     int zs = 1;
 };
 
+// The halo of tile `tile` (one voxel, all its C8 vectors of channels, per thread and k) into
+// registers, for the tile after the one being computed.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // a register quad (uint4 is a struct)
+template <int HK, int C8>
+__device__ __forceinline__ void load_halo_regs(u32x4 (&h)[HK][C8], const uint4* __restrict__ ing, int tile, int n,
+                                               int nty, int ntz, int tid) {
+    const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
+#pragma unroll
+    for (int k = 0; k < HK; ++k) {
+        const int hv = tid + k * 256;
+        if (hv < HVOX) {
+            const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
+            const int gx = wrap_halo(tx * TX + hx - 1, n), gy = wrap_halo(ty * TY + hy - 1, n);
+            const int gz = wrap_halo(tz * TZ + hz - 1, n);
+            const uint4* src = ing + (((long)gx * n + gy) * n + gz) * C8;
+#pragma unroll
+            for (int c8 = 0; c8 < C8; ++c8) h[k][c8] = *reinterpret_cast<const u32x4*>(src + c8);
+        }
+    }
+}
+
 // out[v][co] = sum_tap sum_ci W[co][tap][ci] in[v + d_tap][ci] + bias[co], then
 //   EPI_ZA: out = Z, out2 = silu(Z);  EPI_A: out = silu(Z);  EPI_DSILU: out = Z * silu'(prev[v][co]).
 // in: [V][CINP] BF16; W: [16 NB][27][CINP] BF16; out: [V][16 NB].  Block = 4 waves on a 4x4x16
@@ -133,6 +154,7 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
     constexpr int COP = 16 * NB;
     constexpr int KTOT = 27 * CINP;
     constexpr int KSTEPS = (KTOT + 31) / 32;
+    constexpr int KUNROLL = NB == 1 ? 2 : KSTEPS;
     constexpr int C8 = CINP / 8;
     extern __shared__ uint4 smem[];
     uint4* sw = smem;                      // weights, COP * 27 * C8 vectors
@@ -143,13 +165,31 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
     const int nty = n / TY, ntz = n / TZ;
     const int m = lane & 15, kb = lane >> 4;
     const uint4* ing = reinterpret_cast<const uint4*>(in);
+    // Up to 16 input channels the next tile's halo is requested into registers while the current
+    // tile is computed (one halo voxel, all its channels, per thread and k), so a tile's loads no
+    // longer stand between its barrier and its matrix-core loop.
+    constexpr int HK = (HVOX + 255) / 256;
+    constexpr bool PREFETCH = !FIELDS && C8 <= 2;
+    constexpr int PK = PREFETCH ? HK : 1, PC = PREFETCH ? C8 : 1;
+    u32x4 hreg[PK][PC];
+    if constexpr (PREFETCH)
+        if ((int)blockIdx.x < tiles) load_halo_regs<PK, PC>(hreg, ing, blockIdx.x, n, nty, ntz, tid);
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
         const int y0v = y0;
         __syncthreads();  // the previous tile's readers are done with the halo
+        if constexpr (PREFETCH) {
 #pragma unroll
-        for (int k = 0; k < (HVOX + 255) / 256; ++k) {  // one halo voxel (all its channels) per thread
+            for (int k = 0; k < PK; ++k) {
+                const int hv = tid + k * 256;
+                if (hv < HVOX)
+#pragma unroll
+                    for (int c8 = 0; c8 < PC; ++c8) *reinterpret_cast<u32x4*>(sh + hv * C8 + c8) = hreg[k][c8];
+            }
+        } else
+#pragma unroll
+        for (int k = 0; k < HK; ++k) {  // one halo voxel (all its channels) per thread
             const int hv = tid + k * 256;
             if (hv < HVOX) {
                 const int hz = hv % HZ, hy = (hv / HZ) % HY, hx = hv / (HZ * HY);
@@ -172,11 +212,27 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
             }
         }
         __syncthreads();
+        // the output layer's force-mesh values are requested first, the next halo after them (loads
+        // complete in order, so the epilogue does not wait for the halo)
+        constexpr bool FO_EARLY = EPI == EPI_OUT && NB == 1;  // 32 channels: no registers to spare
+        float fo[3] = {0.0f, 0.0f, 0.0f};
+        long fo_off = 0;
+        if constexpr (FO_EARLY) {
+            const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
+            fo_off = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + (long)(z0 + lz) * od.zs;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fo[c] = od.f[c][fo_off];
+        }
+        if constexpr (PREFETCH)
+            if (tile + (int)gridDim.x < tiles) load_halo_regs<PK, PC>(hreg, ing, tile + gridDim.x, n, nty, ntz, tid);
         f32x4 acc[4][NB];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int b = 0; b < NB; ++b) acc[r][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // 16-channel layers: unrolled by two, which leaves the registers for the prefetched halo
+        // (fully unrolled they needed 150-168)
+#pragma unroll KUNROLL
         for (int ks = 0; ks < KSTEPS; ++ks) {
             const int k = ks * 32 + kb * 8;
             const int tap = k / CINP, c0 = k % CINP;
@@ -229,13 +285,19 @@ __global__ void __launch_bounds__(256, 3) k_conv3_mfma(const uint16_t* __restric
                 y1 += od.w3[COP + co] * a;
                 y2 += od.w3[2 * COP + co] * a;
             }
-            const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
-            const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + (long)(z0 + lz) * od.zs;
             if constexpr (EPI == EPI_OUT_STORE) {
+                const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
+                const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + (long)(z0 + lz) * od.zs;
                 od.f[0][o] = y0 * od.scale;
                 od.f[1][o] = y1 * od.scale;
                 od.f[2][o] = y2 * od.scale;
+            } else if constexpr (FO_EARLY) {
+                od.f[0][fo_off] = fo[0] + y0 * od.scale;
+                od.f[1][fo_off] = fo[1] + y1 * od.scale;
+                od.f[2][fo_off] = fo[2] + y2 * od.scale;
             } else {
+                const int lx = tid >> 6, ly = (tid >> 4) & 3, lz = tid & 15;  // voxel tid of the tile
+                const long o = ((long)(x0 + lx) * n + (y0v + ly)) * od.row + (long)(z0 + lz) * od.zs;
                 od.f[0][o] += y0 * od.scale;
                 od.f[1][o] += y1 * od.scale;
                 od.f[2][o] += y2 * od.scale;
