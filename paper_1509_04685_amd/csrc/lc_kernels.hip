@@ -397,7 +397,7 @@ static hipError_t run_conv_dens(const uint16_t* d0, const uint16_t* w, const flo
                                 hipStream_t st) {
     const long tiles = (long)(n / TX) * (n / TY) * (n / TZ);
     const size_t lds = (size_t)16 * NB * 32 * 2 + (size_t)HVOX * 2;
-    ProfScope ps(PROF_LC_CONV, st);
+    ProfScope ps(PROF_LC_CONV, st, 1);  // tag: input channels
     hipLaunchKernelGGL(k_conv3_dens<NB>, dim3((unsigned)std::min<long>(tiles, 4096)), dim3(256), lds, st, d0, w, bias,
                        out, n, (int)tiles);
     return hipGetLastError();
@@ -413,7 +413,7 @@ static hipError_t run_conv(const uint16_t* in, const uint16_t* w, const float* b
     const size_t lds = (size_t)16 * NB * 27 * CINP * 2 + (size_t)HVOX * CINP * 2;
     auto kern = k_conv3_mfma<CINP, NB, EPI, FIELDS>;
     if (hipError_t e = allow_lds_lc(kern, lds); e != hipSuccess) return e;
-    ProfScope ps(PROF_LC_CONV, st);
+    ProfScope ps(PROF_LC_CONV, st, CINP);  // tag: input channels (padded)
     hipLaunchKernelGGL(kern, dim3((unsigned)std::min<long>(tiles, 4096)), dim3(256), lds, st, in, w, bias, out, out2,
                        prev, n, (int)tiles, fs, od);
     return hipGetLastError();
