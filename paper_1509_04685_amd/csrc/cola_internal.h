@@ -135,21 +135,16 @@ inline void green_slopes(GreenFilter& gf) {
     gf.t_last = gf.t[gf.n - 1];
 }
 
-// PM force from the y-transformed spectrum in P (z and y forward passes done), with Q, R, T free
+// PM force from the y-transformed spectrum in P (z and y forward passes done), with Q, R free
 // buffers of the same size (all distinct):
 //   fused x (forward, Green 1/(k^2 n^3), inverse) -> P = G P, Q = i k_x G P;
 //   y inverse: P -> P (times i k_y), R (plain);  Q -> Q;
-//   z c2r (out of place): Q -> T = F_x, P -> Q = F_y, R (times i k_z) -> P = F_z.
-// Real force rows of 2 nzp floats, with the ghost values of z = 0, 1 at z = n, n + 1.
-// gf (optional): the Green's function is multiplied by gf's T.
-hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
-                                  const float2* tw, float kf, int n_real, hipStream_t st,
-                                  const GreenFilter* gf = nullptr);
-// The same passes, with the three z c2r passes fused into one that writes the force components
-// interleaved: F[(x n + y) frow + 3 z + c], c = 0, 1, 2 for x, y, z, z = 0 .. n + 1 (the ghost cells
-// z = n, n + 1 repeat z = 0, 1), frow = force_row3(n) floats per row (3 (n + 2) rounded up to
-// whole 128-byte lines), fstride floats between realizations.  P, Q, R are overwritten; F must
-// not overlap them.
+//   one z c2r pass of Q (F_x), P (F_y) and R (times i k_z: F_z) writing the components
+//   interleaved: F[(x n + y) frow + 3 z + c], c = 0, 1, 2 for x, y, z, z = 0 .. n + 1 (the ghost
+//   cells z = n, n + 1 repeat z = 0, 1), frow = force_row3(n) floats per row (3 (n + 2) rounded
+//   up to whole 128-byte lines), fstride floats between realizations.
+// P, Q, R are overwritten; F must not overlap them.  gf (optional): the Green's function is
+// multiplied by gf's T.
 long force_row3(int n);
 hipError_t pm_force_interleaved(float2* P, float2* Q, float2* R, float* F, long frow, long fstride, long bstride,
                                 const Mesh3& g, const float2* tw, float kf, int n_real, hipStream_t st,

@@ -336,8 +336,7 @@ static hipError_t launch_shape(FftLaunch& L, int mesh_n, const FftShape& sh) {
         D e{pl, les};
         switch (L.op) {
             case OP_Z_R2C: err = go_z_r2c<D>(L, e); break;
-            case OP_Z_C2R: err = go_z_c2r<D, false>(L, e); break;
-            case OP_Z_C2R_IKZ: err = go_z_c2r<D, true>(L, e); break;
+            case OP_Z_C2R: err = go_z_c2r<D>(L, e); break;
             case OP_Z_C2R3: err = go_z_c2r3<D>(L, e); break;
             case OP_ROWS_FWD: err = go_rows<D, 0>(L, e); break;
             case OP_ROWS_INV: err = go_rows<D, 1>(L, e); break;
@@ -433,12 +432,11 @@ static hipError_t run_z_r2c(const float* in, long in_row, long in_bstride, float
                            shape_for(FK_Z_R2C, g.n), st);
 }
 
-template <bool MUL>
 static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out, long out_row, long out_bstride,
                                   const Mesh3& g, const float2* tw, int n_real, float kf, float scale,
                                   const FftShape& sh, hipStream_t st) {
     FftLaunch L;
-    L.op = MUL ? OP_Z_C2R_IKZ : OP_Z_C2R;
+    L.op = OP_Z_C2R;
     const int lpb = sh.width;
     L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
     L.grid = dim3((unsigned)((long)g.n * g.n / lpb), n_real);
@@ -460,11 +458,10 @@ static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out,
     return launch_shape(L, g.n, sh);
 }
 
-template <bool MUL>
 static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long out_row, long out_bstride,
                             const Mesh3& g, const float2* tw, int n_real, float kf, float scale,
                             hipStream_t st) {
-    return run_z_c2r_shape<MUL>(in, in_bstride, out, out_row, out_bstride, g, tw, n_real, kf, scale,
+    return run_z_c2r_shape(in, in_bstride, out, out_row, out_bstride, g, tw, n_real, kf, scale,
                                 shape_for(FK_Z_C2R, g.n), st);
 }
 
@@ -581,18 +578,6 @@ hipError_t pm_force_interleaved(float2* P, float2* Q, float2* R, float* F, long 
     return run_z_c2r3_shape(Q, P, R, bstride, F, frow, fstride, g, tw, n_real, kf, shape_for(FK_Z_C2R3, g.n), st);
 }
 
-hipError_t pm_force_from_spectrum(float2* P, float2* Q, float2* R, float2* T, long bstride, const Mesh3& g,
-                                  const float2* tw, float kf, int n_real, hipStream_t st, const GreenFilter* gf) {
-    hipError_t e = force_xy_passes(P, Q, R, bstride, g, tw, kf, n_real, st, gf);
-    if (e != hipSuccess) return e;
-    const long rowf = 2L * g.nzp;
-    e = run_z_c2r<false>(Q, bstride, reinterpret_cast<float*>(T), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
-    if (e != hipSuccess) return e;
-    e = run_z_c2r<false>(P, bstride, reinterpret_cast<float*>(Q), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
-    if (e != hipSuccess) return e;
-    return run_z_c2r<true>(R, bstride, reinterpret_cast<float*>(P), rowf, 2 * bstride, g, tw, n_real, kf, 1.0f, st);
-}
-
 hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, long work_bstride,
                           float* out, long out_row, long out_bstride, const Mesh3& g, const float2* tw,
                           int n_real, int mtype, int axis_a, int axis_b, float kf, float scale,
@@ -602,7 +587,7 @@ hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, l
     if (e != hipSuccess) return e;
     e = run_rows(OP_ROWS_INV, work, nullptr, work_bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;
-    return run_z_c2r<false>(work, work_bstride, out, out_row, out_bstride, g, tw, n_real, kf, 1.0f, st);
+    return run_z_c2r(work, work_bstride, out, out_row, out_bstride, g, tw, n_real, kf, 1.0f, st);
 }
 
 // Times every admissible shape of each FFT kernel at mesh size n on the buffers S, A, B (each at
@@ -643,7 +628,7 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
                     return run_z_r2c_shape(reinterpret_cast<const float*>(S), 2L * g.nzp, 0, A, 0, g, tw, 1, 1.0f,
                                            0.0f, sh, st);
                 case FK_Z_C2R:
-                    return run_z_c2r_shape<false>(A, 0, reinterpret_cast<float*>(B), 2L * g.nzp, 0, g, tw, 1, kf,
+                    return run_z_c2r_shape(A, 0, reinterpret_cast<float*>(B), 2L * g.nzp, 0, g, tw, 1, kf,
                                                   1.0f, sh, st);
                 case FK_ROWS_Y: return run_rows_shape(OP_ROWS_FWD, S, nullptr, 0, g, tw, kf, 1, sh, st);
                 case FK_COLS_X: return run_cols_shape(S, 0, g, tw, 1, sh, st);

@@ -182,11 +182,10 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
 // ------------------------------------------------------------------ z pass: half complex -> real
 
 // Z_k = (X_k + conj X_{M-k}) + i conj(W_n^k) (X_k - conj X_{M-k}); x_{2j} + i x_{2j+1} = IFFT_M(Z)_j.
-// MUL_IKZ multiplies X by i k_z first (the kz = M Nyquist plane becomes 0).  Block: the W = 2^lw
-// lines (x, y0 .. y0 + W - 1) of one x plane; line j reads in[k plane + x n + y0 + j] and writes the
-// real row (x, y0 + j).  ghost: the row also gets x_0, x_1 again at n, n + 1 (rows of at least
-// n + 2 floats), so that a CIC pair (z, z + 1) never wraps.
-template <class LE, bool MUL_IKZ>
+// Block: the W = 2^lw lines (x, y0 .. y0 + W - 1) of one x plane; line j reads
+// in[k plane + x n + y0 + j] and writes the real row (x, y0 + j).  ghost: the row also gets x_0, x_1
+// again at n, n + 1 (rows of at least n + 2 floats).
+template <class LE>
 __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bstride, float* out, long out_row,
                                                    long out_bstride, int n, long plane, int lw, int ghost, LE eng,
                                                    const float2* tw, float kf, float scale) {
@@ -217,15 +216,10 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bst
         for (int u = 0; u < R; ++u) {
             const int o = threadIdx.x + u * bd;
             const int k = o >> lw, j = o & (W - 1);
-            float2 y = xv[u];
-            if (MUL_IKZ) {
-                const float kz = kf * (float)k;
-                y = make_float2(-kz * y.y, kz * y.x);
-            }
-            Lb[j * (M + 1) + k] = cscale(y, scale);
+            Lb[j * (M + 1) + k] = cscale(xv[u], scale);
         }
         if (threadIdx.x < W)  // kz Nyquist plane
-            Lb[threadIdx.x * (M + 1) + M] = MUL_IKZ ? make_float2(0.0f, 0.0f) : cscale(xm, scale);
+            Lb[threadIdx.x * (M + 1) + M] = cscale(xm, scale);
     }
     __syncthreads();
     float2* L = Lb + line * (M + 1);
@@ -523,7 +517,7 @@ __global__ void __launch_bounds__((col_bound<LE, TK>())) k_fft_x_mult(const floa
 // ------------------------------------------------------------------ launches
 
 enum FftOp {
-    OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R_IKZ, OP_Z_C2R3,  // z passes (line length n/2)
+    OP_Z_R2C = 0, OP_Z_C2R, OP_Z_C2R3,                // z passes (line length n/2)
     OP_ROWS_FWD, OP_ROWS_INV, OP_ROWS_SPLIT,          // y rows
     OP_COLS_FWD, OP_X_GREEN, OP_X_MULT,               // x columns
     OP_X_GREEN_FILT                                   // x_green with a Green's-function filter
@@ -584,9 +578,9 @@ inline hipError_t go_z_r2c(const FftLaunch& L, LE e) {
     return hipGetLastError();
 }
 
-template <class LE, bool MUL>
+template <class LE>
 inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
-    auto kern = k_fft_z_c2r<LE, MUL>;
+    auto kern = k_fft_z_c2r<LE>;
     const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
     hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.in_bstride, L.rout, L.out_row, L.out_bstride,
@@ -676,8 +670,7 @@ inline hipError_t static_z_ops(const FftLaunch& L) {
     if (L.probe) return hipSuccess;
     switch (L.op) {
         case OP_Z_R2C: return go_z_r2c<E>(L, E{});
-        case OP_Z_C2R: return go_z_c2r<E, false>(L, E{});
-        case OP_Z_C2R_IKZ: return go_z_c2r<E, true>(L, E{});
+        case OP_Z_C2R: return go_z_c2r<E>(L, E{});
         case OP_Z_C2R3: return go_z_c2r3<E>(L, E{});
         default: return hipErrorNotSupported;
     }

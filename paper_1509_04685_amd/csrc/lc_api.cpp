@@ -205,10 +205,31 @@ int cola_lc_adam(const cola_lc_net* net, int32_t t, float lr, float beta1, float
     return COLA_OK;
 }
 
+// Three mesh buffers (S, A, B), the interleaved force mesh F and the twiddle table: the step's
+// force passes (pm_force_interleaved) on a caller's positions or density.
+struct FieldsWs {
+    float2 *S, *A, *B, *tw;
+    float* F;
+    long frow;
+};
+static size_t fields_f_bytes(int n) { return (size_t)n * n * force_row3(n) * sizeof(float); }
+static FieldsWs carve_fields(void* ws, const Mesh3& g) {
+    char* b = static_cast<char*>(ws);
+    const size_t mb = lc_align(g.bytes());
+    FieldsWs w;
+    w.S = reinterpret_cast<float2*>(b);
+    w.A = reinterpret_cast<float2*>(b + mb);
+    w.B = reinterpret_cast<float2*>(b + 2 * mb);
+    w.F = reinterpret_cast<float*>(b + 3 * mb);
+    w.tw = reinterpret_cast<float2*>(b + 3 * mb + lc_align(fields_f_bytes(g.n)));
+    w.frow = force_row3(g.n);
+    return w;
+}
+
 size_t cola_pm_fields_workspace_bytes(int32_t n_mesh) {
     if (!fft_size_ok(n_mesh) || n_mesh > kMaxLcMesh) return 0;
     const Mesh3 g = make_mesh(n_mesh);
-    return 4 * lc_align(g.bytes()) + lc_align((size_t)n_mesh * sizeof(float2));
+    return 3 * lc_align(g.bytes()) + lc_align(fields_f_bytes(n_mesh)) + lc_align((size_t)n_mesh * sizeof(float2));
 }
 
 int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, float* delta, float* g[3],
@@ -221,29 +242,21 @@ int cola_pm_fields(int32_t n_mesh, double box, const float* pos[3], int64_t n, f
     if (ws_bytes < cola_pm_fields_workspace_bytes(n_mesh)) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Mesh3 gm = make_mesh(n_mesh);
-    char* b = static_cast<char*>(ws);
-    float2* S = reinterpret_cast<float2*>(b);
-    float2* A = reinterpret_cast<float2*>(b + lc_align(gm.bytes()));
-    float2* B = reinterpret_cast<float2*>(b + 2 * lc_align(gm.bytes()));
-    float2* C = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
-    float2* tw = reinterpret_cast<float2*>(b + 4 * lc_align(gm.bytes()));
+    const FieldsWs w = carve_fields(ws, gm);
     const long row = 2L * gm.nzp;
-    float* s_real = reinterpret_cast<float*>(S);
+    float* s_real = reinterpret_cast<float*>(w.S);
     const double cells = (double)n_mesh * n_mesh * n_mesh;
     ws_forget(ws);
     (void)hipGetLastError();
-    LC_TRY(launch_twiddles(tw, n_mesh, st));
+    LC_TRY(launch_twiddles(w.tw, n_mesh, st));
     LC_TRY(launch_fill(s_real, 2L * gm.total_c(), 0.0f, st));
     LC_TRY(cic_deposit_absolute(pos, n, n_mesh, (float)(n_mesh / box), row, s_real, st));
     LC_TRY(density_finish(s_real, row, n_mesh, (float)(cells / (double)n), -1.0f, st));
     if (delta) LC_TRY(mesh_unpad(s_real, row, n_mesh, delta, st));
-    LC_TRY(fft_zy_forward(s_real, row, 0, A, 0, gm, tw, 1, 1.0f, 0.0f, st));
-    LC_TRY(pm_force_from_spectrum(A, B, S, C, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
-    const float* f[3] = {reinterpret_cast<const float*>(C), reinterpret_cast<const float*>(B),
-                         reinterpret_cast<const float*>(A)};
-    if (g)
-        for (int d = 0; d < 3; ++d) LC_TRY(mesh_unpad(f[d], row, n_mesh, g[d], st));
-    if (acc) LC_TRY(gather_absolute(pos, n, n_mesh, box, f, row, acc, st));
+    LC_TRY(fft_zy_forward(s_real, row, 0, w.A, 0, gm, w.tw, 1, 1.0f, 0.0f, st));
+    LC_TRY(pm_force_interleaved(w.A, w.B, w.S, w.F, w.frow, 0, 0, gm, w.tw, (float)(2.0 * M_PI / box), 1, st));
+    if (g) LC_TRY(mesh_unpad3(w.F, w.frow, n_mesh, g, st));
+    if (acc) LC_TRY(gather_absolute(pos, n, n_mesh, box, w.F, w.frow, acc, st));
     return COLA_OK;
 }
 
@@ -255,21 +268,13 @@ int cola_mesh_force(int32_t n_mesh, double box, const float* delta, float* g[3],
     if (ws_bytes < cola_pm_fields_workspace_bytes(n_mesh)) return COLA_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Mesh3 gm = make_mesh(n_mesh);
-    char* b = static_cast<char*>(ws);
-    float2* S = reinterpret_cast<float2*>(b);
-    float2* A = reinterpret_cast<float2*>(b + lc_align(gm.bytes()));
-    float2* B = reinterpret_cast<float2*>(b + 2 * lc_align(gm.bytes()));
-    float2* C = reinterpret_cast<float2*>(b + 3 * lc_align(gm.bytes()));
-    float2* tw = reinterpret_cast<float2*>(b + 4 * lc_align(gm.bytes()));
-    const long row = 2L * gm.nzp;
+    const FieldsWs w = carve_fields(ws, gm);
     ws_forget(ws);
     (void)hipGetLastError();
-    LC_TRY(launch_twiddles(tw, n_mesh, st));
-    LC_TRY(fft_zy_forward(delta, n_mesh, 0, A, 0, gm, tw, 1, 1.0f, 0.0f, st));
-    LC_TRY(pm_force_from_spectrum(A, B, S, C, 0, gm, tw, (float)(2.0 * M_PI / box), 1, st));
-    const float* f[3] = {reinterpret_cast<const float*>(C), reinterpret_cast<const float*>(B),
-                         reinterpret_cast<const float*>(A)};
-    for (int d = 0; d < 3; ++d) LC_TRY(mesh_unpad(f[d], row, n_mesh, g[d], st));
+    LC_TRY(launch_twiddles(w.tw, n_mesh, st));
+    LC_TRY(fft_zy_forward(delta, n_mesh, 0, w.A, 0, gm, w.tw, 1, 1.0f, 0.0f, st));
+    LC_TRY(pm_force_interleaved(w.A, w.B, w.S, w.F, w.frow, 0, 0, gm, w.tw, (float)(2.0 * M_PI / box), 1, st));
+    LC_TRY(mesh_unpad3(w.F, w.frow, n_mesh, g, st));
     return COLA_OK;
 }
 

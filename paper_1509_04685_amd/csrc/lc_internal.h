@@ -90,11 +90,14 @@ hipError_t lc_adam(float* p, float* g, float* m, float* v, long np, float lr, fl
 // Absolute positions q + x wrapped into [0, box) (lattice as in the step).
 hipError_t lc_positions(const float* const x[3], long n_per_real, int n_real, int n_part, double box, double qoff,
                         float* const pos[3], hipStream_t st);
-// CIC interpolation of three dense n^3 meshes (row floats per row) to absolute positions.
-hipError_t gather_absolute(const float* const pos[3], long np, int n, double box, const float* const f[3], long row,
+// CIC interpolation of the interleaved force mesh F (pm_force_interleaved: `row` floats per row,
+// ghost cells included) to absolute positions.
+hipError_t gather_absolute(const float* const pos[3], long np, int n, double box, const float* F, long row,
                            float* const out[3], hipStream_t st);
 // Copy of a mesh with `row` floats per row into a dense n^3 array.
 hipError_t mesh_unpad(const float* src, long row, int n, float* dst, hipStream_t st);
+// The three components of the interleaved force mesh F into dense n^3 arrays g[0..2].
+hipError_t mesh_unpad3(const float* F, long row, int n, float* const g[3], hipStream_t st);
 
 // Workspace of the network (lc_api.cpp): x0 for n_real realizations, a1 and a2 shared, and when
 // training z1, z2, dz1, dz2.

@@ -21,6 +21,7 @@
 
 #include "cola_internal.h"
 #include "lc_internal.h"
+#include "force_gather.h"
 
 namespace cola {
 
@@ -904,9 +905,10 @@ __global__ void k_positions(const float* x, long n_per_real, long total, int n_p
     pos[i] = u >= box ? u - box : u;
 }
 
+// CIC interpolation of the interleaved force mesh (rows of `row` floats, cell z of a row at 3 z,
+// ghost cells z = n, n + 1) to absolute positions.
 __global__ void k_gather_abs(const float* px, const float* py, const float* pz, long np, int n, float inv_h,
-                             const float* fx, const float* fy, const float* fz, long row, float* ox, float* oy,
-                             float* oz) {
+                             const float* F, long row, float* ox, float* oy, float* oz) {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     int ix0, ix1, iy0, iy1, iz0, iz1;
@@ -914,30 +916,28 @@ __global__ void k_gather_abs(const float* px, const float* py, const float* pz, 
     cic_abs(px[p], inv_h, n, ix0, ix1, ux);
     cic_abs(py[p], inv_h, n, iy0, iy1, uy);
     cic_abs(pz[p], inv_h, n, iz0, iz1, uz);
-    const int ix[2] = {ix0, ix1}, iy[2] = {iy0, iy1}, iz[2] = {iz0, iz1};
-    const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const long o = ((long)ix[a] * n + iy[b]) * row + iz[c];
-                const float w = wx[a] * wy[b] * wz[c];
-                g0 += w * fx[o];
-                g1 += w * fy[o];
-                g2 += w * fz[o];
-            }
-    ox[p] = g0;
-    oy[p] = g1;
-    oz[p] = g2;
+    float g[3];
+    gather_interleaved(F, row, n, ix0, iy0, iz0, ux, uy, uz, g);
+    ox[p] = g[0];
+    oy[p] = g[1];
+    oz[p] = g[2];
 }
 
 __global__ void k_mesh_unpad(const float* src, long row, int n, float* dst) {
     const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= (long)n * n * n) return;
     dst[v] = src[mesh_off(v, n, row)];
+}
+
+// The three components of the interleaved force mesh into three dense n^3 arrays.
+__global__ void k_mesh_unpad3(const float* F, long row, int n, float* g0, float* g1, float* g2) {
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long)n * n * n) return;
+    const long r = v / n;
+    const float* c = F + r * row + 3 * (v - r * n);
+    g0[v] = c[0];
+    g1[v] = c[1];
+    g2[v] = c[2];
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -1088,11 +1088,18 @@ hipError_t lc_positions(const float* const x[3], long n_per_real, int n_real, in
     return hipGetLastError();
 }
 
-hipError_t gather_absolute(const float* const pos[3], long np, int n, double box, const float* const f[3], long row,
+hipError_t gather_absolute(const float* const pos[3], long np, int n, double box, const float* F, long row,
                            float* const out[3], hipStream_t st) {
     ProfScope ps(PROF_GATHER, st);
     hipLaunchKernelGGL(k_gather_abs, dim3(blocks_for(np, 256)), dim3(256), 0, st, pos[0], pos[1], pos[2], np, n,
-                       (float)(n / box), f[0], f[1], f[2], row, out[0], out[1], out[2]);
+                       (float)(n / box), F, row, out[0], out[1], out[2]);
+    return hipGetLastError();
+}
+
+hipError_t mesh_unpad3(const float* F, long row, int n, float* const g[3], hipStream_t st) {
+    ProfScope ps(PROF_COPY, st);
+    hipLaunchKernelGGL(k_mesh_unpad3, dim3(blocks_for((long)n * n * n, 256)), dim3(256), 0, st, F, row, n, g[0], g[1],
+                       g[2]);
     return hipGetLastError();
 }
 
