@@ -433,8 +433,8 @@ static hipError_t run_z_r2c(const float* in, long in_row, long in_bstride, float
 }
 
 static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out, long out_row, long out_bstride,
-                                  const Mesh3& g, const float2* tw, int n_real, float kf, float scale,
-                                  const FftShape& sh, hipStream_t st) {
+                                  const Mesh3& g, const float2* tw, int n_real, float scale, const FftShape& sh,
+                                  hipStream_t st) {
     FftLaunch L;
     L.op = OP_Z_C2R;
     const int lpb = sh.width;
@@ -452,17 +452,15 @@ static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out,
     L.lw = log2_exact(lpb);
     L.ghost = out_row >= g.n + 2 ? 1 : 0;
     L.tw = tw;
-    L.kf = kf;
     L.scale = scale;
     ProfScope ps(PROF_Z_C2R, st, g.n);
     return launch_shape(L, g.n, sh);
 }
 
 static hipError_t run_z_c2r(const float2* in, long in_bstride, float* out, long out_row, long out_bstride,
-                            const Mesh3& g, const float2* tw, int n_real, float kf, float scale,
-                            hipStream_t st) {
-    return run_z_c2r_shape(in, in_bstride, out, out_row, out_bstride, g, tw, n_real, kf, scale,
-                                shape_for(FK_Z_C2R, g.n), st);
+                            const Mesh3& g, const float2* tw, int n_real, float scale, hipStream_t st) {
+    return run_z_c2r_shape(in, in_bstride, out, out_row, out_bstride, g, tw, n_real, scale, shape_for(FK_Z_C2R, g.n),
+                           st);
 }
 
 // The three force components into one interleaved mesh (k_fft_z_c2r3); `lines` rows (x, y) from
@@ -587,7 +585,7 @@ hipError_t fft3d_c2r_mult(const float2* spec, long spec_bstride, float2* work, l
     if (e != hipSuccess) return e;
     e = run_rows(OP_ROWS_INV, work, nullptr, work_bstride, g, tw, kf, n_real, st);
     if (e != hipSuccess) return e;
-    return run_z_c2r(work, work_bstride, out, out_row, out_bstride, g, tw, n_real, kf, 1.0f, st);
+    return run_z_c2r(work, work_bstride, out, out_row, out_bstride, g, tw, n_real, 1.0f, st);
 }
 
 // Times every admissible shape of each FFT kernel at mesh size n on the buffers S, A, B (each at
@@ -628,8 +626,7 @@ hipError_t autotune_fft(int n, float2* S, float2* A, float2* B, const float2* tw
                     return run_z_r2c_shape(reinterpret_cast<const float*>(S), 2L * g.nzp, 0, A, 0, g, tw, 1, 1.0f,
                                            0.0f, sh, st);
                 case FK_Z_C2R:
-                    return run_z_c2r_shape(A, 0, reinterpret_cast<float*>(B), 2L * g.nzp, 0, g, tw, 1, kf,
-                                                  1.0f, sh, st);
+                    return run_z_c2r_shape(A, 0, reinterpret_cast<float*>(B), 2L * g.nzp, 0, g, tw, 1, 1.0f, sh, st);
                 case FK_ROWS_Y: return run_rows_shape(OP_ROWS_FWD, S, nullptr, 0, g, tw, kf, 1, sh, st);
                 case FK_COLS_X: return run_cols_shape(S, 0, g, tw, 1, sh, st);
                 case FK_X_GREEN: return run_x_green_shape(S, S, A, 0, g, tw, kf, 1, sh, st);

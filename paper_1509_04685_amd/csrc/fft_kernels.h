@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
 template <class LE>
 __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bstride, float* out, long out_row,
                                                    long out_bstride, int n, long plane, int lw, int ghost, LE eng,
-                                                   const float2* tw, float kf, float scale) {
+                                                   const float2* tw, float scale) {
     constexpr int R = LE::kR;
     constexpr int TW = z_tw_entries<LE>();
     extern __shared__ float2 lds[];
@@ -584,7 +584,7 @@ inline hipError_t go_z_c2r(const FftLaunch& L, LE e) {
     const size_t lds = L.lds + tw_lds_bytes(z_tw_entries<LE>());
     if (hipError_t ea = allow_lds_fft(kern, lds); ea != hipSuccess) return ea;
     hipLaunchKernelGGL(kern, L.grid, L.block, lds, L.st, L.cin, L.in_bstride, L.rout, L.out_row, L.out_bstride,
-                       L.mesh_n, L.plane, L.lw, L.ghost, e, L.tw, L.kf, L.scale);
+                       L.mesh_n, L.plane, L.lw, L.ghost, e, L.tw, L.scale);
     return hipGetLastError();
 }
 
