@@ -682,7 +682,8 @@ __global__ void k_lc_pack_delta(const float* delta, long row, int n, float s0, u
     d0[v] = (uint16_t)f2bf(delta[mesh_off(v, n, row)] * s0);
 }
 
-// dF[c] = (W3 A2[v] + b3) * out_scale, written to (or added into) three meshes of `row` floats per row.
+// dF[c] = (W3 A2[v] + b3) * out_scale, written to (or added into) three dense meshes of `row` floats
+// per row (the training path; the step's output layer is the fused EPI_OUT epilogue).
 template <int C>
 __global__ void k_lc_out(const uint16_t* a2, const float* w3, const float* b3, float out_scale, int n, long row,
                          float* fx, float* fy, float* fz, int accumulate) {

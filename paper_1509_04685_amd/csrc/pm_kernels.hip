@@ -1,6 +1,6 @@
 // Particle kernels of the COLA particle-mesh step (Sec. 2.2; Eq. 1-2):
-//   CIC mass assignment onto the force mesh, CIC interpolation of the three force meshes back to
-//   the particles fused with the COLA kick and drift in the frame of the 2LPT trajectories.
+//   CIC mass assignment onto the force mesh, CIC interpolation of the interleaved force mesh back
+//   to the particles fused with the COLA kick and drift in the frame of the 2LPT trajectories.
 //
 // Particles are structure-of-arrays in Lagrangian order; the position is never stored as an
 // absolute float.  Along each axis the cell coordinate is split into an exact integer part from
@@ -180,7 +180,7 @@ __device__ __forceinline__ float bracket(float g, float d1, float d2m, float s1,
 
 // p += kick [g - D1 psi1 - (D2 - D1^2) psi2];  x += p Dr + dD1 psi1 + dD2 psi2.
 // Grid: (particle blocks, realizations).  Every particle array is read before the first store, so
-// the twelve streaming loads and the 24 mesh reads are in flight together (the arrays of one
+// the twelve streaming loads and the eight corner-column loads are in flight together (the arrays of one
 // particle set could alias as far as the compiler knows, which would otherwise order them).  The
 // particle streams are non-temporal, leaving L2 to the force-mesh lines that neighbouring
 // particles share.
