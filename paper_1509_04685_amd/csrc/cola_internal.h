@@ -72,8 +72,8 @@ Schedule make_schedule(const cola_problem& p, const cola_cosmology& c);
 // ------------------------------------------------------------------ mesh geometry
 // A cubic mesh of n cells per side.  A workspace buffer of total_c() float2 holds either a real
 // field [x][y][z] with rows of 2 nzp floats (nzp >= n/2 + 1 rounded up to 16: rows start on
-// 128-byte boundaries) or the
-// transposed half spectrum [kz][x][y], kz planes of n^2 values `plane` float2 apart.
+// 128-byte boundaries) or the transposed half spectrum [kz][x][y], kz planes of n^2 values `plane`
+// float2 apart.
 struct Mesh3 {
     int n = 0;
     int m = 0;     // n / 2
