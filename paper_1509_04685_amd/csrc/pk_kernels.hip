@@ -203,7 +203,7 @@ __global__ void k_pk_finish_ell(double* kmean, double* p0, double* p2, double* p
 
 hipError_t pk_finish_multipoles(double* kmean, double* p0, double* p2, double* p4, const double* cnt, long n,
                                 double pnorm, hipStream_t st) {
-    ProfScope ps(PROF_PK, st);
+    ProfScope ps(PROF_OTHER, st);  // a few hundred bins: kept out of the binning kind's per-launch figure
     hipLaunchKernelGGL(k_pk_finish_ell, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, kmean, p0, p2, p4, cnt,
                        n, pnorm);
     return hipGetLastError();
@@ -219,7 +219,7 @@ __global__ void k_pk_finish(double* kmean, double* pk, const double* cnt, long n
 }
 
 hipError_t pk_finish(double* kmean, double* pk, double* cnt, long n, double pnorm, hipStream_t st) {
-    ProfScope ps(PROF_PK, st);
+    ProfScope ps(PROF_OTHER, st);  // a few hundred bins: kept out of the binning kind's per-launch figure
     hipLaunchKernelGGL(k_pk_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, kmean, pk, cnt, n, pnorm);
     return hipGetLastError();
 }
