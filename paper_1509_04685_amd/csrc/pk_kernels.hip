@@ -28,11 +28,13 @@ __device__ __forceinline__ float sinc_pi(float x) {  // sin(pi x) / (pi x)
 // the shell changes (one set of atomics per shell and run instead of per mode).
 constexpr int kPkRun = 8;
 
+// LDS: the bins are summed in LDS first (n_bins <= kMaxBinsLds).  A compile-time choice: with the
+// target picked at run time the sums went through generic-address (flat) atomics even for LDS.
+template <bool LDS>
 __global__ void k_pk_bin(const float2* spec, long bstride, int n, long plane, int n_bins, double* ksum,
                          double* psum, double* cnt, double kf) {
-    __shared__ double sk[kMaxBinsLds], sp[kMaxBinsLds], sc[kMaxBinsLds];
-    const bool use_lds = n_bins <= kMaxBinsLds;
-    if (use_lds)
+    __shared__ double sk[LDS ? kMaxBinsLds : 1], sp[LDS ? kMaxBinsLds : 1], sc[LDS ? kMaxBinsLds : 1];
+    if (LDS)
         for (int b = threadIdx.x; b < n_bins; b += blockDim.x) sk[b] = sp[b] = sc[b] = 0.0;
     __syncthreads();
     const int r = blockIdx.y;
@@ -40,9 +42,9 @@ __global__ void k_pk_bin(const float2* spec, long bstride, int n, long plane, in
     ksum += (long)r * n_bins;
     psum += (long)r * n_bins;
     cnt += (long)r * n_bins;
-    double* dk = use_lds ? sk : ksum;
-    double* dp = use_lds ? sp : psum;
-    double* dc = use_lds ? sc : cnt;
+    double* dk = LDS ? sk : ksum;
+    double* dp = LDS ? sp : psum;
+    double* dc = LDS ? sc : cnt;
     const int m = n / 2;
     const int runs = (n + kPkRun - 1) / kPkRun;  // runs per row
     const long total = (long)(m + 1) * n * runs;
@@ -89,7 +91,7 @@ __global__ void k_pk_bin(const float2* spec, long bstride, int n, long plane, in
         }
     }
     __syncthreads();
-    if (use_lds)
+    if (LDS)
         for (int b = threadIdx.x; b < n_bins; b += blockDim.x) {
             if (sc[b] != 0.0) {
                 atomicAdd(&ksum[b], sk[b]);
@@ -105,8 +107,12 @@ hipError_t pk_bin(const float2* spec, long bstride, const Mesh3& g, int n_real, 
     long blocks = (total + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     ProfScope ps(PROF_PK, st);
-    hipLaunchKernelGGL(k_pk_bin, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n, g.plane,
-                       n_bins, ksum, psum, cnt, kf);
+    if (n_bins <= kMaxBinsLds)
+        hipLaunchKernelGGL(k_pk_bin<true>, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n,
+                           g.plane, n_bins, ksum, psum, cnt, kf);
+    else
+        hipLaunchKernelGGL(k_pk_bin<false>, dim3((unsigned)blocks, n_real), dim3(256), 0, st, spec, bstride, g.n,
+                           g.plane, n_bins, ksum, psum, cnt, kf);
     return hipGetLastError();
 }
 
