@@ -219,9 +219,12 @@ static long shape_threads(FftKind k, int n, const FftShape& sh) {
     return (long)sh.width * (line_len(k, n) / sh.R) * (k == FK_Z_C2R3 ? 3 : 1);
 }
 
+// LDS of one block: z passes stage lines of L + 1 values (the kz Nyquist plane); z_c2r3 keeps its
+// lines L + 2 apart, one group of lines per force component.
 static size_t shape_lds(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
-    if (is_z(k)) return (size_t)sh.width * (L + 1) * sizeof(float2) * (k == FK_Z_C2R3 ? 3 : 1);
+    if (k == FK_Z_C2R3) return (size_t)sh.width * (L + 2) * sizeof(float2) * 3;
+    if (is_z(k)) return (size_t)sh.width * (L + 1) * sizeof(float2);
     return (size_t)sh.width * L * (sh.split ? sizeof(float) : sizeof(float2));
 }
 

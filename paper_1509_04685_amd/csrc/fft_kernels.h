@@ -266,7 +266,10 @@ __global__ void __launch_bounds__(1024) k_fft_z_c2r3(const float2* in0, const fl
     const long first = (long)xcd_block() * W;
     const int x = (int)(first / n), y0 = (int)(first - (long)x * n);
     float2* const Lb = lds + TW;
-    float2* const Lg = Lb + (long)comp * W * (M + 1);  // this group's lines
+    // this group's lines, M + 2 apart: the staging writes below put the 8 lines x 8 k planes of a
+    // wave at j (M + 2) + k, at most four lanes on one LDS bank pair (eight at M + 1 apart)
+    const int LS = M + 2;
+    float2* const Lg = Lb + (long)comp * W * LS;
     const float2* twl = stage_twiddles<TW>(tw, lds);  // visible after the barrier below
     {
         const float2* src = (comp == 0 ? in0 : (comp == 1 ? in1 : in2)) + (long)blockIdx.y * in_bstride +
@@ -288,13 +291,13 @@ __global__ void __launch_bounds__(1024) k_fft_z_c2r3(const float2* in0, const fl
                 const float kz = kf * (float)k;
                 y = make_float2(-kz * y.y, kz * y.x);
             }
-            Lg[j * (M + 1) + k] = cscale(y, scale);
+            Lg[j * LS + k] = cscale(y, scale);
         }
         if (lt < W)  // kz Nyquist plane (0 for the i k_z component)
-            Lg[lt * (M + 1) + M] = comp == 2 ? make_float2(0.0f, 0.0f) : cscale(xm, scale);
+            Lg[lt * LS + M] = comp == 2 ? make_float2(0.0f, 0.0f) : cscale(xm, scale);
     }
     __syncthreads();
-    float2* L = Lg + line * (M + 1);
+    float2* L = Lg + line * LS;
     float2 v[R];
     eng.first(t, [&](int q, int k) {
         float2 xk = L[k];
