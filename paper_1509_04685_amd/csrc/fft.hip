@@ -219,12 +219,12 @@ static long shape_threads(FftKind k, int n, const FftShape& sh) {
     return (long)sh.width * (line_len(k, n) / sh.R) * (k == FK_Z_C2R3 ? 3 : 1);
 }
 
-// LDS of one block: z passes stage lines of L + 1 values (the kz Nyquist plane); z_c2r3 keeps its
-// lines L + 2 apart, one group of lines per force component.
+// LDS of one block: z passes keep their lines L + 2 complex values apart (the line, its kz Nyquist
+// value and one value against bank conflicts of the transposed accesses); z_c2r3 holds one group
+// of lines per force component.
 static size_t shape_lds(FftKind k, int n, const FftShape& sh) {
     int L = line_len(k, n);
-    if (k == FK_Z_C2R3) return (size_t)sh.width * (L + 2) * sizeof(float2) * 3;
-    if (is_z(k)) return (size_t)sh.width * (L + 1) * sizeof(float2);
+    if (is_z(k)) return (size_t)sh.width * (L + 2) * sizeof(float2) * (k == FK_Z_C2R3 ? 3 : 1);
     return (size_t)sh.width * L * (sh.split ? sizeof(float) : sizeof(float2));
 }
 
@@ -410,7 +410,7 @@ static hipError_t run_z_r2c_shape(const float* in, long in_row, long in_bstride,
     FftLaunch L;
     L.op = OP_Z_R2C;
     const int lpb = sh.width;
-    L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
+    L.lds = shape_lds(FK_Z_R2C, g.n, sh);
     L.grid = dim3((unsigned)((long)g.n * g.n / lpb), n_real);
     L.block = dim3(lpb * (g.m / sh.R));
     L.st = st;
@@ -441,7 +441,7 @@ static hipError_t run_z_c2r_shape(const float2* in, long in_bstride, float* out,
     FftLaunch L;
     L.op = OP_Z_C2R;
     const int lpb = sh.width;
-    L.lds = (size_t)lpb * (g.m + 1) * sizeof(float2);
+    L.lds = shape_lds(FK_Z_C2R, g.n, sh);
     L.grid = dim3((unsigned)((long)g.n * g.n / lpb), n_real);
     L.block = dim3(lpb * (g.m / sh.R));
     L.st = st;

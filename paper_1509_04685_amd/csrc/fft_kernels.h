@@ -126,6 +126,11 @@ __device__ __forceinline__ void store_col(float2* p, float2 v) {
 
 // ------------------------------------------------------------------ z pass: real -> half complex
 
+// LDS stride of the lines of a z pass block: M + 1 complex values fit a line with its kz Nyquist
+// value; M + 2 makes the transposed LDS accesses of a wave (W lines x 64 / W planes k at
+// j stride + k) meet at most 64 / W lanes on a bank pair instead of twice as many.
+__device__ __forceinline__ constexpr int z_line_stride(int M) { return M + 2; }
+
 // Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
 // X_k = (Z_k + conj Z_{M-k})/2 - i W_n^k (Z_k - conj Z_{M-k})/2, k = 0..M.
 // Block: W = 2^lw lines (x, y0 .. y0 + W - 1) of one x plane (W divides n); output X_k of line j
@@ -145,7 +150,8 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
     in += (long)blockIdx.y * in_bstride;
     out += (long)blockIdx.y * out_bstride;
     float2* const Lb = lds + TW;
-    float2* L = Lb + line * (M + 1);
+    const int LS = z_line_stride(M);
+    float2* L = Lb + line * LS;
     float2 v[R];
     const float2* src = reinterpret_cast<const float2*>(in + (first + line) * in_row);
     eng.first(t, [&](int q, int e) {
@@ -165,7 +171,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
     for (int u = 0; u < R; ++u) {
         const int o = threadIdx.x + u * bd;
         const int k = o >> lw, j = o & (W - 1);
-        const float2* Lj = Lb + j * (M + 1);
+        const float2* Lj = Lb + j * LS;
         const float2 zk = Lj[k];
         const float2 zc = cconj(Lj[k == 0 ? 0 : M - k]);
         const float2 e = cscale(cadd(zk, zc), 0.5f);
@@ -174,7 +180,7 @@ __global__ void __launch_bounds__(512) k_fft_z_r2c(const float* in, long in_row,
         store_stream(dst + (long)k * plane + j, cadd(e, cmul(twl[k], od)));
     }
     if (threadIdx.x < W) {
-        const float2 z0 = Lb[threadIdx.x * (M + 1)];
+        const float2 z0 = Lb[threadIdx.x * LS];
         store_stream(dst + (long)M * plane + threadIdx.x, make_float2(z0.x - z0.y, 0.0f));
     }
 }
@@ -200,6 +206,7 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bst
     in += (long)blockIdx.y * in_bstride;
     out += (long)blockIdx.y * out_bstride;
     float2* const Lb = lds + TW;
+    const int LS = z_line_stride(M);
     const float2* twl = stage_twiddles<TW>(tw, lds);  // visible after the barrier below
     {
         // every load of this thread is issued before the first LDS store
@@ -216,13 +223,13 @@ __global__ void __launch_bounds__(512) k_fft_z_c2r(const float2* in, long in_bst
         for (int u = 0; u < R; ++u) {
             const int o = threadIdx.x + u * bd;
             const int k = o >> lw, j = o & (W - 1);
-            Lb[j * (M + 1) + k] = cscale(xv[u], scale);
+            Lb[j * LS + k] = cscale(xv[u], scale);
         }
         if (threadIdx.x < W)  // kz Nyquist plane
-            Lb[threadIdx.x * (M + 1) + M] = cscale(xm, scale);
+            Lb[threadIdx.x * LS + M] = cscale(xm, scale);
     }
     __syncthreads();
-    float2* L = Lb + line * (M + 1);
+    float2* L = Lb + line * LS;
     float2 v[R];
     eng.first(t, [&](int q, int k) {
         float2 xk = L[k];
@@ -266,9 +273,7 @@ __global__ void __launch_bounds__(1024) k_fft_z_c2r3(const float2* in0, const fl
     const long first = (long)xcd_block() * W;
     const int x = (int)(first / n), y0 = (int)(first - (long)x * n);
     float2* const Lb = lds + TW;
-    // this group's lines, M + 2 apart: the staging writes below put the 8 lines x 8 k planes of a
-    // wave at j (M + 2) + k, at most four lanes on one LDS bank pair (eight at M + 1 apart)
-    const int LS = M + 2;
+    const int LS = z_line_stride(M);  // this group's lines
     float2* const Lg = Lb + (long)comp * W * LS;
     const float2* twl = stage_twiddles<TW>(tw, lds);  // visible after the barrier below
     {
