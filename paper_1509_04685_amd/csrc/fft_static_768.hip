@@ -22,6 +22,8 @@ hipError_t fft_static_768(const FftLaunch& L) {
     if (L.split) {
         if (L.R == 24 && L.width == 16) return static_cols_ops<768, 24, 16, true>(L);
         if (L.R == 24 && L.width == 8) return static_cols_ops<768, 24, 8, true>(L);
+        // 16-column tiles (whole 128-byte rows) in 1024-thread blocks of 49 KB: two per CU
+        if (L.R == 12 && L.width == 16) return static_cols_ops<768, 12, 16, true>(L);
         return hipErrorNotSupported;
     }
     if (L.R == 24 && L.width == 8) return static_cols_ops<768, 24, 8>(L);

@@ -1,6 +1,6 @@
 """The x-column FFT plans whose LDS exchanges move the real and then the imaginary parts (half the
-LDS of a float2 exchange), against closed forms on 768^3 and 1536^3 meshes (1536 with R = 12 and
-8-column tiles runs 1024-thread blocks).
+LDS of a float2 exchange), against closed forms on 768^3 and 1536^3 meshes (768 with R = 12 and
+16-column tiles, and 1536 with R = 12 and 8-column tiles, run 1024-thread blocks).
 
 A plane wave delta = cos(2 pi m / n), m = (a i + b j + c l) mod n, has the force
 g_d = -(k_d / k^2) sin(2 pi m / n); the unnormalised inverse transform of a half spectrum with a
@@ -67,7 +67,7 @@ def check_field(n, field, want_fn, amp, label):
     assert worst < 1e-4, label
 
 
-@pytest.mark.parametrize("n,R,width", [(768, 24, 16), (768, 24, 8), (1536, 24, 8), (1536, 12, 8)])
+@pytest.mark.parametrize("n,R,width", [(768, 24, 16), (768, 24, 8), (768, 12, 16), (1536, 24, 8), (1536, 12, 8)])
 def test_split_exchange_plans(cola, n, R, width):
     if n == 1536 and torch.cuda.get_device_properties(0).total_memory < 200 * 2 ** 30:
         pytest.skip("needs about 130 GB of device memory")
