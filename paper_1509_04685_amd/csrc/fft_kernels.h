@@ -127,8 +127,9 @@ __device__ __forceinline__ void store_col(float2* p, float2 v) {
 // ------------------------------------------------------------------ z pass: real -> half complex
 
 // LDS stride of the lines of a z pass block: M + 1 complex values fit a line with its kz Nyquist
-// value; M + 2 makes the transposed LDS accesses of a wave (W lines x 64 / W planes k at
-// j stride + k) meet at most 64 / W lanes on a bank pair instead of twice as many.
+// value.  A wave's transposed LDS accesses cover W lines x 64 / W planes k at j stride + k; with M
+// a multiple of 32 the stride M + 2 puts half as many of its lanes on one LDS bank pair as M + 1
+// does at W = 8 and 16 (4 instead of 8, 2 instead of 4).
 __device__ __forceinline__ constexpr int z_line_stride(int M) { return M + 2; }
 
 // Rows of n = 2M reals; output M+1 complex per row.  Z = FFT_M(x_even + i x_odd);
